@@ -1,0 +1,198 @@
+"""Adaptive parareal iteration of the oracle (formula4, Algorithm 2).
+
+Numbering (reading of where T_0 sits): [0, T] is split into N subintervals of
+length DeltaT. The warm-up window [0, T_0] is subinterval 0 (T_0 = DeltaT, as
+in the paper's runs), so the parareal partition of [T_0, T] has N' = N - 1
+subintervals and states U_n at t_hat_n = (n + 1) DeltaT, n = 0..N'. U_0 is the
+fine solution at T_0 (u_hat_0 of Case I).
+
+k = 0 (Algorithm 2, lines 3-5): fine solve on [0, T_0] with snapshots,
+POD_Mode(W, gamma_1) gives G_0, and U^0_{n+1} = G_0(P U^0_n).
+
+k >= 1 (lines 7-19):
+  (i)   F(U^{k-1}_n) and the snapshots W^k_{n,0} for n = k-1..N'-1 (line 8);
+        POD_Mode(W^k_{n,0}, gamma_2) -> R^k_{n,0} (line 9).
+  (ii)  W^k_n = [R_{n-m_l,0} .. R_{n,0} (latest iteration of each),
+        R^{k-1}_{n,0} .. R^{k-p}_{n,0}]; blocks with index < 0 or iteration
+        < 1 are omitted; POD_Mode(W^k_n, gamma_3) -> R^k_n (line 10).
+  (iii) U^k_j = U^{k-1}_j for j < k and U^k_k = F(U^{k-1}_{k-1}): the two
+        coarse terms cancel there because U^k_{k-1} = U^{k-1}_{k-1}.
+  (iv)  sequentially for n = k..N'-1 (lines 12-17): augment R^k_n with U^k_n
+        (eq12), then U^k_{n+1} = G(P U^k_n) + F(U^{k-1}_n) - G(P U^{k-1}_n).
+  (v)   stopping ("while not converged" is unspecified): the jump
+        e_k = max_{n>=1} ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M <= tol, or
+        k = N' (finite termination, Sec. 2), or k = max_iter.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import coarse as C
+from . import fd
+from . import pod as P
+
+
+@dataclasses.dataclass
+class Result:
+    U: List[np.ndarray]           # N + 1 states at t = j DeltaT (U[0] = u0)
+    iters: int
+    converged: bool
+    jumps: List[float]            # e_k, k = 1..iters
+    errors: List[float]           # vs U_ref, k = 0..iters (empty without U_ref)
+    ranks: Dict[int, List[int]]   # k -> [m^k_n for n = k..N'-1]
+    ranks0: Dict[int, List[int]]  # k -> [m^k_{n,0} for n = k-1..N'-1]
+    m0: int                       # rank of V^0_POD
+    n_f: int
+    dt: float
+    dM: int
+    n_c: int
+    history: List[List[np.ndarray]]  # iterates per k (only with keep_history)
+    t_phase: Dict[str, float]
+
+
+def _norm_m(x: np.ndarray, h3: float) -> float:
+    return math.sqrt(h3 * float(np.vdot(x, x)))
+
+
+def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
+          tau_r: float = P.TAU_R_F64, keep_history: bool = False) -> Result:
+    op = fd.Operator.of(prob)
+    n = prob.n
+    h3 = op.h ** 3
+    N = opts.N
+    dT_sub = opts.T / N
+    n_f, dt = fd.steps_per_subinterval(dT_sub, opts.dt)
+    dM = fd.snapshot_stride(n_f, opts.dM)
+    Np = N - 1
+    n_c0 = C.coarse_steps(n_f, opts.coarse_ratio)
+    max_iter = opts.max_iter if opts.max_iter > 0 else Np
+    t_phase = {"F": 0.0, "C": 0.0, "U": 0.0, "A": 0.0, "G": 0.0}
+    u0v = np.asarray(u0, dtype=np.float64).reshape(-1)
+
+    def err_of(states):
+        if U_ref is None:
+            return None
+        e = 0.0
+        for j in range(1, len(states)):
+            ref = np.asarray(U_ref[j + 1]).reshape(-1)
+            e = max(e, _norm_m(states[j] - ref, h3) / _norm_m(ref, h3))
+        return e
+
+    # ---- k = 0: Case I ----------------------------------------------------
+    t0 = time.perf_counter()
+    F0, W = fd.fine_propagate(op, u0v.reshape(n, n, n), dt, n_f, dM)
+    t_phase["F"] += time.perf_counter() - t0
+    U0hat = F0.reshape(-1)
+    t0 = time.perf_counter()
+    R0, m0, _ = P.pod_mode(W, opts.gamma1, h3, opts.cap, tau_r)
+    t_phase["C"] += time.perf_counter() - t0
+    del W
+    t0 = time.perf_counter()
+    Lr0, Mr0 = C.reduced_matrices(op, R0, h3)
+    n_c = C.guarded_steps(Lr0, Mr0, dT_sub, n_c0)
+    t_phase["U"] += time.perf_counter() - t0
+    U_prev = [U0hat]
+    t0 = time.perf_counter()
+    for _ in range(Np):
+        beta = C.project(R0, Mr0, U_prev[-1], h3)
+        beta = C.reduced_rk4(Lr0, Mr0, beta, dT_sub, n_c)
+        U_prev.append(R0 @ beta if m0 > 0 else np.zeros_like(U0hat))
+    t_phase["G"] += time.perf_counter() - t0
+
+    errors = []
+    e0 = err_of(U_prev)
+    if e0 is not None:
+        errors.append(e0)
+    history = [list(U_prev)] if keep_history else []
+
+    hist: Dict[int, Dict[int, np.ndarray]] = {}
+    jumps: List[float] = []
+    ranks: Dict[int, List[int]] = {}
+    ranks0: Dict[int, List[int]] = {}
+    converged = Np == 0
+    k = 0
+    while not converged and k < max_iter:
+        k += 1
+        # (i) fine propagation and stage-1 POD, parallel over n
+        Fk: Dict[int, np.ndarray] = {}
+        hist[k] = {}
+        ranks0[k] = []
+        for nn in range(k - 1, Np):
+            t0 = time.perf_counter()
+            Fn, Wn = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f, dM)
+            t_phase["F"] += time.perf_counter() - t0
+            Fk[nn] = Fn.reshape(-1)
+            t0 = time.perf_counter()
+            R, m, _ = P.pod_mode(Wn, opts.gamma2, h3, opts.cap0, tau_r)
+            t_phase["C"] += time.perf_counter() - t0
+            hist[k][nn] = R
+            ranks0[k].append(m)
+
+        def latest(j):
+            return hist[min(k, j + 1)][j]
+
+        # (iii) converged prefix
+        U_cur = [U_prev[j] for j in range(k)]
+        U_cur.append(Fk[k - 1])
+        ranks[k] = []
+        # (ii) + (iv) sequential sweep
+        for nn in range(k, Np):
+            t0 = time.perf_counter()
+            blocks = [latest(j) for j in range(nn - opts.ml, nn + 1) if j >= 0]
+            blocks += [hist[k - i][nn] for i in range(1, opts.p + 1) if k - i >= 1]
+            Wkn = np.concatenate(blocks, axis=1)
+            Rkn, mkn, _ = P.pod_mode(Wkn, opts.gamma3, h3, opts.cap, tau_r)
+            t_phase["C"] += time.perf_counter() - t0
+            ranks[k].append(mkn)
+            t0 = time.perf_counter()
+            Psi, _ = C.augment(Rkn, U_cur[nn], h3)
+            t_phase["A"] += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            Lr, Mr = C.reduced_matrices(op, Psi, h3)
+            nc = C.guarded_steps(Lr, Mr, dT_sub, n_c0)
+            t_phase["U"] += time.perf_counter() - t0
+            t0 = time.perf_counter()
+            b_new = C.reduced_rk4(Lr, Mr, C.project(Psi, Mr, U_cur[nn], h3), dT_sub, nc)
+            b_old = C.reduced_rk4(Lr, Mr, C.project(Psi, Mr, U_prev[nn], h3), dT_sub, nc)
+            g_new = Psi @ b_new if Psi.shape[1] else 0.0
+            g_old = Psi @ b_old if Psi.shape[1] else 0.0
+            U_cur.append(g_new + Fk[nn] - g_old)
+            t_phase["G"] += time.perf_counter() - t0
+        # (v) jump
+        e = 0.0
+        for j in range(1, Np + 1):
+            nrm = _norm_m(U_cur[j], h3)
+            dj = _norm_m(U_cur[j] - U_prev[j], h3)
+            e = max(e, dj / nrm if nrm > 0 else (0.0 if dj == 0 else math.inf))
+        jumps.append(e)
+        ek = err_of(U_cur)
+        if ek is not None:
+            errors.append(ek)
+        if keep_history:
+            history.append(list(U_cur))
+        # drop bases no longer reachable: latest() needs hist[j+1][j] for
+        # j < k - 1 and hist[k - i] for i <= p.
+        for kk in list(hist.keys()):
+            if kk < k - opts.p:
+                keep = {j: v for j, v in hist[kk].items() if j == kk - 1}
+                hist[kk] = keep
+        U_prev = U_cur
+        converged = (e <= opts.tol) or (k == Np)
+
+    U_out = [u0v.copy()] + [u.copy() for u in U_prev]
+    return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
+                  ranks=ranks, ranks0=ranks0, m0=m0, n_f=n_f, dt=dt, dM=dM,
+                  n_c=n_c, history=history, t_phase=t_phase)
+
+
+def reference(prob, opts, u0: np.ndarray) -> List[np.ndarray]:
+    """Serial fine solution at t = j DeltaT, j = 0..N (eq. error's U_n)."""
+    op = fd.Operator.of(prob)
+    out = fd.serial_fine(op, np.asarray(u0, dtype=np.float64).reshape(prob.n, prob.n, prob.n),
+                         opts.T / opts.N, opts.N, opts.dt)
+    return [o.reshape(-1) for o in out]

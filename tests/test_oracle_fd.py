@@ -1,0 +1,149 @@
+"""Pins of the oracle's fine propagator against closed forms.
+
+* A single Fourier mode under a uniform velocity evolves by the FD symbol
+  times the RK4 amplification polynomial: exact decay and translation.
+* Under Kolmogorov shear an x-independent mode feels only diffusion.
+* Every flow here has u_d independent of x_d, so the advection matrix is skew
+  with A 1 = 0 and the Laplacian sums to zero: the field's sum is conserved.
+* The ABC flow with A = B = C commutes with the cyclic permutation of axes.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fd
+
+
+def _grid(n, L=2 * math.pi):
+    x = np.arange(n) * (L / n)
+    return np.meshgrid(x, x, x, indexing="ij")
+
+
+def _p4(z):
+    return 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def _symbol(k, c, kappa, h):
+    lam = -(4 * kappa / h ** 2) * sum(math.sin(kd * h / 2) ** 2 for kd in k)
+    lam = lam - 1j * sum(cd * math.sin(kd * h) / h for kd, cd in zip(k, c))
+    return lam
+
+
+@pytest.mark.parametrize("n,k,c,kappa", [
+    (12, (1, 2, -3), (0.7, -0.4, 1.1), 0.03),
+    (10, (4, 0, 1), (0.0, 2.0, -1.5), 0.2),
+    (16, (-2, 5, 7), (1.3, 0.3, 0.0), 0.0),
+])
+def test_fourier_mode_uniform_flow(n, k, c, kappa):
+    op = fd.Operator(n, kappa, fd.FLOW_UNIFORM, c)
+    X, Y, Z = _grid(n)
+    arg = k[0] * X + k[1] * Y + k[2] * Z
+    phi0 = np.cos(arg)
+    lam = _symbol(k, c, kappa, op.h)
+    # one application of L: Re(lam e^{i k.x})
+    Lphi = op.apply(phi0)
+    exact_L = lam.real * np.cos(arg) - lam.imag * np.sin(arg)
+    assert np.max(np.abs(Lphi - exact_L)) <= 1e-12 * max(1.0, abs(lam))
+    dt = 0.3 / max(1.0, abs(lam))
+    steps = 9
+    phi, _ = fd.fine_propagate(op, phi0, dt, steps)
+    R = _p4(dt * lam)
+    exact = abs(R) ** steps * np.cos(arg + steps * np.angle(R))
+    assert np.max(np.abs(phi - exact)) <= 1e-13
+
+
+def test_kolmogorov_x_independent_mode_is_pure_diffusion():
+    n, kappa = 16, 0.05
+    op = fd.Operator(n, kappa, fd.FLOW_KOLMOGOROV, (1.3, 2.0, 0.0))
+    X, Y, Z = _grid(n)
+    phi0 = np.cos(2 * Y + 3 * Z)
+    lam = -(4 * kappa / op.h ** 2) * (math.sin(2 * op.h / 2) ** 2 + math.sin(3 * op.h / 2) ** 2)
+    dt, steps = 0.01, 25
+    phi, _ = fd.fine_propagate(op, phi0, dt, steps)
+    exact = _p4(dt * lam) ** steps * phi0
+    assert np.max(np.abs(phi - exact)) <= 1e-13
+
+
+def test_kolmogorov_advects_along_x():
+    # u = (a sin(k_f y), 0, 0): a mode cos(x) at y with sin(k_f y) = 0 only
+    # diffuses, and the advection term of L is -u_x d/dx exactly.
+    n, a, kf = 16, 0.8, 2.0
+    op = fd.Operator(n, 0.0, fd.FLOW_KOLMOGOROV, (a, kf, 0.0))
+    X, Y, Z = _grid(n)
+    phi0 = np.cos(X)
+    Lphi = op.apply(phi0)
+    exact = a * np.sin(kf * Y) * np.sin(X) * math.sin(op.h) / op.h
+    assert np.max(np.abs(Lphi - exact)) <= 1e-13
+
+
+@pytest.mark.parametrize("flow,fp", [(fd.FLOW_ABC, (1.0, 1.0, 1.0)),
+                                     (fd.FLOW_ABC, (0.5, 1.5, 0.8)),
+                                     (fd.FLOW_KOLMOGOROV, (1.0, 3.0, 0.0))])
+def test_sum_conservation(flow, fp):
+    n = 14
+    op = fd.Operator(n, 0.04, flow, fp)
+    phi0 = W.random_field(n, 11)
+    phi, _ = fd.fine_propagate(op, phi0, 0.01, 30)
+    s0, s1 = float(np.sum(phi0)), float(np.sum(phi))
+    assert abs(s1 - s0) <= 1e-12 * float(np.sum(np.abs(phi0)))
+    # and the flow really moves the field
+    assert np.max(np.abs(phi - phi0)) > 1e-2
+
+
+def test_abc_cyclic_permutation():
+    n = 12
+    op = fd.Operator(n, 0.05, fd.FLOW_ABC, (1.0, 1.0, 1.0))
+    phi0 = W.random_field(n, 5)
+
+    def perm(a):  # (P a)[i, j, k] = a[j, k, i]
+        return np.transpose(a, (2, 0, 1))
+
+    a, _ = fd.fine_propagate(op, perm(phi0), 0.02, 10)
+    b, _ = fd.fine_propagate(op, phi0, 0.02, 10)
+    assert np.max(np.abs(a - perm(b))) <= 1e-13
+    # the permutation is not a symmetry of an asymmetric ABC flow
+    op2 = fd.Operator(n, 0.05, fd.FLOW_ABC, (1.0, 0.5, 0.2))
+    a2, _ = fd.fine_propagate(op2, perm(phi0), 0.02, 10)
+    b2, _ = fd.fine_propagate(op2, phi0, 0.02, 10)
+    assert np.max(np.abs(a2 - perm(b2))) > 1e-6
+
+
+def test_step_count_reading():
+    assert fd.steps_per_subinterval(1.0 / 8, 2e-3) == (63, 0.125 / 63)
+    assert fd.steps_per_subinterval(10.0 / 64, 1e-3)[0] == 157
+    assert fd.steps_per_subinterval(50.0 / 128, 5e-4)[0] == 782
+    assert fd.steps_per_subinterval(5.0, 1e-2)[0] == 500   # the paper's 500 steps
+    assert fd.snapshot_stride(63) == 4
+    assert fd.snapshot_stride(157) == 10
+    assert fd.snapshot_stride(782) == 49
+    assert fd.snapshot_stride(500, 5) == 5
+
+
+def test_snapshots_are_states_at_multiples_of_dM():
+    n = 8
+    op = fd.Operator(n, 0.1, fd.FLOW_ABC, (1.0, 1.0, 1.0))
+    phi0 = W.random_field(n, 3)
+    out, Wm = fd.fine_propagate(op, phi0, 0.01, 11, snap_every=4)
+    assert Wm.shape == (n ** 3, 11 // 4 + 1)
+    assert np.array_equal(Wm[:, 0], phi0.reshape(-1))
+    p = phi0
+    for j in range(1, 12):
+        p = fd.rk4_step(op, p, 0.01)
+        if j % 4 == 0:
+            assert np.array_equal(Wm[:, j // 4], p.reshape(-1))
+    assert np.array_equal(out, p)
+
+
+def test_rk4_is_fourth_order_polynomial_of_L():
+    # For linear autonomous L one RK4 step is P4(dt L) phi.
+    n = 6
+    op = fd.Operator(n, 0.07, fd.FLOW_ABC, (1.0, 0.6, 0.3))
+    phi = W.random_field(n, 9)
+    dt = 0.05
+    terms = [phi]
+    for j in range(1, 5):
+        terms.append(op.apply(terms[-1]))
+    poly = phi + dt * terms[1] + dt ** 2 / 2 * terms[2] + dt ** 3 / 6 * terms[3] + dt ** 4 / 24 * terms[4]
+    assert np.max(np.abs(fd.rk4_step(op, phi, dt) - poly)) <= 1e-13

@@ -1,0 +1,96 @@
+"""Pins of the oracle's adaptive parareal iteration (formula4, Algorithm 2).
+
+* Finite termination (Sec. 2): after N' iterations the iterate equals the
+  serial fine solution, and at every k the states U^k_j, j <= k, already do.
+* L-invariant problem: when the snapshots span an L-invariant subspace and
+  the coarse step equals the fine one, G = F and the k = 0 iterate is already
+  the fine solution.
+* The jumps of a converging run decrease and the final error is at the
+  tolerance level.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import parareal
+
+
+def _tiny(flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0), n=12, kappa=0.05, N=6, T=0.6,
+          dt=0.01, tol=0.0, cap0=6, cap=8, ml=1, p=1, coarse_ratio=10):
+    prob = W.Problem(n=n, kappa=kappa, flow=flow, fp=fp)
+    opts = W.PararealOpts(T=T, N=N, dt=dt, cap0=cap0, cap=cap, tol=tol, ml=ml, p=p,
+                          coarse_ratio=coarse_ratio)
+    return prob, opts
+
+
+def test_finite_termination_and_prefix():
+    prob, opts = _tiny()
+    u0 = W.blob_field(prob.n, 7)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref, keep_history=True)
+    Np = opts.N - 1
+    assert r.iters == Np
+    for j in range(opts.N + 1):
+        assert np.array_equal(r.U[j], ref[j].reshape(-1))
+    # prefix property: U^k_j (parareal index j -> time index j + 1) exact for j <= k
+    for k, states in enumerate(r.history):
+        for j in range(0, k + 1):
+            assert np.array_equal(states[j], ref[j + 1].reshape(-1)), (k, j)
+    assert r.errors[-1] == 0.0
+
+
+@pytest.mark.parametrize("ml,p", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 1)])
+def test_finite_termination_all_variants(ml, p):
+    prob, opts = _tiny(N=5, T=0.5, ml=ml, p=p)
+    u0 = W.fourier_field(prob.n, 8, n_modes=6, kmax=3.0)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref)
+    assert r.iters == opts.N - 1
+    assert r.errors[-1] == 0.0
+
+
+def test_invariant_subspace_converges_at_k0():
+    n = 10
+    prob = W.Problem(n=n, kappa=0.05, flow=W.FLOW_UNIFORM, fp=(0.6, -0.9, 0.4))
+    opts = W.PararealOpts(T=0.4, N=4, dt=0.01, cap0=8, cap=8, tol=1e-10,
+                          coarse_ratio=1, gamma1=1.0, gamma2=1.0, gamma3=1.0)
+    x = np.arange(n) * (2 * math.pi / n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    u0 = np.cos(X + 2 * Y - Z) + 0.5 * np.sin(3 * Y + Z + 0.4)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref)
+    assert r.m0 == 4              # two cos/sin pairs
+    assert r.errors[0] <= 1e-12   # G_0 = F on the invariant subspace
+    assert r.iters == 1 and r.jumps[0] <= 1e-12
+
+
+def test_converging_run_reaches_tolerance():
+    prob, opts = _tiny(n=12, kappa=0.3, N=12, T=1.2, tol=1e-7, cap0=8, cap=12,
+                       flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref)
+    assert r.converged
+    assert r.errors[-1] <= 1e-6
+    assert all(b < a for a, b in zip(r.errors[:3], r.errors[1:4]))
+    assert r.iters < opts.N - 1   # converged before finite termination
+    assert r.jumps[-1] <= opts.tol
+
+
+def test_zero_initial_field():
+    prob, opts = _tiny(N=4, T=0.4)
+    u0 = np.zeros((prob.n,) * 3)
+    r = parareal.solve(prob, opts, u0)
+    assert r.m0 == 0
+    assert all(np.all(u == 0) for u in r.U)
+
+
+def test_single_subinterval_is_plain_fine_solve():
+    prob, opts = _tiny(N=1, T=0.1)
+    u0 = W.random_field(prob.n, 4)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0)
+    assert r.iters == 0 and len(r.U) == 2
+    assert np.array_equal(r.U[1], ref[1].reshape(-1))
