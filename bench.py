@@ -1,0 +1,198 @@
+"""Benchmark of the adaptive parareal hot path on one MI355X.
+
+A step is one whole adaptive parareal solve (k = 0 initialisation, every
+iteration's batched fine solves, both POD stages, the sequential
+augmentation / coarse / correction sweep and the convergence check) of the
+128^3 Kolmogorov FP64 workload (kappa = 0.01, T = 10 over 64 subintervals,
+dt = 1e-3, POD rank <= 20), inputs resident in HBM.
+
+Printed JSON line (rank 0, one line):
+  value      fine grid-point RK4 updates per second of the whole solve (GPts/s)
+  roofline   the fine-stencil stage kernel: algorithmic bytes per launch over
+             its average launch duration (HIP events on the library's stream)
+  cpu_baseline  the FP64 oracle's fine propagator on a bounded sample
+plus the time to reach 1e-6 relative L2 against the serial fine solution.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--stencil-only", action="store_true",
+                    help="time only the batched fine propagator (profiling runs)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, budget_s):
+    """Oracle fine propagator (numpy FP64, classical RK4) on one field of the
+    workload, as many RK4 steps as fit the time budget."""
+    import numpy as np
+    import workloads as W
+    from oracle import fd
+    op = fd.Operator.of(w.problem)
+    u = W.initial_field(w)
+    n_f, dt = fd.steps_per_subinterval(w.opts.T / w.opts.N, w.opts.dt)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        u = fd.rk4_step(op, u, dt)
+        steps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    ng = w.problem.n ** 3
+    return {"value": steps * ng / el / 1e9, "unit": "GPts/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} RK4 steps of one {w.problem.n}^3 field of the workload "
+                      f"(oracle fine propagator, numpy FP64, {el:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    from oracle import fd as ofd  # step-count reading only, for the config echo
+
+    w = W.KOL_128_F64
+    prob = pr.problem_of(w.problem)
+    opts = w.opts
+    n = w.problem.n
+    ng = n ** 3
+    N = opts.N
+    ctx = pr.Context(0)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    u0 = torch.from_numpy(W.initial_field(w).reshape(-1).copy()).cuda()
+
+    n_f, dt = ofd.steps_per_subinterval(opts.T / N, opts.dt)
+
+    # serial fine reference (outside the timed region)
+    log("serial fine reference")
+    U_ref = torch.empty((N + 1, ng), dtype=torch.float64, device="cuda")
+    U_ref[0].copy_(u0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(N):
+        pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=n_f, u_in=U_ref[j],
+                                        u_out=U_ref[j + 1])])
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+
+    # stencil roofline: the batched fine launch of one iteration (63 fields)
+    B = N - 1
+    log(f"stencil timing: {B} x {n}^3, {n_f} steps")
+    xin = U_ref[:B].clone()
+    xout = torch.empty_like(xin)
+    items = [dict(prob=prob, dt=dt, n_steps=n_f, u_in=xin[i], u_out=xout[i]) for i in range(B)]
+    pr.pr_fine_propagate(ctx, items)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 2
+    e0.record(stream)
+    for _ in range(reps):
+        pr.pr_fine_propagate(ctx, items)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fine_ms = e0.elapsed_time(e1) / reps
+    launches = 4 * n_f
+    avg_launch_s = fine_ms * 1e-3 / launches
+    # algorithmic bytes: per RK4 step and point, stage 1 reads y and writes w1,
+    # stages 2-4 read y and the previous stage and write one field: 11 x 8 B
+    bytes_per_launch = 11 * 8 * ng * B / 4
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    stencil_gpts = B * ng * n_f / (fine_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_fine_stage<double>", "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "bytes_per_launch": bytes_per_launch}
+    del xin, xout
+    if args.stencil_only:
+        print(json.dumps({"stencil_gpts": stencil_gpts, "roofline": roofline}))
+        ctx.close()
+        return
+
+    def one_solve():
+        U, rep = pr.pr_parareal_solve(ctx, prob, opts, u0, U_ref=U_ref)
+        return U, rep
+
+    for i in range(args.warmup):
+        log(f"warmup solve {i}")
+        one_solve()
+    torch.cuda.synchronize()
+    reps_out = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        log(f"timed solve {i}")
+        _, rep = one_solve()
+        reps_out.append(rep)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    updates = sum(r.fine_updates for r in reps_out)
+    value = updates / el / 1e9
+    rep = reps_out[-1]
+    t_to = None
+    for k, e in enumerate(rep.err):
+        if e <= 1e-6:
+            t_to = rep.t_iter[k]
+            break
+
+    out = {
+        "metric": "fine-stencil GPts/s + %HBM roofline; parareal time to 1e-6 rel L2; p99 latency",
+        "value": round(value, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(el / args.steps * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "flow": "kolmogorov k_f=4", "kappa": w.problem.kappa,
+                   "T": opts.T, "N": N, "dt": opts.dt, "n_f": n_f, "cap": opts.cap,
+                   "tol": opts.tol, "parallelism": "time subintervals batched on 1 GPU"},
+        "iters": rep.iters,
+        "converged": rep.converged,
+        "err_final": rep.err[-1] if rep.err else None,
+        "parareal_time_to_1e-6_s": t_to,
+        "serial_fine_s": round(serial_s, 4),
+        "stencil_gpts": round(stencil_gpts, 2),
+        "t_phase_s": {k: round(v, 4) for k, v in rep.t_phase.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * pr.h -- C ABI of the MOR-based adaptive parareal hot path on MI355X (gfx950).
+ *
+ * Method: arXiv 2601.10981, "A model order reduction based adaptive parareal
+ * method for time-dependent PDEs". The library implements, for the periodic
+ * 3-D advection-diffusion equation u_t = kappa Lap u - v . grad u (eq1 of
+ * Sec. 4 with c = 0, f = 0 and a steady velocity v), the fine propagator F,
+ * POD_Mode (Algorithm 1), the POD-Galerkin coarse propagator G with
+ * augmentation by the interface state (eqaug, eq12, eq13) and the whole
+ * adaptive parareal iteration (formula4, Algorithm 2).
+ *
+ * Discretisation (replaces the paper's FEM + implicit Euler, Sec. 3.1):
+ *   grid      periodic cube [0, L)^3, n^3 nodes x_i = i h, h = L / n
+ *   layout    one field = n^3 contiguous values indexed ((i n) + j) n + k for
+ *             (x_i, y_j, z_k): z fastest
+ *   operator  (L u)_p = kappa sum_d (u_{p+e_d} - 2 u_p + u_{p-e_d}) / h^2
+ *                       - sum_d v_d(p) (u_{p+e_d} - u_{p-e_d}) / (2 h)
+ *   fine step classical RK4 (one step = P4(dt L) for this linear operator)
+ *   mass      M = h^3 I (discrete L2 inner product)
+ *
+ * Conventions for every entry point:
+ *   - Buffers named "device" are device pointers on the context's device;
+ *     the caller allocates and frees them and keeps them alive until the work
+ *     queued on `stream` has completed. The library keeps no caller pointer
+ *     after a call returns.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Unless
+ *     stated otherwise a call only enqueues work on it and returns.
+ *   - Field precision: PR_F64 fields are double; under PR_MIXED the stencil,
+ *     the snapshots and the POD bases are float while states (u_in, u_out,
+ *     U_out) and every reduction, eigen-decomposition, re-orthogonalisation
+ *     and reduced system stay double.
+ *   - Every entry point returns a pr_status; nothing throws or aborts across
+ *     the ABI. pr_last_error() describes the last failure of the context. On
+ *     an error other than PR_ENOTCONV the outputs are unspecified.
+ *   - One host thread at a time per context.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PR_OK = 0,
+  PR_EINVAL = -1,     /* bad shape or parameter                              */
+  PR_ENOMEM = -2,     /* request exceeds the context's HBM budget            */
+  PR_EDEVICE = -3,    /* HIP runtime error                                   */
+  PR_EUNSTABLE = -4,  /* dt * rho(L) > 2.6: outside the RK4 stability region */
+  PR_ENOTCONV = -5,   /* max_iter reached above tol; outputs = last iterate  */
+  PR_ENUMERIC = -6,   /* NaN or Inf in a jump norm                           */
+  PR_EBUSY = -7       /* context in use                                      */
+} pr_status;
+
+enum { PR_FLOW_UNIFORM = 0, PR_FLOW_ABC = 1, PR_FLOW_KOLMOGOROV = 2 };
+enum { PR_F64 = 0, PR_MIXED = 1 };
+
+/* Problem of eq1 (Sec. 4) on the finite-difference grid.
+ *   flow PR_FLOW_ABC:        v = (A sin z + C cos y, B sin x + A cos z,
+ *                                 C sin y + B cos x),  fp = {A, B, C}
+ *   flow PR_FLOW_KOLMOGOROV: v = (a sin(k_f y), 0, 0),  fp = {a, k_f, -}
+ *   flow PR_FLOW_UNIFORM:    v = (c_x, c_y, c_z),        fp = {c_x, c_y, c_z}
+ * n >= 4; L > 0; kappa >= 0. */
+typedef struct {
+  int n;
+  double L;
+  double kappa;
+  int flow;
+  double fp[3];
+  int precision; /* PR_F64 or PR_MIXED */
+} pr_grid_problem;
+
+typedef struct pr_ctx pr_ctx;
+
+/* Create a context on HIP device `device`. The context owns the library's
+ * device scratch memory (never more than hbm_budget_bytes; 0 = 90% of the
+ * device's free memory), its pinned staging memory and its events.
+ * Returns PR_EINVAL for a bad device, PR_EDEVICE on a HIP failure. */
+pr_status pr_ctx_create(int device, size_t hbm_budget_bytes, pr_ctx** out);
+/* Synchronise the context's device and release everything it owns. */
+void pr_ctx_destroy(pr_ctx* ctx);
+/* Message describing the last failure on ctx (never NULL; "" if none). */
+const char* pr_last_error(const pr_ctx* ctx);
+/* Bytes of device scratch currently held by the context. */
+size_t pr_ctx_scratch_bytes(const pr_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Fine propagator F (Sec. 2; Algorithm 2, line 8; snapshot matrix W of
+ * Sec. 3.2 Case I): n_steps RK4 steps of size dt from u_in, for every item of
+ * the batch in the same launches (items may differ in n, flow, kappa, dt and
+ * n_steps but share the precision).
+ *   u_in      device, N_g doubles
+ *   u_out     device, N_g doubles; may equal u_in
+ *   snaps     device, N_g x n_s values in field precision, n_s =
+ *             floor(n_steps / snap_every) + 1, column j (contiguous, N_g
+ *             values) = state after j * snap_every steps; NULL iff
+ *             snap_every == 0
+ * Errors: PR_EINVAL (n < 4, n_steps < 0, dt <= 0, mixed precisions in one
+ * batch, snaps missing), PR_EUNSTABLE (dt * (12 kappa / h^2 +
+ * sum_d max|v_d| / h) > 2.6), PR_ENOMEM (work fields exceed the budget). */
+typedef struct {
+  const pr_grid_problem* prob;
+  double dt;
+  int n_steps;
+  const double* u_in;
+  double* u_out;
+  int snap_every;
+  void* snaps;
+} pr_fine_item;
+pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * POD_Mode (Algorithm 1; Sec. 3.2 Case I and Case II, eq. W^k_n): modes of
+ * the column concatenation W = [block_0, block_1, ...] with M = h^3 I.
+ *   1. G = W^T M W (FP64 sums of per-chunk MFMA partials; FP32 MFMA products
+ *      under PR_MIXED, FP64 MFMA under PR_F64)
+ *   2. eigenpairs of G by cyclic Jacobi in FP64, descending; each
+ *      eigenvector's largest-magnitude entry made positive
+ *   3. r = #{lambda_i > tau_r lambda_1} (tau_r = 1e-13 F64, 1e-6 MIXED);
+ *      m = min(cap, min{k : sum_{i<=k} sqrt(lambda_i) >= gamma
+ *      sum_{i<=r} sqrt(lambda_i)}); force_m >= 0 gives min(force_m, r, cap)
+ *   4. R = W Y_m Lambda_m^{-1/2}, then two CholQR passes in the M inner
+ *      product (a column whose Cholesky pivot falls below 1e-8 is dropped
+ *      with all later ones, lowering m)
+ *   blocks[b]    device pointer to block_cols[b] columns of N_g values each
+ *                (field precision); block_valid[b] is NULL (all columns
+ *                valid) or a device int holding how many leading columns
+ *                are valid (the rest are ignored)
+ *   total columns (sum of block_cols) <= 64; 1 <= cap <= 32
+ *   R_out        device, N_g x cap in field precision; columns >= m zeroed
+ *   m_out        device int
+ *   lambda_out   device, sum(block_cols) doubles (descending; invalid
+ *                columns contribute zero eigenvalues), or NULL */
+typedef struct {
+  const pr_grid_problem* prob;
+  int n_blocks;
+  const void* const* blocks;
+  const int* block_cols;
+  const int* const* block_valid;
+  double gamma;
+  int cap;
+  int force_m;
+  void* R_out;
+  int* m_out;
+  double* lambda_out;
+} pr_pod_item;
+pr_status pr_pod_build(pr_ctx* ctx, int batch, const pr_pod_item* items, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Snapshot Gram (Algorithm 1, step 1): G = W^T M W = h^3 W^T W for the
+ * N_g x ncols column block W (field precision, column j contiguous), on
+ * MFMA (FP32 products under PR_MIXED, FP64 under PR_F64) with FP64 per-chunk
+ * partials summed in a fixed order.
+ *   W       device, ncols * N_g values; 1 <= ncols <= 64
+ *   G_out   device, ncols x ncols doubles, row-major (symmetric)
+ * Errors: PR_EINVAL for a bad problem or ncols. */
+pr_status pr_gram(pr_ctx* ctx, const pr_grid_problem* prob, const void* W, int ncols,
+                  double* G_out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Coarse propagator G_{k,n} (eq. 8 / eq00; with augmentation eqaug, eq12,
+ * eq13; formula4): Galerkin projection of each input state onto span(Psi),
+ * n_c RK4 steps of M_r beta' = L_r beta over dT_total, optional lift.
+ *   R            device, N_g x cap, field precision, M-orthonormal columns
+ *   m            device int: valid columns of R (<= cap <= 32)
+ *   u_aug        NULL, or device N_g doubles: Psi = [R, d] with
+ *                d~ = u_aug - R R^T M u_aug applied twice (CGS2) and d =
+ *                d~ / ||d~||_M, unless ||d~||_M <= 1e-12 ||u_aug||_M (then
+ *                Psi = R); NULL: Psi = R
+ *   n_in         1 or 2 states u_in[0..n_in) (device, N_g doubles)
+ *   n_c          RK4 steps (>= 1), or 0 for ceil(n_f_hint / 10) with
+ *                n_f_hint = round(dT_total / dt_hint)
+ *   the step count is doubled while (dT_total / n_c) ||M_r^{-1} L_r||_F > 2.5
+ *   u_out[i]     NULL, or device N_g doubles: Psi beta_i(dT_total)
+ *   beta_out     NULL, or device n_in x (cap + 1) doubles (row i = beta_i in
+ *                the basis [R(:, 0..m), d]; unused entries zero)
+ *   n_c_out      NULL, or device int: steps after the guard */
+typedef struct {
+  const pr_grid_problem* prob;
+  const void* R;
+  int cap;
+  const int* m;
+  const double* u_aug;
+  int n_in;
+  const double* u_in[2];
+  double dT_total;
+  int n_c;
+  double dt_hint;
+  double* u_out[2];
+  double* beta_out;
+  int* n_c_out;
+} pr_coarse_item;
+pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* items, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * The adaptive parareal solve (formula4, Algorithm 2).
+ * [0, T] is split into N subintervals of DeltaT = T / N; subinterval 0 is the
+ * warm-up window [0, T_0] (T_0 = DeltaT) whose fine solve gives G_0 (Case I);
+ * the parareal partition of [T_0, T] has N - 1 subintervals.
+ *   fine steps    n_f = ceil(DeltaT / dt - 1e-9), delta_t = DeltaT / n_f
+ *   snapshots     every dM steps (0: ceil(n_f / 16))
+ *   coarse steps  n_c = max(1, ceil(n_f / coarse_ratio)) (then the guard)
+ *   POD           gamma1 (k = 0), gamma2 (per subinterval), gamma3 (local
+ *                 collection W^k_n of m_l left neighbours and p previous
+ *                 iterations; 0 <= m_l, 0 <= p <= 1), rank caps cap0 (stage
+ *                 1 and k = 0 use cap) and cap
+ *   stopping      e_k = max_n ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M <= tol,
+ *                 or k = N - 1 (finite termination), or k = max_iter
+ *                 (max_iter <= 0: N - 1)
+ *   u0            device, N_g doubles (t = 0)
+ *   U_out         device, (N + 1) x N_g doubles: U_out[j] = state at j DeltaT
+ *   U_ref         NULL or device (N + 1) x N_g doubles (serial fine
+ *                 solution): then err[k] = max_n ||U^k_n - U_ref||/||U_ref||
+ * The call synchronises `stream` once per iteration (8-byte jump read) and
+ * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
+ * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
+typedef struct {
+  double T;
+  int N;
+  double dt;
+  int dM;
+  double gamma1, gamma2, gamma3;
+  int cap0, cap;
+  int ml, p;
+  int coarse_ratio;
+  double tol;
+  int max_iter;
+  const double* U_ref;
+} pr_parareal_opts;
+
+/* Per-solve report; every pointer member is an optional host array. */
+typedef struct {
+  int iters;          /* parareal iterations performed (k_max)            */
+  int converged;      /* 1 if e_k <= tol or finite termination            */
+  int n_f, dM, n_s, n_c, n_sub; /* derived sizes (n_sub = N - 1)          */
+  int m0;             /* rank of V^0_POD                                   */
+  double* jump;       /* [max_iter + 1]: jump[k - 1] = e_k                 */
+  double* err;        /* [max_iter + 1]: err[k] vs U_ref (k = 0..iters)    */
+  double* t_iter;     /* [max_iter + 1]: seconds from start to end of k    */
+  int* ranks;         /* [(max_iter + 1) * n_sub]: row k, column n: m^k_n  */
+  double t_phase[5];  /* seconds in F, C (POD), U (reduced ops), A, G      */
+  double fine_updates;/* grid-point RK4 updates performed                  */
+  double seconds;     /* wall time of the solve                            */
+} pr_report;
+
+pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,
+                            const pr_parareal_opts* opts, const double* u0,
+                            double* U_out, pr_report* report, void* stream);
+
+/* Device bytes pr_parareal_solve needs for (prob, opts) (pure host function). */
+pr_status pr_footprint(const pr_grid_problem* prob, const pr_parareal_opts* opts,
+                       size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H */

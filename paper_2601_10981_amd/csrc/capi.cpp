@@ -1,0 +1,913 @@
+// libpr: context, staging and the fine / POD / coarse entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "ctx.h"
+
+namespace pr {
+
+[[noreturn]] void fail(pr_status st, const std::string& msg) { throw Error{st, msg}; }
+
+// ---------------------------------------------------------------------------
+// scratch memory
+void* scratch(pr_ctx* c, const std::string& name, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  bytes = (bytes + 4095) & ~size_t(4095);
+  auto& b = c->bufs[name];
+  if (b.bytes >= bytes) return b.p;
+  if (b.p) {
+    PR_HIP(hipDeviceSynchronize());
+    PR_HIP(hipFree(b.p));
+    c->used -= b.bytes;
+    b = pr_ctx::Buf{};
+  }
+  if (c->used + bytes > c->budget) {
+    char msg[256];
+    snprintf(msg, sizeof msg, "scratch '%s' of %zu bytes exceeds the budget (%zu of %zu used)",
+             name.c_str(), bytes, c->used, c->budget);
+    fail(PR_ENOMEM, msg);
+  }
+  PR_HIP(hipMalloc(&b.p, bytes));
+  b.bytes = bytes;
+  c->used += bytes;
+  return b.p;
+}
+
+void release_all(pr_ctx* c) {
+  for (auto& kv : c->bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  c->bufs.clear();
+  c->used = 0;
+}
+
+// ---------------------------------------------------------------------------
+// descriptor staging
+void stage_begin(pr_ctx* c) {
+  c->slot = (c->slot + 1) % pr_ctx::kSlots;
+  PR_HIP(hipEventSynchronize(c->slot_ev[c->slot]));
+  c->off = 0;
+  c->flushed = 0;
+}
+
+void* stage_push_bytes(pr_ctx* c, const void* src, size_t bytes) {
+  const size_t o = (c->off + 255) & ~size_t(255);
+  if (o + bytes > pr_ctx::kSlotBytes) fail(PR_ENOMEM, "descriptor staging slot overflow");
+  if (bytes) memcpy(c->host_slot[c->slot] + o, src, bytes);
+  c->off = o + bytes;
+  return c->dev_slot[c->slot] + o;
+}
+
+void stage_flush(pr_ctx* c, hipStream_t s) {
+  if (c->off > c->flushed) {
+    PR_HIP(hipMemcpyAsync(c->dev_slot[c->slot] + c->flushed, c->host_slot[c->slot] + c->flushed,
+                          c->off - c->flushed, hipMemcpyHostToDevice, s));
+    c->flushed = c->off;
+  }
+}
+
+void stage_end(pr_ctx* c, hipStream_t s) {
+  stage_flush(c, s);
+  PR_HIP(hipEventRecord(c->slot_ev[c->slot], s));
+}
+
+hipEvent_t event_get(pr_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PR_HIP(hipEventCreate(&e));
+  return e;
+}
+void event_put(pr_ctx* c, hipEvent_t e) { c->ev_pool.push_back(e); }
+
+void PhaseEvents::begin(int phase) {
+  if (!c) return;
+  end();
+  cur = phase;
+  cur_start = event_get(c);
+  PR_HIP(hipEventRecord(cur_start, s));
+}
+void PhaseEvents::end() {
+  if (!c || cur < 0) return;
+  hipEvent_t e = event_get(c);
+  PR_HIP(hipEventRecord(e, s));
+  open.push_back({cur, {cur_start, e}});
+  cur = -1;
+  cur_start = nullptr;
+}
+void PhaseEvents::collect() {
+  if (!c) return;
+  for (auto& o : open) {
+    float ms = 0.f;
+    PR_HIP(hipEventElapsedTime(&ms, o.second.first, o.second.second));
+    t[o.first] += ms * 1e-3;
+    event_put(c, o.second.first);
+    event_put(c, o.second.second);
+  }
+  open.clear();
+}
+
+// ---------------------------------------------------------------------------
+// problems
+double spacing(const pr_grid_problem& p) { return p.L / p.n; }
+
+void check_problem(const pr_grid_problem* p) {
+  PR_CHECK(p != nullptr, "null problem");
+  PR_CHECK(p->n >= 4 && p->n <= 2048, "grid size n must be in [4, 2048]");
+  PR_CHECK(std::isfinite(p->L) && p->L > 0, "domain length L must be positive");
+  PR_CHECK(std::isfinite(p->kappa) && p->kappa >= 0, "kappa must be >= 0");
+  PR_CHECK(p->flow == PR_FLOW_UNIFORM || p->flow == PR_FLOW_ABC || p->flow == PR_FLOW_KOLMOGOROV,
+           "unknown flow");
+  PR_CHECK(p->precision == PR_F64 || p->precision == PR_MIXED, "unknown precision");
+  for (int i = 0; i < 3; ++i) PR_CHECK(std::isfinite(p->fp[i]), "flow parameters must be finite");
+}
+
+// Upper bound of |lambda(L)|: 12 kappa / h^2 + sum_d sup|v_d| / h.
+double spectral_bound(const pr_grid_problem& p) {
+  const double h = spacing(p);
+  double vs = 0;
+  if (p.flow == PR_FLOW_ABC) {
+    const double A = fabs(p.fp[0]), B = fabs(p.fp[1]), C = fabs(p.fp[2]);
+    vs = (A + C) + (B + A) + (C + B);
+  } else if (p.flow == PR_FLOW_KOLMOGOROV) {
+    vs = fabs(p.fp[0]);
+  } else {
+    vs = fabs(p.fp[0]) + fabs(p.fp[1]) + fabs(p.fp[2]);
+  }
+  return 12.0 * p.kappa / (h * h) + vs / h;
+}
+
+Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
+  char key[256];
+  snprintf(key, sizeof key, "%d|%a|%d|%a|%a|%a", p.n, p.L, p.flow, p.fp[0], p.fp[1], p.fp[2]);
+  const int n = p.n;
+  auto it = c->tables.find(key);
+  void* dev = nullptr;
+  if (it == c->tables.end()) {
+    const double h = spacing(p), s = 1.0 / (2.0 * h);
+    std::vector<double> t(6 * (size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      const double x = i * h;
+      if (p.flow == PR_FLOW_ABC) {
+        const double A = p.fp[0], B = p.fp[1], C = p.fp[2];
+        t[0 * n + i] = C * cos(x) * s;   // v_x: C cos y
+        t[1 * n + i] = A * sin(x) * s;   // v_x: A sin z
+        t[2 * n + i] = B * sin(x) * s;   // v_y: B sin x
+        t[3 * n + i] = A * cos(x) * s;   // v_y: A cos z
+        t[4 * n + i] = B * cos(x) * s;   // v_z: B cos x
+        t[5 * n + i] = C * sin(x) * s;   // v_z: C sin y
+      } else if (p.flow == PR_FLOW_KOLMOGOROV) {
+        t[0 * n + i] = p.fp[0] * sin(p.fp[1] * x) * s;
+      } else {
+        t[0 * n + i] = p.fp[0] * s;
+        t[2 * n + i] = p.fp[1] * s;
+        t[4 * n + i] = p.fp[2] * s;
+      }
+    }
+    std::vector<float> tf(t.size());
+    for (size_t i = 0; i < t.size(); ++i) tf[i] = (float)t[i];
+    const size_t bytes = t.size() * 8 + tf.size() * 4;
+    PR_HIP(hipMalloc(&dev, bytes));
+    PR_HIP(hipMemcpy(dev, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+    PR_HIP(hipMemcpy((char*)dev + t.size() * 8, tf.data(), tf.size() * 4, hipMemcpyHostToDevice));
+    c->tables[key] = dev;
+  } else {
+    dev = it->second;
+  }
+  const double h = spacing(p);
+  Geom g;
+  g.n = n;
+  g.c_lap = p.kappa / (h * h);
+  g.tab64 = (const double*)dev;
+  g.tab32 = (const float*)((char*)dev + 6 * (size_t)n * 8);
+  return g;
+}
+
+int gram_chunk_rows(long long nrows, int items) {
+  const long long target = std::max(1, 2048 / std::max(1, items));
+  long long ch = (nrows + target - 1) / target;
+  ch = std::max<long long>(ch, 1024);
+  ch = (ch + 63) / 64 * 64;
+  const long long cap = (nrows + 63) / 64 * 64;
+  return (int)std::min(ch, std::max<long long>(cap, 64));
+}
+
+// ---------------------------------------------------------------------------
+// fine propagator
+template <typename T>
+static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
+                       const std::string& tag) {
+  const bool f32 = std::is_same<T, float>::value;
+  const int nwork = f32 ? 3 : 2;
+  size_t total = 0;
+  for (auto& w : items) total += (size_t)ngrid(*w.prob) * nwork * sizeof(T);
+  char* base = (char*)scratch(c, tag + "_w", total);
+  std::vector<FineDesc<T>> descs;
+  long long tiles = 0;
+  int max_steps = 0;
+  size_t off = 0;
+  for (auto& w : items) {
+    const long long ng = ngrid(*w.prob);
+    FineDesc<T> d{};
+    d.g = geom_of(c, *w.prob);
+    T* work = (T*)(base + off);
+    off += (size_t)ng * nwork * sizeof(T);
+    if (f32) {
+      d.y = work;
+      d.wa = work + ng;
+      d.wb = work + 2 * ng;
+      launch_convert_f64_to_f32(w.u_in, (float*)d.y, ng, s);
+    } else {
+      d.y = (T*)w.u_out;
+      d.wa = work;
+      d.wb = work + ng;
+      if (w.u_in != w.u_out)
+        PR_HIP(hipMemcpyAsync(w.u_out, w.u_in, ng * 8, hipMemcpyDeviceToDevice, s));
+    }
+    d.snaps = (T*)w.snaps;
+    d.snap_every = w.snap_every;
+    if (w.snaps) PR_HIP(hipMemcpyAsync(w.snaps, d.y, ng * sizeof(T), hipMemcpyDeviceToDevice, s));
+    d.n_steps = w.n_steps;
+    d.dt = w.dt;
+    d.tiles_q = tiles_q(w.prob->n);
+    d.tiles_x = tiles_x(w.prob->n);
+    d.tile_begin = tiles;
+    tiles += (long long)d.tiles_q * d.tiles_x;
+    max_steps = std::max(max_steps, w.n_steps);
+    descs.push_back(d);
+  }
+  FineDesc<T>* dd = stage_push(c, descs);
+  stage_flush(c, s);
+  if (f32)
+    launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, s);
+  else
+    launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, s);
+  if (f32)
+    for (size_t i = 0; i < items.size(); ++i)
+      launch_convert_f32_to_f64((const float*)descs[i].y, items[i].u_out, ngrid(*items[i].prob), s);
+}
+
+void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
+                  const std::string& tag) {
+  if (items.empty()) return;
+  const int prec = items[0].prob->precision;
+  for (auto& w : items) {
+    check_problem(w.prob);
+    PR_CHECK(w.prob->precision == prec, "all items of a batch must share the precision");
+    PR_CHECK(w.n_steps >= 0, "n_steps must be >= 0");
+    PR_CHECK(std::isfinite(w.dt) && w.dt > 0, "dt must be positive");
+    PR_CHECK(w.u_in && w.u_out, "null state pointer");
+    PR_CHECK(w.snap_every >= 0, "snap_every must be >= 0");
+    PR_CHECK((w.snap_every == 0) == (w.snaps == nullptr), "snaps must be given iff snap_every > 0");
+    if (w.dt * spectral_bound(*w.prob) > kStabRK4)
+      fail(PR_EUNSTABLE, "dt exceeds the RK4 stability bound 2.6 / rho(L)");
+  }
+  if (prec == PR_MIXED) fine_typed<float>(c, items, s, tag);
+  else fine_typed<double>(c, items, s, tag);
+}
+
+// ---------------------------------------------------------------------------
+// Gram products
+void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
+                  hipStream_t s, const std::string& tag) {
+  if (items.empty()) return;
+  const int P = (nb == 0) ? na * (na + 1) / 2 : na * nb;
+  const size_t ncol = (size_t)(na + nb) * 16;
+  std::vector<GemmDesc> descs;
+  std::vector<long long> part_off;
+  long long wg = 0;
+  size_t part_total = 0;
+  for (auto& it : items) {
+    PR_CHECK(it.cols.size() == ncol, "Gram column list size mismatch");
+    GemmDesc d{};
+    d.nrows = it.nrows;
+    d.chunk_rows = gram_chunk_rows(it.nrows, (int)items.size());
+    d.nchunks = (int)((it.nrows + d.chunk_rows - 1) / d.chunk_rows);
+    d.wg_begin = wg;
+    wg += d.nchunks;
+    d.out = it.out;
+    d.ld = it.ld;
+    d.scale = it.scale;
+    part_off.push_back((long long)part_total);
+    part_total += (size_t)d.nchunks * P * 256;
+    descs.push_back(d);
+  }
+  double* part = (double*)scratch(c, tag + "_part", part_total * 8);
+  for (size_t i = 0; i < items.size(); ++i) {
+    descs[i].partial = part + part_off[i];
+    descs[i].cols = stage_push(c, items[i].cols);
+  }
+  GemmDesc* dd = stage_push(c, descs);
+  stage_flush(c, s);
+  launch_gemm_tn(dd, (int)descs.size(), wg, na, nb, f32, s);
+  launch_gemm_reduce(dd, (int)descs.size(), na, nb, s);
+}
+
+// ---------------------------------------------------------------------------
+// L applied to columns
+void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s) {
+  if (items.empty()) return;
+  const bool f32 = items[0].prob->precision == PR_MIXED;
+  long long tiles = 0;
+  if (f32) {
+    std::vector<ApplyLDesc<float>> d;
+    for (auto& w : items) {
+      ApplyLDesc<float> a{};
+      a.g = geom_of(c, *w.prob);
+      a.in = (const float*)w.in;
+      a.out = (float*)w.out;
+      a.ncols = w.ncols;
+      a.mptr = w.mptr;
+      a.tiles_q = tiles_q(w.prob->n);
+      a.tiles_x = tiles_x(w.prob->n);
+      a.tile_begin = tiles;
+      tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
+      d.push_back(a);
+    }
+    auto* dd = stage_push(c, d);
+    stage_flush(c, s);
+    launch_applyL_f32(dd, (int)d.size(), tiles, s);
+  } else {
+    std::vector<ApplyLDesc<double>> d;
+    for (auto& w : items) {
+      ApplyLDesc<double> a{};
+      a.g = geom_of(c, *w.prob);
+      a.in = (const double*)w.in;
+      a.out = (double*)w.out;
+      a.ncols = w.ncols;
+      a.mptr = w.mptr;
+      a.tiles_q = tiles_q(w.prob->n);
+      a.tiles_x = tiles_x(w.prob->n);
+      a.tile_begin = tiles;
+      tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
+      d.push_back(a);
+    }
+    auto* dd = stage_push(c, d);
+    stage_flush(c, s);
+    launch_applyL_f64(dd, (int)d.size(), tiles, s);
+  }
+}
+
+void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out, int ncols,
+                    const int* mptr, hipStream_t s) {
+  enqueue_applyL_batch(c, {ApplyLWork{&p, in, out, ncols, mptr}}, s);
+}
+
+// ---------------------------------------------------------------------------
+// POD_Mode
+static ColDesc col_of(const void* base, int idx, long long ng, bool f32, const int* mptr) {
+  ColDesc d;
+  d.ptr = (const char*)base + (size_t)idx * ng * (f32 ? 4 : 8);
+  d.mptr = mptr;
+  d.idx = idx;
+  d.f32 = f32 ? 1 : 0;
+  return d;
+}
+static ColDesc col_null() { return ColDesc{nullptr, nullptr, 0, 0}; }
+
+static long long tsmm_wgs(long long nrows) { return (nrows + 255) / 256; }
+
+void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
+                 const std::string& tag) {
+  if (items.empty()) return;
+  const int prec = items[0].prob->precision;
+  const bool f32 = prec == PR_MIXED;
+  int maxcols = 0;
+  for (auto& w : items) {
+    check_problem(w.prob);
+    PR_CHECK(w.prob->precision == prec, "all items of a batch must share the precision");
+    PR_CHECK(!w.cols.empty() && (int)w.cols.size() <= kMaxPodCols, "POD input needs 1..64 columns");
+    PR_CHECK(w.cap >= 1 && w.cap <= kMaxCap, "cap must be in [1, 31]");
+    PR_CHECK(w.gamma > 0 && w.gamma <= 1, "gamma must be in (0, 1]");
+    PR_CHECK(w.R_out && w.m_out, "null POD output");
+    maxcols = std::max(maxcols, (int)w.cols.size());
+  }
+  const int na = (maxcols + 15) / 16;
+  const int ldg = na * 16;
+  const int nitems = (int)items.size();
+  double* G = (double*)scratch(c, tag + "_G", (size_t)nitems * ldg * ldg * 8);
+  double* lam = (double*)scratch(c, tag + "_lam", (size_t)nitems * 64 * 8);
+  double* coef = (double*)scratch(c, tag + "_coef", (size_t)nitems * 64 * 32 * 8);
+  double* G2 = (double*)scratch(c, tag + "_G2", (size_t)nitems * 32 * 32 * 8);
+  double* coef2 = (double*)scratch(c, tag + "_coef2", (size_t)nitems * 32 * 32 * 8);
+
+  // 1. Gram of the snapshots (FP32 MFMA for float data)
+  std::vector<GramWork> gw;
+  for (int i = 0; i < nitems; ++i) {
+    GramWork g;
+    g.nrows = ngrid(*items[i].prob);
+    g.cols = items[i].cols;
+    g.cols.resize((size_t)na * 16, col_null());
+    g.out = G + (size_t)i * ldg * ldg;
+    g.ld = ldg;
+    const double h = spacing(*items[i].prob);
+    g.scale = h * h * h;
+    gw.push_back(g);
+  }
+  enqueue_gram(c, gw, na, 0, f32, s, tag + "_g1");
+
+  // 2-3. eigen-decomposition, rank and mode coefficients
+  std::vector<EigDesc> ed;
+  for (int i = 0; i < nitems; ++i) {
+    EigDesc e{};
+    e.G = G + (size_t)i * ldg * ldg;
+    e.ldg = ldg;
+    e.nc = (int)items[i].cols.size();
+    e.gamma = items[i].gamma;
+    e.cap = items[i].cap;
+    e.force_m = items[i].force_m;
+    e.tau_r = f32 ? kTauRankF32 : kTauRankF64;
+    e.lambda = items[i].lambda_out ? items[i].lambda_out : lam + (size_t)i * 64;
+    e.coef = coef + (size_t)i * 64 * 32;
+    e.ld_coef = items[i].cap;
+    e.m_out = items[i].m_out;
+    ed.push_back(e);
+  }
+  EigDesc* edd = stage_push(c, ed);
+  stage_flush(c, s);
+  launch_eig_select(edd, nitems, s);
+
+  // 4. modes R = W Y_m Lambda_m^{-1/2}
+  std::vector<TsmmDesc> td;
+  long long wg = 0;
+  for (int i = 0; i < nitems; ++i) {
+    TsmmDesc t{};
+    t.nrows = ngrid(*items[i].prob);
+    t.in = stage_push(c, items[i].cols);
+    t.nin = (int)items[i].cols.size();
+    t.C = ed[i].coef;
+    t.ldc = items[i].cap;
+    t.out = items[i].R_out;
+    t.out_f32 = f32;
+    t.nout = items[i].cap;
+    t.out_mptr = items[i].m_out;
+    t.add = nullptr;
+    t.alpha = 1.0;
+    t.wg_begin = wg;
+    wg += tsmm_wgs(t.nrows);
+    td.push_back(t);
+  }
+  TsmmDesc* tdd = stage_push(c, td);
+  stage_flush(c, s);
+  launch_tsmm(tdd, nitems, wg, s);
+
+  // 5. two CholQR passes in the M inner product (FP64 MFMA)
+  std::vector<ColDesc> rcols_all;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<GramWork> g2;
+    std::vector<std::vector<ColDesc>> rcols(nitems);
+    for (int i = 0; i < nitems; ++i) {
+      const long long ng = ngrid(*items[i].prob);
+      for (int j = 0; j < 32; ++j)
+        rcols[i].push_back(j < items[i].cap ? col_of(items[i].R_out, j, ng, f32, items[i].m_out)
+                                            : col_null());
+      GramWork g;
+      g.nrows = ng;
+      g.cols = rcols[i];
+      g.out = G2 + (size_t)i * 32 * 32;
+      g.ld = 32;
+      const double h = spacing(*items[i].prob);
+      g.scale = h * h * h;
+      g2.push_back(g);
+    }
+    enqueue_gram(c, g2, 2, 0, false, s, tag + "_g2");
+    std::vector<CholDesc> cd;
+    for (int i = 0; i < nitems; ++i)
+      cd.push_back(CholDesc{G2 + (size_t)i * 32 * 32, 32, items[i].cap, items[i].m_out,
+                            coef2 + (size_t)i * 32 * 32});
+    CholDesc* cdd = stage_push(c, cd);
+    stage_flush(c, s);
+    launch_cholqr_coef(cdd, nitems, s);
+    std::vector<TsmmDesc> t2;
+    wg = 0;
+    for (int i = 0; i < nitems; ++i) {
+      TsmmDesc t{};
+      t.nrows = ngrid(*items[i].prob);
+      std::vector<ColDesc> in(rcols[i].begin(), rcols[i].begin() + items[i].cap);
+      t.in = stage_push(c, in);
+      t.nin = items[i].cap;
+      t.C = coef2 + (size_t)i * 32 * 32;
+      t.ldc = items[i].cap;
+      t.out = items[i].R_out;
+      t.out_f32 = f32;
+      t.nout = items[i].cap;
+      t.out_mptr = items[i].m_out;
+      t.alpha = 1.0;
+      t.wg_begin = wg;
+      wg += tsmm_wgs(t.nrows);
+      t2.push_back(t);
+    }
+    TsmmDesc* t2d = stage_push(c, t2);
+    stage_flush(c, s);
+    launch_tsmm(t2d, nitems, wg, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// correction / lift
+void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi,
+                     const double* coef, const void* fine, int fine_f32, double* out,
+                     const double* prev, const double* ref, double* norms4, double h3,
+                     hipStream_t s, const std::string& tag) {
+  const int nwg = (int)std::min<long long>(4096, std::max<long long>(1, (nrows + 2047) / 2048));
+  double* part = (double*)scratch(c, tag + "_cpart", (size_t)nwg * 4 * 8);
+  CorrectDesc d{};
+  d.nrows = nrows;
+  d.psi = psi.empty() ? nullptr : stage_push(c, psi);
+  d.npsi = (int)psi.size();
+  d.coef = coef;
+  d.fine = fine;
+  d.fine_f32 = fine_f32;
+  d.out = out;
+  d.prev = prev;
+  d.ref = ref;
+  d.partial = part;
+  d.wg_begin = 0;
+  d.nwg = nwg;
+  CorrectDesc* dd = stage_push1(c, d);
+  NormReduceDesc nr{part, nwg, h3, norms4};
+  NormReduceDesc* nrd = stage_push1(c, nr);
+  stage_flush(c, s);
+  launch_correct(dd, 1, nwg, s);
+  launch_norm_reduce(nrd, 1, s);
+}
+
+// ---------------------------------------------------------------------------
+// coarse step
+void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* ph) {
+  const pr_grid_problem& p = *w.prob;
+  const bool f32 = p.precision == PR_MIXED;
+  const long long ng = ngrid(p);
+  const size_t sf = f32 ? 4 : 8;
+  const double h = spacing(p), h3 = h * h * h;
+  const int cap = w.cap;
+  PR_CHECK(cap >= 1 && cap <= kMaxCap, "cap must be in [1, 31]");
+  PR_CHECK(w.n_in == 1 || w.n_in == 2, "n_in must be 1 or 2");
+
+  char* sm = (char*)scratch(c, "co_small", 64 * 1024);
+  double* S1 = (double*)(sm);              // 32 x 16
+  double* S2 = (double*)(sm + 4096);       // 32 x 16
+  double* S3 = (double*)(sm + 8192);       // 16 x 16
+  int* flag = (int*)(sm + 12288);
+  int* status = (int*)(sm + 12288 + 64);
+  double* dscale = (double*)(sm + 12288 + 128);
+  double* coef = (double*)(sm + 16384);    // cap + 1
+  double* betas = (double*)(sm + 16384 + 512);  // 2 x (cap + 1)
+  double* nrm = (double*)(sm + 16384 + 1024);   // scratch norms
+  double* Sbig = (double*)(sm + 20480);    // 32 x 80
+
+  PhaseEvents dummy;
+  PhaseEvents& P = ph ? *ph : dummy;
+
+  const void* LR = w.LR;
+  char* ld = (char*)scratch(c, "co_fields", (size_t)ng * sf * 2 + (size_t)ng * 8);
+  void* dcol = ld;                          // augmented column d (field precision)
+  void* Ld = ld + (size_t)ng * sf;          // L d
+  double* dtil = (double*)(ld + (size_t)ng * sf * 2);
+  if (!LR) {
+    P.begin(2);
+    void* lr = scratch(c, "co_LR", (size_t)ng * sf * cap);
+    enqueue_applyL(c, p, w.R, lr, cap, w.m, s);
+    LR = lr;
+  }
+
+  auto Rcol = [&](int j) { return col_of(w.R, j, ng, f32, w.m); };
+  auto LRcol = [&](int j) { return col_of(LR, j, ng, f32, w.m); };
+  auto f64col = [&](const double* x) { return ColDesc{x, nullptr, 0, 0}; };
+  const int* aug = nullptr;
+  if (w.u_aug) {
+    P.begin(3);
+    // c1 = R^T M u, |u|^2
+    GramWork g1;
+    g1.nrows = ng;
+    for (int j = 0; j < 32; ++j)
+      g1.cols.push_back(j < cap ? Rcol(j) : (j == cap ? f64col(w.u_aug) : col_null()));
+    g1.cols.push_back(f64col(w.u_aug));
+    g1.cols.resize(48, col_null());
+    g1.out = S1;
+    g1.ld = 16;
+    g1.scale = h3;
+    enqueue_gram(c, {g1}, 2, 1, false, s, "co_g");
+    // d~ = u - R c1
+    std::vector<ColDesc> rc;
+    for (int j = 0; j < cap; ++j) rc.push_back(Rcol(j));
+    TsmmDesc t{};
+    t.nrows = ng;
+    t.in = stage_push(c, rc);
+    t.nin = cap;
+    t.C = S1;
+    t.ldc = 16;
+    t.out = dtil;
+    t.out_f32 = 0;
+    t.nout = 1;
+    t.add = w.u_aug;
+    t.alpha = -1.0;
+    t.wg_begin = 0;
+    TsmmDesc* td = stage_push1(c, t);
+    stage_flush(c, s);
+    launch_tsmm(td, 1, tsmm_wgs(ng), s);
+    // second Gram-Schmidt pass: c2 = R^T M d~, d~ -= R c2
+    GramWork g2 = g1;
+    for (int j = cap; j < 32; ++j) g2.cols[j] = col_null();
+    g2.cols[32] = f64col(dtil);
+    g2.out = S2;
+    enqueue_gram(c, {g2}, 2, 1, false, s, "co_g");
+    TsmmDesc t2 = t;
+    t2.in = stage_push(c, rc);
+    t2.C = S2;
+    t2.add = dtil;
+    TsmmDesc* td2 = stage_push1(c, t2);
+    stage_flush(c, s);
+    launch_tsmm(td2, 1, tsmm_wgs(ng), s);
+    // |d~|^2, |u|^2
+    GramWork g3;
+    g3.nrows = ng;
+    g3.cols.push_back(f64col(dtil));
+    g3.cols.push_back(f64col(w.u_aug));
+    g3.cols.resize(16, col_null());
+    g3.out = S3;
+    g3.ld = 16;
+    g3.scale = h3;
+    enqueue_gram(c, {g3}, 1, 0, false, s, "co_g");
+    AugDesc a{S3, S3 + 17, flag, dscale, w.m, nullptr};
+    AugDesc* ad = stage_push1(c, a);
+    stage_flush(c, s);
+    launch_aug_decide(ad, 1, s);
+    launch_scale_into(dtil, dcol, f32, ng, dscale, s);
+    aug = flag;
+    P.begin(2);
+    enqueue_applyL(c, p, dcol, Ld, 1, flag, s);
+  }
+  P.begin(2);
+  // Galerkin products of Psi against [Psi, L Psi, u_in]
+  GramWork gb;
+  gb.nrows = ng;
+  std::vector<ColDesc> psi;
+  for (int j = 0; j < 32; ++j) {
+    ColDesc cd = col_null();
+    if (j < cap) cd = Rcol(j);
+    else if (j == cap && aug) cd = ColDesc{dcol, aug, 0, f32 ? 1 : 0};
+    psi.push_back(cd);
+  }
+  gb.cols = psi;                                   // A tiles
+  gb.cols.insert(gb.cols.end(), psi.begin(), psi.end());  // B: Psi
+  for (int j = 0; j < 32; ++j) {                   // B: L Psi
+    ColDesc cd = col_null();
+    if (j < cap) cd = LRcol(j);
+    else if (j == cap && aug) cd = ColDesc{Ld, aug, 0, f32 ? 1 : 0};
+    gb.cols.push_back(cd);
+  }
+  for (int j = 0; j < 16; ++j)                     // B: states
+    gb.cols.push_back(j < w.n_in ? f64col(w.u_in[j]) : col_null());
+  gb.out = Sbig;
+  gb.ld = 80;
+  gb.scale = h3;
+  enqueue_gram(c, {gb}, 2, 5, false, s, "co_g");
+
+  P.begin(4);
+  double* beta = w.beta_out ? w.beta_out : betas;
+  ReducedDesc rd{};
+  rd.S = Sbig;
+  rd.ld = 80;
+  rd.cap = cap;
+  rd.m = w.m;
+  rd.aug = aug;
+  rd.off_M = 0;
+  rd.off_L = 32;
+  rd.off_U = 64;
+  rd.n_in = w.n_in;
+  rd.dT = w.dT;
+  rd.n_c = w.n_c;
+  rd.beta = beta;
+  rd.coef = coef;
+  rd.n_c_out = w.n_c_out;
+  rd.status = status;
+  ReducedDesc* rdd = stage_push1(c, rd);
+  stage_flush(c, s);
+  launch_reduced(rdd, 1, s);
+  std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
+  if (w.corr_out)
+    enqueue_correct(c, ng, psi_cols, coef, w.fine, 0, w.corr_out, w.prev, w.ref,
+                    w.norms4 ? w.norms4 : nrm, h3, s, "co");
+  for (int i = 0; i < w.n_in; ++i)
+    if (w.lift[i])
+      enqueue_correct(c, ng, psi_cols, beta + (size_t)i * (cap + 1), nullptr, 0, w.lift[i],
+                      nullptr, nullptr, nrm, h3, s, "co");
+  P.end();
+}
+
+}  // namespace pr
+
+using namespace pr;
+
+// ---------------------------------------------------------------------------
+// C ABI
+#define PR_API_BEGIN(ctx) \
+  if (!(ctx)) return PR_EINVAL; \
+  try {
+#define PR_API_END(ctx)                      \
+  }                                          \
+  catch (const pr::Error& e) {               \
+    (ctx)->err = e.msg;                      \
+    return e.st;                             \
+  }                                          \
+  catch (const std::exception& e) {          \
+    (ctx)->err = e.what();                   \
+    return PR_EDEVICE;                       \
+  }                                          \
+  catch (...) {                              \
+    (ctx)->err = "unknown error";            \
+    return PR_EDEVICE;                       \
+  }
+
+extern "C" {
+
+pr_status pr_ctx_create(int device, size_t hbm_budget_bytes, pr_ctx** out) {
+  if (!out) return PR_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PR_EDEVICE;
+  if (device < 0 || device >= ndev) return PR_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return PR_EDEVICE;
+  pr_ctx* c = new pr_ctx();
+  c->device = device;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    delete c;
+    return PR_EDEVICE;
+  }
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)fr);
+  for (int i = 0; i < pr_ctx::kSlots; ++i) {
+    if (hipHostMalloc((void**)&c->host_slot[i], pr_ctx::kSlotBytes) != hipSuccess ||
+        hipMalloc((void**)&c->dev_slot[i], pr_ctx::kSlotBytes) != hipSuccess ||
+        hipEventCreateWithFlags(&c->slot_ev[i], hipEventDisableTiming) != hipSuccess) {
+      pr_ctx_destroy(c);
+      return PR_EDEVICE;
+    }
+  }
+  if (hipHostMalloc((void**)&c->host_scalars, 4096) != hipSuccess) {
+    pr_ctx_destroy(c);
+    return PR_EDEVICE;
+  }
+  *out = c;
+  return PR_OK;
+}
+
+void pr_ctx_destroy(pr_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  release_all(c);
+  for (auto& kv : c->tables) (void)hipFree(kv.second);
+  for (int i = 0; i < pr_ctx::kSlots; ++i) {
+    if (c->host_slot[i]) (void)hipHostFree(c->host_slot[i]);
+    if (c->dev_slot[i]) (void)hipFree(c->dev_slot[i]);
+    if (c->slot_ev[i]) (void)hipEventDestroy(c->slot_ev[i]);
+  }
+  if (c->host_scalars) (void)hipHostFree(c->host_scalars);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* pr_last_error(const pr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t pr_ctx_scratch_bytes(const pr_ctx* c) { return c ? c->used : 0; }
+
+pr_status pr_fine_propagate(pr_ctx* c, int batch, const pr_fine_item* items, void* stream) {
+  PR_API_BEGIN(c)
+  PR_CHECK(batch >= 0 && (batch == 0 || items), "bad batch");
+  if (batch == 0) return PR_OK;
+  PR_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<FineWork> w;
+  for (int i = 0; i < batch; ++i) {
+    const pr_fine_item& it = items[i];
+    w.push_back(FineWork{it.prob, it.dt, it.n_steps, it.u_in, it.u_out, it.snap_every, it.snaps});
+  }
+  stage_begin(c);
+  enqueue_fine(c, w, s, "api_fine");
+  stage_end(c, s);
+  return PR_OK;
+  PR_API_END(c)
+}
+
+pr_status pr_pod_build(pr_ctx* c, int batch, const pr_pod_item* items, void* stream) {
+  PR_API_BEGIN(c)
+  PR_CHECK(batch >= 0 && (batch == 0 || items), "bad batch");
+  if (batch == 0) return PR_OK;
+  PR_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<PodWork> w;
+  for (int i = 0; i < batch; ++i) {
+    const pr_pod_item& it = items[i];
+    check_problem(it.prob);
+    PR_CHECK(it.n_blocks >= 1 && it.blocks && it.block_cols, "POD item needs blocks");
+    const bool f32 = it.prob->precision == PR_MIXED;
+    const long long ng = ngrid(*it.prob);
+    PodWork pw;
+    pw.prob = it.prob;
+    for (int b = 0; b < it.n_blocks; ++b) {
+      PR_CHECK(it.blocks[b] && it.block_cols[b] >= 0, "bad POD block");
+      const int* v = it.block_valid ? it.block_valid[b] : nullptr;
+      for (int j = 0; j < it.block_cols[b]; ++j) pw.cols.push_back(col_of(it.blocks[b], j, ng, f32, v));
+    }
+    pw.gamma = it.gamma;
+    pw.cap = it.cap;
+    pw.force_m = it.force_m;
+    pw.R_out = it.R_out;
+    pw.m_out = it.m_out;
+    pw.lambda_out = it.lambda_out;
+    w.push_back(pw);
+  }
+  for (auto& x : w)
+    PR_CHECK((int)x.cols.size() <= kMaxPodCols && !x.cols.empty(), "POD input needs 1..64 columns");
+  // items of different column-tile counts go in separate launches
+  stage_begin(c);
+  for (int na = 1; na <= 4; ++na) {
+    std::vector<PodWork> g;
+    for (auto& x : w)
+      if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
+    if (!g.empty()) enqueue_pod(c, g, s, "api_pod");
+  }
+  stage_end(c, s);
+  return PR_OK;
+  PR_API_END(c)
+}
+
+pr_status pr_gram(pr_ctx* c, const pr_grid_problem* prob, const void* W, int ncols,
+                  double* G_out, void* stream) {
+  PR_API_BEGIN(c)
+  check_problem(prob);
+  PR_CHECK(W && G_out, "null Gram buffer");
+  PR_CHECK(ncols >= 1 && ncols <= kMaxPodCols, "ncols must be in [1, 64]");
+  PR_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  const bool f32 = prob->precision == PR_MIXED;
+  const long long ng = ngrid(*prob);
+  const int na = (ncols + 15) / 16, ldg = na * 16;
+  double* G = (double*)scratch(c, "api_gram_G", (size_t)ldg * ldg * 8);
+  GramWork g;
+  g.nrows = ng;
+  for (int j = 0; j < ldg; ++j) g.cols.push_back(j < ncols ? col_of(W, j, ng, f32, nullptr) : col_null());
+  g.out = G;
+  g.ld = ldg;
+  const double h = spacing(*prob);
+  g.scale = h * h * h;
+  stage_begin(c);
+  enqueue_gram(c, {g}, na, 0, f32, s, "api_gram");
+  PR_HIP(hipMemcpy2DAsync(G_out, (size_t)ncols * 8, G, (size_t)ldg * 8, (size_t)ncols * 8, ncols,
+                          hipMemcpyDeviceToDevice, s));
+  stage_end(c, s);
+  return PR_OK;
+  PR_API_END(c)
+}
+
+pr_status pr_coarse_propagate(pr_ctx* c, int batch, const pr_coarse_item* items, void* stream) {
+  PR_API_BEGIN(c)
+  PR_CHECK(batch >= 0 && (batch == 0 || items), "bad batch");
+  if (batch == 0) return PR_OK;
+  PR_HIP(hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)stream;
+  for (int i = 0; i < batch; ++i) {
+    const pr_coarse_item& it = items[i];
+    check_problem(it.prob);
+    PR_CHECK(it.R && it.m, "coarse item needs R and m");
+    PR_CHECK(it.cap >= 1 && it.cap <= kMaxCap, "cap must be in [1, 31]");
+    PR_CHECK(it.n_in == 1 || it.n_in == 2, "n_in must be 1 or 2");
+    for (int j = 0; j < it.n_in; ++j) PR_CHECK(it.u_in[j], "null input state");
+    PR_CHECK(std::isfinite(it.dT_total) && it.dT_total > 0, "dT_total must be positive");
+    int n_c = it.n_c;
+    if (n_c <= 0) {
+      PR_CHECK(it.dt_hint > 0, "n_c = 0 needs dt_hint > 0");
+      const long long nf = std::max<long long>(1, llround(it.dT_total / it.dt_hint));
+      n_c = (int)std::max<long long>(1, (nf + 9) / 10);
+    }
+    CoarseWork w{};
+    w.prob = it.prob;
+    w.R = it.R;
+    w.LR = nullptr;
+    w.cap = it.cap;
+    w.m = it.m;
+    w.u_aug = it.u_aug;
+    w.n_in = it.n_in;
+    w.u_in[0] = it.u_in[0];
+    w.u_in[1] = it.n_in > 1 ? it.u_in[1] : nullptr;
+    w.dT = it.dT_total;
+    w.n_c = n_c;
+    w.lift[0] = it.u_out[0];
+    w.lift[1] = it.n_in > 1 ? it.u_out[1] : nullptr;
+    w.beta_out = it.beta_out;
+    w.n_c_out = it.n_c_out;
+    stage_begin(c);
+    enqueue_coarse(c, w, s, nullptr);
+    stage_end(c, s);
+  }
+  return PR_OK;
+  PR_API_END(c)
+}
+
+}  // extern "C"

@@ -1,0 +1,183 @@
+// Context of libpr: scratch memory under a budget, descriptor staging and
+// cached velocity tables. Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pr_internal.h"
+
+struct pr_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  std::string err;
+
+  struct Buf {
+    void* p = nullptr;
+    size_t bytes = 0;
+  };
+  std::map<std::string, Buf> bufs;
+  std::map<std::string, void*> tables;   // velocity tables by problem key
+
+  // Descriptor staging: a ring of pinned host slots mirrored by device slots.
+  static constexpr int kSlots = 8;
+  static constexpr size_t kSlotBytes = size_t(16) << 20;
+  char* host_slot[kSlots] = {};
+  char* dev_slot[kSlots] = {};
+  hipEvent_t slot_ev[kSlots] = {};
+  int slot = -1;
+  size_t off = 0, flushed = 0;
+
+  // Small pinned host buffer for scalars read back by the solver.
+  double* host_scalars = nullptr;
+
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace pr {
+
+// Device scratch buffer `name` of at least `bytes` (grows; budget-checked).
+void* scratch(pr_ctx* c, const std::string& name, size_t bytes);
+void release_all(pr_ctx* c);
+
+// Descriptor staging. begin() takes a fresh slot (waiting for its previous
+// use to complete), push() copies items into it and returns their device
+// address, flush() enqueues the host-to-device copy of what was pushed since
+// the last flush, end() marks the slot's use as finished on `s`.
+void stage_begin(pr_ctx* c);
+void* stage_push_bytes(pr_ctx* c, const void* src, size_t bytes);
+template <typename T>
+T* stage_push(pr_ctx* c, const std::vector<T>& v) {
+  return (T*)stage_push_bytes(c, v.data(), v.size() * sizeof(T));
+}
+template <typename T>
+T* stage_push1(pr_ctx* c, const T& v) {
+  return (T*)stage_push_bytes(c, &v, sizeof(T));
+}
+void stage_flush(pr_ctx* c, hipStream_t s);
+void stage_end(pr_ctx* c, hipStream_t s);
+
+// Problem geometry with device velocity tables.
+Geom geom_of(pr_ctx* c, const pr_grid_problem& p);
+double spacing(const pr_grid_problem& p);
+double spectral_bound(const pr_grid_problem& p);
+void check_problem(const pr_grid_problem* p);
+inline long long ngrid(const pr_grid_problem& p) { return (long long)p.n * p.n * p.n; }
+inline size_t field_bytes(const pr_grid_problem& p) {
+  return (size_t)ngrid(p) * (p.precision == PR_MIXED ? 4 : 8);
+}
+
+// Tile counts of the stencil launches.
+inline int tiles_q(int n) { return (n * n + kTileQ - 1) / kTileQ; }
+inline int tiles_x(int n) { return (n + kChunkX - 1) / kChunkX; }
+
+// Chunking of the MFMA Gram: rows per chunk (multiple of 64) for a launch
+// of `items` items of `nrows` rows.
+int gram_chunk_rows(long long nrows, int items);
+
+// Enqueue helpers shared by the entry points and the solver.
+struct FineWork {
+  const pr_grid_problem* prob;
+  double dt;
+  int n_steps;
+  const double* u_in;
+  double* u_out;
+  int snap_every;
+  void* snaps;
+};
+void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
+                  const std::string& tag);
+
+struct PodWork {
+  const pr_grid_problem* prob;
+  std::vector<ColDesc> cols;   // input columns (<= 64)
+  double gamma;
+  int cap;
+  int force_m;
+  void* R_out;                 // N_g x cap (field precision)
+  int* m_out;
+  double* lambda_out;          // nullable, >= cols.size()
+};
+void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
+                 const std::string& tag);
+
+// One Gram product: A columns (na tiles of 16) against B columns (nb tiles,
+// 0 = symmetric Gram of A), out = scale * A^T B with leading dimension ld.
+struct GramWork {
+  long long nrows;
+  std::vector<ColDesc> cols;   // (na + nb) * 16
+  double* out;
+  int ld;
+  double scale;
+};
+void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
+                  hipStream_t s, const std::string& tag);
+
+void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out, int ncols,
+                    const int* mptr, hipStream_t s);
+struct ApplyLWork {
+  const pr_grid_problem* prob;
+  const void* in;
+  void* out;
+  int ncols;
+  const int* mptr;
+};
+void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
+
+// The coarse step of the sweep (eqaug, eq12, eq13, formula4): augment span(R)
+// with u_aug, form the Galerkin matrices of Psi = [R, d] against [Psi, L Psi,
+// u_in[0], u_in[1]], propagate the projections with RK4 over dT and either
+// lift each (lift) or write the correction Psi (beta_0 - beta_1) + fine into
+// corr_out with jump partials.
+struct CoarseWork {
+  const pr_grid_problem* prob;
+  const void* R;          // N_g x cap (field precision)
+  const void* LR;         // L R (N_g x cap), may be nullptr (then computed)
+  int cap;
+  const int* m;
+  const double* u_aug;    // nullable
+  int n_in;
+  const double* u_in[2];
+  double dT;
+  int n_c;
+  // outputs
+  double* lift[2];        // nullable
+  double* beta_out;       // nullable, n_in x (cap + 1)
+  int* n_c_out;           // nullable
+  // correction (sweep): out = Psi coef + fine, partial norms
+  double* corr_out;       // nullable
+  const double* fine;
+  const double* prev;
+  const double* ref;
+  double* norms4;         // 4 doubles (|U-prev|^2, |U|^2, |U-ref|^2, |ref|^2)
+};
+struct PhaseEvents;
+void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* ph);
+
+// Correction / lift: out = sum_c psi_c coef_c + fine with norm partials.
+void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi,
+                     const double* coef, const void* fine, int fine_f32, double* out,
+                     const double* prev, const double* ref, double* norms4, double h3,
+                     hipStream_t s, const std::string& tag);
+
+// Phase timing with events (F, C, U, A, G).
+struct PhaseEvents {
+  pr_ctx* c = nullptr;
+  hipStream_t s = nullptr;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
+  double t[5] = {0, 0, 0, 0, 0};
+  int cur = -1;
+  hipEvent_t cur_start = nullptr;
+  void begin(int phase);
+  void end();
+  void collect();   // after a synchronisation point
+};
+
+hipEvent_t event_get(pr_ctx* c);
+void event_put(pr_ctx* c, hipEvent_t e);
+
+}  // namespace pr

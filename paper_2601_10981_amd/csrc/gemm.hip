@@ -1,0 +1,418 @@
+// Tall-skinny contractions of the POD and reduced-system path:
+//   * Gram / A^T B on MFMA (the snapshot Gram W^T M W of Algorithm 1 and the
+//     Galerkin products Psi^T M (L Psi), Psi^T M Psi, Psi^T M U of eq. 8 /
+//     eq13), split over row chunks with per-chunk FP64 partials summed in a
+//     fixed order (deterministic);
+//   * out = alpha * In C (+ add): modes r_i = W y_i / sqrt(lambda_i),
+//     re-orthonormalisation, projection residual and lift;
+//   * the parareal correction U^k_{n+1} = Psi (beta_new - beta_old) + F_n
+//     (formula4) with wave-shuffle partial sums of the jump norms.
+#include "pr_internal.h"
+
+namespace pr {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename D>
+__device__ __forceinline__ int find_wg(const D* d, int nd, long long w) {
+  int lo = 0, hi = nd - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].wg_begin <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool col_valid(const ColDesc& c) {
+  return c.ptr != nullptr && (c.mptr == nullptr || c.idx < *c.mptr);
+}
+
+template <typename In>
+__device__ __forceinline__ In load_col(const void* p, int f32, long long row) {
+  return f32 ? (In)((const float*)p)[row] : (In)((const double*)p)[row];
+}
+
+// ---------------------------------------------------------------------------
+// MFMA 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the 16x16 result has lane l holding, in its
+// register v = 0..3, column l % 16 and row
+//   4 (l / 16) + v   for v_mfma_f32_16x16x4_f32,
+//   l / 16 + 4 v     for v_mfma_f64_16x16x4_f64.
+// For a Gram over rows r, A[i][k] = X[r_k][i] and B[k][j] = Y[r_k][j] with
+// the same row r_k for lane group k: lane (i, kq) loads rows
+// r0 + 4 kq + u (u = 0..3) of its column, i.e. 16 lanes x 4 rows of one
+// column are 16 consecutive values (128 B for FP64), and the four u give
+// four MFMA steps over 16 rows.
+template <bool F32>
+struct Mfma;
+template <>
+struct Mfma<false> {
+  using In = double;
+  using Acc = v4d;
+  __device__ static Acc op(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<true> {
+  using In = float;
+  using Acc = v4f;
+  __device__ static Acc op(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <int NA, int NB>
+struct PairList {
+  static constexpr int P = (NB == 0) ? NA * (NA + 1) / 2 : NA * NB;
+  static constexpr int NT = NA + NB;
+  __host__ __device__ static constexpr int a(int p) {
+    if (NB != 0) return p / NB;
+    int i = 0, c = NA;
+    while (p >= c) { p -= c; ++i; --c; }
+    return i;
+  }
+  __host__ __device__ static constexpr int b(int p) {
+    if (NB != 0) return NA + p % NB;
+    int i = 0, c = NA;
+    while (p >= c) { p -= c; ++i; --c; }
+    return i + p;
+  }
+};
+
+constexpr int kFlushSteps = 4;  // FP32 MFMA: fold into FP64 every 4 x 64 rows
+
+template <int NA, int NB, bool F32>
+__global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ descs, int nd) {
+  using M = Mfma<F32>;
+  using In = typename M::In;
+  using PL = PairList<NA, NB>;
+  constexpr int P = PL::P;
+  constexpr int NT = PL::NT;
+  __shared__ double red[4][256];
+
+  const long long w = blockIdx.x;
+  const int f = find_wg(descs, nd, w);
+  const GemmDesc& d = descs[f];
+  const int chunk = (int)(w - d.wg_begin);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ci = lane & 15, kq = lane >> 4;
+
+  const void* cp[NT];
+  int cf[NT];
+  bool cv[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const ColDesc c = d.cols[t * 16 + ci];
+    cv[t] = col_valid(c);
+    cp[t] = c.ptr;
+    cf[t] = c.f32;
+  }
+
+  v4d acc[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) acc[p] = v4d{0.0, 0.0, 0.0, 0.0};
+  typename M::Acc acc32[P];
+  if constexpr (F32) {
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc32[p] = typename M::Acc{0, 0, 0, 0};
+  }
+
+  const long long r_begin = (long long)chunk * d.chunk_rows;
+  const long long r_end = min(d.nrows, r_begin + (long long)d.chunk_rows);
+  int since_flush = 0;
+  for (long long r0 = r_begin + wave * 16; r0 < r_end; r0 += 64) {
+    In v[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long row = r0 + 4 * kq + u;
+        v[t][u] = (cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        if constexpr (F32)
+          acc32[p] = M::op(v[PL::a(p)][u], v[PL::b(p)][u], acc32[p]);
+        else
+          acc[p] = M::op(v[PL::a(p)][u], v[PL::b(p)][u], acc[p]);
+      }
+    }
+    if constexpr (F32) {
+      if (++since_flush < kFlushSteps) continue;
+      since_flush = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[p][e] += (double)acc32[p][e];
+        acc32[p] = typename M::Acc{0, 0, 0, 0};
+      }
+    }
+  }
+  if constexpr (F32) {
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[p][e] += (double)acc32[p][e];
+  }
+
+  // Sum the four waves' tiles through LDS, one pair at a time; thread
+  // t = v * 64 + lane handles the element register v of `lane` holds.
+  const int tv = threadIdx.x >> 6, tl = threadIdx.x & 63;
+  const int e_row = F32 ? 4 * (tl >> 4) + tv : (tl >> 4) + 4 * tv;
+  const int e_out = e_row * 16 + (tl & 15);
+  double* part = d.partial + (long long)chunk * P * 256;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) red[wave][e * 64 + lane] = acc[p][e];
+    __syncthreads();
+    const double s = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                     (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    part[p * 256 + e_out] = s;
+    __syncthreads();
+  }
+}
+
+// Fixed-order reduction of the chunk partials, scaled, into the output
+// matrix (row = A column, column = B column; the symmetric form mirrors).
+template <int NA, int NB>
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
+  using PL = PairList<NA, NB>;
+  constexpr int P = PL::P;
+  const GemmDesc& d = descs[blockIdx.y];
+  const int p = blockIdx.x;
+  const int e = threadIdx.x;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  const double* src = d.partial + (long long)p * 256 + e;
+  const long long stride = (long long)P * 256;
+  int c = 0;
+  for (; c + 4 <= d.nchunks; c += 4) {
+    s0 += src[(long long)(c + 0) * stride];
+    s1 += src[(long long)(c + 1) * stride];
+    s2 += src[(long long)(c + 2) * stride];
+    s3 += src[(long long)(c + 3) * stride];
+  }
+  for (; c < d.nchunks; ++c) s0 += src[(long long)c * stride];
+  const double s = d.scale * ((s0 + s1) + (s2 + s3));
+  const int row = e >> 4, col = e & 15;
+  const int ta = PL::a(p), tb = PL::b(p);
+  if (NB == 0) {
+    d.out[(long long)(ta * 16 + row) * d.ld + tb * 16 + col] = s;
+    if (ta != tb) d.out[(long long)(tb * 16 + col) * d.ld + ta * 16 + row] = s;
+  } else {
+    d.out[(long long)(ta * 16 + row) * d.ld + (tb - NA) * 16 + col] = s;
+  }
+}
+
+template <int NA, int NB>
+static void launch_gemm_shape(const GemmDesc* d, int nd, long long total_wg, bool f32,
+                              hipStream_t s) {
+  if (f32)
+    hipLaunchKernelGGL((k_gemm_tn<NA, NB, true>), dim3((unsigned)total_wg), dim3(256), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL((k_gemm_tn<NA, NB, false>), dim3((unsigned)total_wg), dim3(256), 0, s, d,
+                       nd);
+}
+
+template <int NA, int NB>
+static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P, nd), dim3(256), 0, s, d);
+}
+
+#define PR_GEMM_SHAPES(X) \
+  X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 1) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(1, 2) X(1, 4)
+
+void launch_gemm_tn(const GemmDesc* d, int nd, long long total_wg, int na, int nb, bool f32,
+                    hipStream_t s) {
+  if (total_wg <= 0) return;
+#define X(A, B)                                             \
+  if (na == A && nb == B) {                                 \
+    launch_gemm_shape<A, B>(d, nd, total_wg, f32, s);       \
+    PR_HIP(hipGetLastError());                              \
+    return;                                                 \
+  }
+  PR_GEMM_SHAPES(X)
+#undef X
+  fail(PR_EINVAL, "unsupported Gram shape");
+}
+
+void launch_gemm_reduce(const GemmDesc* d, int nd, int na, int nb, hipStream_t s) {
+  if (nd <= 0) return;
+#define X(A, B)                                  \
+  if (na == A && nb == B) {                      \
+    launch_reduce_shape<A, B>(d, nd, s);         \
+    PR_HIP(hipGetLastError());                   \
+    return;                                      \
+  }
+  PR_GEMM_SHAPES(X)
+#undef X
+  fail(PR_EINVAL, "unsupported Gram shape");
+}
+
+// ---------------------------------------------------------------------------
+// out[:, j] = alpha * sum_c in_c * C[c][j] (+ add for j = 0); j < nout, and
+// columns j >= *out_mptr are zero. Rows are private to a thread, so the
+// output may alias the input columns (all reads of a row precede its writes).
+constexpr int kTsmmMaxOut = 32;
+
+__global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs, int nd) {
+  const long long w = blockIdx.x;
+  const int f = find_wg(descs, nd, w);
+  const TsmmDesc& d = descs[f];
+  const long long row = (w - d.wg_begin) * 256 + threadIdx.x;
+  if (row >= d.nrows) return;
+  double acc[kTsmmMaxOut];
+#pragma unroll
+  for (int j = 0; j < kTsmmMaxOut; ++j) acc[j] = 0.0;
+  const int nout = d.nout;
+  for (int c = 0; c < d.nin; ++c) {
+    const ColDesc cd = d.in[c];
+    if (!col_valid(cd)) continue;
+    const double x = load_col<double>(cd.ptr, cd.f32, row);
+    const double* Cr = d.C + (long long)c * d.ldc;
+#pragma unroll
+    for (int j = 0; j < kTsmmMaxOut; ++j)
+      if (j < nout) acc[j] += x * Cr[j];
+  }
+  const int mo = d.out_mptr ? *d.out_mptr : nout;
+  const long long ng = d.nrows;
+#pragma unroll
+  for (int j = 0; j < kTsmmMaxOut; ++j) {
+    if (j < nout) {
+      double v = (j < mo) ? d.alpha * acc[j] : 0.0;
+      if (j == 0 && d.add != nullptr) v += d.add[row];
+      if (d.out_f32) ((float*)d.out)[(long long)j * ng + row] = (float)v;
+      else ((double*)d.out)[(long long)j * ng + row] = v;
+    }
+  }
+}
+
+void launch_tsmm(const TsmmDesc* d, int nd, long long total_wg, hipStream_t s) {
+  if (total_wg <= 0) return;
+  hipLaunchKernelGGL(k_tsmm, dim3((unsigned)total_wg), dim3(256), 0, s, d, nd);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Parareal correction with jump partials.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_correct(const CorrectDesc* __restrict__ descs, int nd) {
+  __shared__ double red[4][4];
+  const long long w = blockIdx.x;
+  const int f = find_wg(descs, nd, w);
+  const CorrectDesc& d = descs[f];
+  const long long wl = w - d.wg_begin;
+  const long long rows_per_wg = (d.nrows + d.nwg - 1) / d.nwg;
+  const long long r0 = wl * rows_per_wg;
+  const long long r1 = min(d.nrows, r0 + rows_per_wg);
+  double s_jump = 0, s_u = 0, s_err = 0, s_ref = 0;
+  for (long long row = r0 + threadIdx.x; row < r1; row += 256) {
+    double v = 0.0;
+    if (d.fine) v = d.fine_f32 ? (double)((const float*)d.fine)[row] : ((const double*)d.fine)[row];
+    double g = 0.0;
+    for (int c = 0; c < d.npsi; ++c) {
+      const ColDesc cd = d.psi[c];
+      if (!col_valid(cd)) continue;
+      g += d.coef[c] * load_col<double>(cd.ptr, cd.f32, row);
+    }
+    v += g;
+    d.out[row] = v;
+    s_u += v * v;
+    if (d.prev) {
+      const double dj = v - d.prev[row];
+      s_jump += dj * dj;
+    }
+    if (d.ref) {
+      const double r = d.ref[row];
+      const double de = v - r;
+      s_err += de * de;
+      s_ref += r * r;
+    }
+  }
+  s_jump = wave_sum(s_jump);
+  s_u = wave_sum(s_u);
+  s_err = wave_sum(s_err);
+  s_ref = wave_sum(s_ref);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wave][0] = s_jump;
+    red[wave][1] = s_u;
+    red[wave][2] = s_err;
+    red[wave][3] = s_ref;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int i = threadIdx.x;
+    d.partial[wl * 4 + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+  }
+}
+
+void launch_correct(const CorrectDesc* d, int nd, long long total_wg, hipStream_t s) {
+  if (total_wg <= 0) return;
+  hipLaunchKernelGGL(k_correct, dim3((unsigned)total_wg), dim3(256), 0, s, d, nd);
+  PR_HIP(hipGetLastError());
+}
+
+// Per item: out[0..4) = scale * fixed-order sums of partial[nwg][4].
+__global__ __launch_bounds__(256) void k_norm_reduce(const NormReduceDesc* __restrict__ descs) {
+  __shared__ double red[4][4];
+  const NormReduceDesc& d = descs[blockIdx.x];
+  double s[4] = {0, 0, 0, 0};
+  for (int w = threadIdx.x; w < d.nwg; w += 256)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] += d.partial[(long long)w * 4 + i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) s[i] = wave_sum(s[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[wave][i] = s[i];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int i = threadIdx.x;
+    d.out[i] = d.scale * ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
+  }
+}
+
+void launch_norm_reduce(const NormReduceDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// out[0] = max_i sqrt(n[i][0] / n[i][1]) (jump), out[1] = max_i
+// sqrt(n[i][2] / n[i][3]) (error); NaN propagates.
+__global__ void k_jump_max(const double* __restrict__ n4, int count, double* out) {
+  if (threadIdx.x != 0) return;
+  double e = 0.0, r = 0.0;
+  bool bad = false;
+  for (int i = 0; i < count; ++i) {
+    const double j = n4[4 * i + 0], u = n4[4 * i + 1];
+    const double ee = n4[4 * i + 2], rr = n4[4 * i + 3];
+    double q = (u > 0) ? sqrt(j / u) : (j > 0 ? INFINITY : 0.0);
+    if (q != q) bad = true;
+    e = fmax(e, q);
+    double qe = (rr > 0) ? sqrt(ee / rr) : 0.0;
+    r = fmax(r, qe);
+  }
+  out[0] = bad ? NAN : e;
+  out[1] = r;
+}
+
+void launch_jump_max(const double* norms4, int count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_jump_max, dim3(1), dim3(64), 0, s, norms4, count, out);
+  PR_HIP(hipGetLastError());
+}
+
+}  // namespace pr

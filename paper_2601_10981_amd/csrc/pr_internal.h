@@ -1,0 +1,255 @@
+// Internal declarations of libpr: device descriptors, launchers, context.
+// Not part of the public ABI (include/pr.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pr.h"
+
+namespace pr {
+
+struct Error {
+  pr_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(pr_status st, const std::string& msg);
+
+#define PR_HIP(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      ::pr::fail(PR_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+#define PR_CHECK(cond, msg)                                                        \
+  do {                                                                             \
+    if (!(cond)) ::pr::fail(PR_EINVAL, msg);                                       \
+  } while (0)
+
+constexpr int kTileQ = 256;     // stencil: (y, z) points per workgroup
+constexpr int kChunkX = 16;     // stencil: x planes per workgroup
+constexpr int kMaxPodCols = 64;  // columns of one POD input (4 MFMA tiles)
+constexpr int kMaxCap = 31;      // basis columns; cap + 1 fits two MFMA tiles
+constexpr double kTauRankF64 = 1e-13;
+constexpr double kTauRankF32 = 1e-6;
+constexpr double kTauAug = 1e-12;
+constexpr double kDropPivot = 1e-8;
+constexpr double kGuard = 2.5;
+constexpr double kStabRK4 = 2.6;
+
+// ----------------------------------------------------------------------------
+// Grid geometry on the device. The velocity of every flow here is a sum of
+// one-dimensional functions of the two other coordinates, so it is stored as
+// six tables of n values, pre-multiplied by 1 / (2h):
+//   v_x(y, z) = t[0][y] + t[1][z],  v_y(x, z) = t[2][x] + t[3][z],
+//   v_z(x, y) = t[4][x] + t[5][y].
+// tab64 holds them in double, tab32 in float (for the FP32 stencil).
+struct Geom {
+  int n;
+  double c_lap;          // kappa / h^2
+  const double* tab64;   // 6 n doubles
+  const float* tab32;    // 6 n floats
+};
+
+// Column of a tall-skinny operand: N_g values at ptr (float if f32), valid iff
+// mptr == nullptr || idx < *mptr (invalid columns read as zero).
+struct ColDesc {
+  const void* ptr;
+  const int* mptr;
+  int idx;
+  int f32;
+};
+
+// ---- fine propagator -------------------------------------------------------
+template <typename T>
+struct FineDesc {
+  Geom g;
+  T* y;        // state (in place)
+  T* wa;       // stage buffers
+  T* wb;
+  T* snaps;    // nullptr or N_g x n_s
+  int snap_every;
+  int n_steps;
+  double dt;
+  int tiles_q;      // tiles over the (y, z) plane
+  int tiles_x;      // chunks along x
+  long long tile_begin;
+};
+
+// ---- L applied to basis columns -------------------------------------------
+template <typename T>
+struct ApplyLDesc {
+  Geom g;
+  const T* in;     // ncols columns of N_g
+  T* out;
+  int ncols;
+  const int* mptr;  // valid columns (nullptr = all)
+  int tiles_q, tiles_x;
+  long long tile_begin;  // tiles per column = tiles_q * tiles_x
+};
+
+// ---- tall-skinny Gram / A^T B on MFMA --------------------------------------
+struct GemmDesc {
+  long long nrows;
+  int chunk_rows;     // multiple of 64
+  int nchunks;
+  long long wg_begin;
+  const ColDesc* cols;   // (NA + NB) * 16 descriptors (A tiles then B tiles;
+                         //  for the symmetric form only NA tiles)
+  double* partial;       // nchunks x npairs x 256
+  double* out;           // reduced output (ld x ...), row = A column
+  int ld;
+  double scale;
+};
+
+// ---- tall-skinny times small (out = sum_c in_c C[c][j] (+ add)) ------------
+struct TsmmDesc {
+  long long nrows;
+  const ColDesc* in;     // nin descriptors
+  int nin;
+  const double* C;       // nin x ldc, FP64, device
+  int ldc;
+  void* out;             // nout columns of N_g
+  int out_f32;
+  int nout;
+  const int* out_mptr;   // columns >= *out_mptr written as zero (nullptr: none)
+  const double* add;     // nullptr or N_g doubles added to column 0
+  double alpha;
+  long long wg_begin;
+};
+
+// ---- correction with jump partials ----------------------------------------
+struct CorrectDesc {
+  long long nrows;
+  const ColDesc* psi;    // npsi basis columns
+  int npsi;
+  const double* coef;    // npsi doubles (device): beta_new - beta_old
+  const void* fine;      // F_n (double or float if fine_f32); nullptr = 0
+  int fine_f32;
+  double* out;           // U^k_{n+1}
+  const double* prev;    // U^{k-1}_{n+1} (nullable)
+  const double* ref;     // reference (nullable)
+  double* partial;       // nwg x 4: |U-prev|^2, |U|^2, |U-ref|^2, |ref|^2
+  long long wg_begin;
+  int nwg;
+};
+
+// ---- launchers -------------------------------------------------------------
+void launch_fine_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
+                     int max_steps, hipStream_t s);
+void launch_fine_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
+                     int max_steps, hipStream_t s);
+void launch_convert_f64_to_f32(const double* in, float* out, long long n, hipStream_t s);
+void launch_convert_f32_to_f64(const float* in, double* out, long long n, hipStream_t s);
+void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, hipStream_t s);
+void launch_applyL_f32(const ApplyLDesc<float>* d, int nitems, long long total_tiles, hipStream_t s);
+
+// Gram / A^T B: shape = number of A tiles (na) and B tiles (nb, 0 = symmetric
+// Gram of the A tiles). f32 selects the FP32 MFMA (products of float data).
+void launch_gemm_tn(const GemmDesc* d, int nitems, long long total_wg, int na, int nb,
+                    bool f32, hipStream_t s);
+void launch_gemm_reduce(const GemmDesc* d, int nitems, int na, int nb, hipStream_t s);
+
+void launch_tsmm(const TsmmDesc* d, int nitems, long long total_wg, hipStream_t s);
+void launch_correct(const CorrectDesc* d, int nitems, long long total_wg, hipStream_t s);
+
+// Small dense FP64 kernels (one workgroup per item).
+struct EigDesc {
+  const double* G;   // nc x nc (leading dimension ldg)
+  int ldg;
+  int nc;
+  double gamma;
+  int cap;
+  int force_m;
+  double tau_r;
+  double* lambda;    // nc (sorted descending)
+  double* coef;      // nc x ld_coef: Y_m Lambda_m^{-1/2} (columns >= m zero)
+  int ld_coef;
+  int* m_out;
+};
+void launch_eig_select(const EigDesc* d, int nitems, hipStream_t s);
+
+struct CholDesc {
+  const double* G;   // cap x cap (leading dimension ldg): Gram of the modes
+  int ldg;
+  int cap;
+  int* m;            // in/out: valid columns (lowered if a pivot is dropped)
+  double* coef;      // cap x cap: L^{-T} (upper triangular), zero beyond m
+};
+void launch_cholqr_coef(const CholDesc* d, int nitems, hipStream_t s);
+
+// Reduced propagation (one item per coarse solve). The reduced matrices are
+// read from the Gram output: S (q x ld) with Psi^T M Psi in columns
+// [0, q) and Psi^T M L Psi in columns [q_off_L, q_off_L + q) and the
+// projections Psi^T M u_i in column q_off_U + i.
+struct ReducedDesc {
+  const double* S;
+  int ld;            // leading dimension of S (row = basis index)
+  int cap;           // R columns (rows 0..cap-1); the augmented column is row cap
+  const int* m;      // valid R columns
+  const int* aug;    // device flag: 1 if column `cap` (d) is present
+  int off_M, off_L, off_U;
+  int n_in;
+  double dT;
+  int n_c;
+  double* beta;      // n_in x (cap + 1): beta_i(dT)
+  double* coef;      // nullable: (cap+1): beta_0 - beta_1 (correction coefficients)
+  int* n_c_out;      // nullable
+  int* status;       // nullable: set to 1 if M_r is not positive definite
+};
+void launch_reduced(const ReducedDesc* d, int nitems, hipStream_t s);
+
+// k = 0 recurrence: beta_{n+1} = S^{n_c} beta_n for n = 0..count-1 written
+// into coef rows (count x ld_out) for the lift.
+struct Reduced0Desc {
+  const double* S;
+  int ld, cap;
+  const int* m;
+  int off_M, off_L, off_U;
+  double dT;
+  int n_c;
+  int count;
+  double* betas;     // count x ld_out
+  int ld_out;
+  int* n_c_out;
+};
+void launch_reduced0(const Reduced0Desc* d, hipStream_t s);
+
+// Augmentation helpers.
+// aug_decide: given c2 = ||d~||_M^2 and u2 = ||u||_M^2 (from partial sums),
+// set flag and scale = 1/||d~||_M (or 0).
+struct AugDesc {
+  const double* nd2;   // device scalar
+  const double* nu2;   // device scalar
+  int* flag;
+  double* scale;
+  const int* m;        // R columns valid
+  int* m_aug;          // m + flag
+};
+void launch_aug_decide(const AugDesc* d, int nitems, hipStream_t s);
+
+// Partial-sum reduction of jump norms: per item sums partial (nwg x 4) in
+// fixed order into out (4 doubles, times h^3).
+struct NormReduceDesc {
+  const double* partial;
+  int nwg;
+  double scale;
+  double* out;
+};
+void launch_norm_reduce(const NormReduceDesc* d, int nitems, hipStream_t s);
+
+// e_k = max_n sqrt(j_n) / sqrt(u_n) over the items' 4-vectors; err likewise
+// from entries 2 and 3. Writes {e_k, err_k} to out.
+void launch_jump_max(const double* norms4, int count, double* out, hipStream_t s);
+
+// out = (*scale) * in, with out double or float (out_f32).
+void launch_scale_into(const double* in, void* out, int out_f32, long long n,
+                       const double* scale, hipStream_t s);
+
+}  // namespace pr

@@ -1,0 +1,443 @@
+// Small dense FP64 kernels, one workgroup per matrix:
+//   * eigen-decomposition of the POD Gram (Algorithm 1, step 1) by cyclic
+//     two-sided Jacobi in round-robin pair order (all N/2 disjoint rotations of
+//     a round applied together), descending sort, sign normalisation, the
+//     numerical rank and the sqrt(lambda) criterion (Algorithm 1, step 2) and
+//     the mode coefficients Y_m Lambda_m^{-1/2} (r_i = W y_i / sqrt(lambda_i));
+//   * Cholesky of the modes' Gram for CholQR re-orthonormalisation;
+//   * the reduced Galerkin system M_r beta' = L_r beta (eq. 8 / eq13) solved
+//     by RK4 with the step-doubling stability guard.
+#include "pr_internal.h"
+
+namespace pr {
+
+constexpr int kMaxN = 64;
+constexpr int kMaxSweeps = 40;
+constexpr double kJacobiRel = 1e-15;
+
+__global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ descs) {
+  const EigDesc d = descs[blockIdx.x];
+  __shared__ double A[kMaxN][kMaxN + 1];
+  __shared__ double V[kMaxN][kMaxN + 1];
+  __shared__ double cs[kMaxN / 2], sn[kMaxN / 2];
+  __shared__ int pp[kMaxN / 2], qq[kMaxN / 2];
+  __shared__ int rotated;
+  __shared__ double lam[kMaxN];
+  __shared__ int order[kMaxN];
+  __shared__ double sgn[kMaxN];
+  __shared__ int m_sh;
+  const int tid = threadIdx.x;
+  const int nc = d.nc;
+  const int N = nc + (nc & 1);
+  for (int e = tid; e < N * N; e += 256) {
+    const int i = e / N, j = e % N;
+    A[i][j] = (i < nc && j < nc) ? d.G[(long long)i * d.ldg + j] : 0.0;
+    V[i][j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int half = N / 2;
+  for (int sweep = 0; sweep < kMaxSweeps && N >= 2; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < N - 1; ++r) {
+      if (tid < half) {
+        // round-robin tournament: position 0 fixed, the others rotate
+        const int a = (tid == 0) ? 0 : 1 + (tid - 1 + r) % (N - 1);
+        const int b = 1 + (N - 2 - tid + r) % (N - 1);
+        const int p = min(a, b), q = max(a, b);
+        const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-300 && fabs(apq) > kJacobiRel * sqrt(fabs(app * aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          double t;
+          if (fabs(tau) > 1e150) t = 0.5 / tau;
+          else t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          rotated = 1;
+        }
+        cs[tid] = c;
+        sn[tid] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * N; e += 256) {
+        const int i = e / N, k = e % N;
+        const double s = sn[i];
+        if (s == 0.0) continue;
+        const double c = cs[i];
+        const int p = pp[i], q = qq[i];
+        const double apk = A[p][k], aqk = A[q][k];
+        A[p][k] = c * apk - s * aqk;
+        A[q][k] = s * apk + c * aqk;
+      }
+      __syncthreads();
+      for (int e = tid; e < half * N; e += 256) {
+        const int i = e / N, k = e % N;
+        const double s = sn[i];
+        if (s == 0.0) continue;
+        const double c = cs[i];
+        const int p = pp[i], q = qq[i];
+        const double akp = A[k][p], akq = A[k][q];
+        A[k][p] = c * akp - s * akq;
+        A[k][q] = s * akp + c * akq;
+        const double vkp = V[k][p], vkq = V[k][q];
+        V[k][p] = c * vkp - s * vkq;
+        V[k][q] = s * vkp + c * vkq;
+      }
+      __syncthreads();
+    }
+    if (!rotated) break;
+    __syncthreads();
+  }
+  // descending order, ties by index
+  if (tid < nc) {
+    const double li = A[tid][tid];
+    int rank = 0;
+    for (int j = 0; j < nc; ++j) {
+      const double lj = A[j][j];
+      if (lj > li || (lj == li && j < tid)) ++rank;
+    }
+    order[rank] = tid;
+  }
+  __syncthreads();
+  if (tid < nc) {
+    const int col = order[tid];
+    lam[tid] = A[col][col];
+    int kmax = 0;
+    double vmax = -1.0;
+    for (int k = 0; k < nc; ++k) {
+      const double v = fabs(V[k][col]);
+      if (v > vmax) { vmax = v; kmax = k; }
+    }
+    sgn[tid] = (V[kmax][col] < 0.0) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int m = 0;
+    const double l0 = (nc > 0) ? lam[0] : 0.0;
+    if (l0 > 0.0) {
+      int r = 0;
+      while (r < nc && lam[r] > d.tau_r * l0) ++r;
+      if (d.force_m >= 0) {
+        m = min(d.force_m, r);
+      } else {
+        double total = 0.0;
+        for (int i = 0; i < r; ++i) total += sqrt(lam[i]);
+        double acc = 0.0;
+        m = r;
+        for (int i = 0; i < r; ++i) {
+          acc += sqrt(lam[i]);
+          if (acc >= d.gamma * total) { m = i + 1; break; }
+        }
+      }
+      m = min(m, d.cap);
+    }
+    m_sh = m;
+    *d.m_out = m;
+  }
+  __syncthreads();
+  const int m = m_sh;
+  if (d.lambda)
+    for (int i = tid; i < nc; i += 256) d.lambda[i] = lam[i];
+  for (int e = tid; e < nc * d.ld_coef; e += 256) {
+    const int c = e / d.ld_coef, j = e % d.ld_coef;
+    double v = 0.0;
+    if (j < m) v = sgn[j] * V[c][order[j]] / sqrt(lam[j]);
+    d.coef[e] = v;
+  }
+}
+
+void launch_eig_select(const EigDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_eig_select, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky G = L L^T of the leading m x m block of the modes' Gram; a pivot
+// <= kDropPivot drops that column and all later ones (m lowered). Writes
+// coef = L^{-T} (upper triangular, zero beyond the new m), so that
+// R <- R coef has M-orthonormal columns.
+constexpr int kMaxQ = 32;
+
+__global__ __launch_bounds__(256) void k_cholqr_coef(const CholDesc* __restrict__ descs) {
+  const CholDesc d = descs[blockIdx.x];
+  __shared__ double Lm[kMaxQ][kMaxQ + 1];
+  __shared__ double Li[kMaxQ][kMaxQ + 1];
+  __shared__ int m_sh;
+  const int tid = threadIdx.x;
+  const int cap = d.cap;
+  if (tid == 0) m_sh = *d.m;
+  for (int e = tid; e < kMaxQ * kMaxQ; e += 256) {
+    const int i = e / kMaxQ, j = e % kMaxQ;
+    Lm[i][j] = (i < cap && j < cap) ? d.G[(long long)i * d.ldg + j] : 0.0;
+    Li[i][j] = 0.0;
+  }
+  __syncthreads();
+  const int m0 = m_sh;
+  for (int j = 0; j < m0; ++j) {
+    // column j of the right-looking factorisation; Lm's lower triangle is
+    // overwritten with L, the trailing block with the Schur complement
+    if (tid == 0) {
+      const double dj = Lm[j][j];
+      if (!(dj > kDropPivot) && m_sh > j) m_sh = j;
+      if (m_sh > j) Lm[j][j] = sqrt(dj);
+    }
+    __syncthreads();
+    if (m_sh <= j) break;
+    const double ljj = Lm[j][j];
+    for (int i = j + 1 + tid; i < m0; i += 256) Lm[i][j] /= ljj;
+    __syncthreads();
+    const int t = m0 - j - 1;
+    for (int e = tid; e < t * t; e += 256) {
+      const int i = j + 1 + e / t, k = j + 1 + e % t;
+      if (k <= i) Lm[i][k] -= Lm[i][j] * Lm[k][j];
+    }
+    __syncthreads();
+  }
+  const int m = m_sh;
+  // columns of L^{-1} by forward substitution (one column per thread)
+  if (tid < m) {
+    const int c = tid;
+    for (int i = c; i < m; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= Lm[i][k] * Li[k][c];
+      Li[i][c] = s / Lm[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < cap * cap; e += 256) {
+    const int c = e / cap, j = e % cap;
+    d.coef[e] = (c < m && j < m && c <= j) ? Li[j][c] : 0.0;
+  }
+  if (tid == 0) *d.m = m;
+}
+
+void launch_cholqr_coef(const CholDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_cholqr_coef, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Reduced system helpers shared by the sweep and the k = 0 recurrence.
+struct RedShared {
+  double M[kMaxQ + 1][kMaxQ + 2];
+  double K[kMaxQ + 1][kMaxQ + 2];
+  double B[kMaxQ + 1][kMaxQ + 2];
+  double T[kMaxQ + 1][kMaxQ + 2];
+  double beta[2][kMaxQ + 1];
+  double tmp[2][kMaxQ + 1];
+  int idx[kMaxQ + 1];
+  double red[256];
+  int q, n_c, bad;
+};
+
+// Cholesky in place of sh.M (q x q, lower); sets bad on a non-positive pivot.
+__device__ void red_cholesky(RedShared& sh, int q) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < q; ++j) {
+    if (tid == 0) {
+      const double dj = sh.M[j][j];
+      if (!(dj > 0.0)) sh.bad = 1;
+      sh.M[j][j] = sqrt(fmax(dj, 1e-300));
+    }
+    __syncthreads();
+    const double ljj = sh.M[j][j];
+    for (int i = j + 1 + tid; i < q; i += 256) sh.M[i][j] /= ljj;
+    __syncthreads();
+    const int t = q - j - 1;
+    for (int e = tid; e < t * t; e += 256) {
+      const int i = j + 1 + e / t, k = j + 1 + e % t;
+      if (k <= i) sh.M[i][k] -= sh.M[i][j] * sh.M[k][j];
+    }
+    __syncthreads();
+  }
+}
+
+// Solve (L L^T) x = b in place for a vector held by one thread.
+__device__ void red_solve(const RedShared& sh, int q, double* x, int stride) {
+  for (int i = 0; i < q; ++i) {
+    double s = x[i * stride];
+    for (int k = 0; k < i; ++k) s -= sh.M[i][k] * x[k * stride];
+    x[i * stride] = s / sh.M[i][i];
+  }
+  for (int i = q - 1; i >= 0; --i) {
+    double s = x[i * stride];
+    for (int k = i + 1; k < q; ++k) s -= sh.M[k][i] * x[k * stride];
+    x[i * stride] = s / sh.M[i][i];
+  }
+}
+
+// Given sh.M (Cholesky factor) and sh.K holding L_r, turn sh.K into
+// M_r^{-1} L_r, apply the guard and form sh.B = P4(h K) by Horner.
+__device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0) {
+  const int tid = threadIdx.x;
+  if (tid < q) red_solve(sh, q, &sh.K[0][tid], kMaxQ + 2);
+  __syncthreads();
+  double s = 0.0;
+  for (int e = tid; e < q * q; e += 256) {
+    const double v = sh.K[e / q][e % q];
+    s += v * v;
+  }
+  sh.red[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < 256; ++i) t += sh.red[i];
+    const double nrm = sqrt(t);
+    int n_c = max(1, n_c0);
+    while ((dT / n_c) * nrm > kGuard && n_c < (1 << 16)) n_c *= 2;
+    sh.n_c = n_c;
+  }
+  __syncthreads();
+  const double h = dT / sh.n_c;
+  // B = I + (h/4) K
+  for (int e = tid; e < q * q; e += 256) {
+    const int i = e / q, j = e % q;
+    sh.B[i][j] = (i == j ? 1.0 : 0.0) + 0.25 * h * sh.K[i][j];
+  }
+  __syncthreads();
+  const double cf[3] = {h / 3.0, h / 2.0, h};
+  for (int st = 0; st < 3; ++st) {
+    for (int e = tid; e < q * q; e += 256) {
+      const int i = e / q, j = e % q;
+      double acc = 0.0;
+      for (int k = 0; k < q; ++k) acc += sh.K[i][k] * sh.B[k][j];
+      sh.T[i][j] = (i == j ? 1.0 : 0.0) + cf[st] * acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < q * q; e += 256) sh.B[e / q][e % q] = sh.T[e / q][e % q];
+    __syncthreads();
+  }
+}
+
+// beta[v] <- B^{n_c} beta[v] for v < nv.
+__device__ void red_advance(RedShared& sh, int q, int nv) {
+  const int tid = threadIdx.x;
+  for (int it = 0; it < sh.n_c; ++it) {
+    if (tid < nv * q) {
+      const int v = tid / q, i = tid % q;
+      double acc = 0.0;
+      for (int k = 0; k < q; ++k) acc += sh.B[i][k] * sh.beta[v][k];
+      sh.tmp[v][i] = acc;
+    }
+    __syncthreads();
+    if (tid < nv * q) sh.beta[tid / q][tid % q] = sh.tmp[tid / q][tid % q];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__ descs) {
+  const ReducedDesc d = descs[blockIdx.x];
+  __shared__ RedShared sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int m = *d.m;
+    const int aug = d.aug ? *d.aug : 0;
+    int q = 0;
+    for (int a = 0; a < m; ++a) sh.idx[q++] = a;
+    if (aug) sh.idx[q++] = d.cap;
+    sh.q = q;
+    sh.bad = 0;
+  }
+  __syncthreads();
+  const int q = sh.q;
+  for (int e = tid; e < q * q; e += 256) {
+    const int a = e / q, b = e % q;
+    const double* row = d.S + (long long)sh.idx[a] * d.ld;
+    sh.M[a][b] = row[d.off_M + sh.idx[b]];
+    sh.K[a][b] = row[d.off_L + sh.idx[b]];
+  }
+  if (tid < d.n_in * q) {
+    const int v = tid / q, a = tid % q;
+    sh.beta[v][a] = d.S[(long long)sh.idx[a] * d.ld + d.off_U + v];
+  }
+  __syncthreads();
+  red_cholesky(sh, q);
+  if (tid < d.n_in) red_solve(sh, q, sh.beta[tid], 1);
+  __syncthreads();
+  red_propagator(sh, q, d.dT, d.n_c);
+  red_advance(sh, q, d.n_in);
+  const int w = d.cap + 1;
+  for (int e = tid; e < d.n_in * w; e += 256) d.beta[e] = 0.0;
+  if (d.coef)
+    for (int e = tid; e < w; e += 256) d.coef[e] = 0.0;
+  __syncthreads();
+  if (tid < d.n_in * q) {
+    const int v = tid / q, a = tid % q;
+    d.beta[v * w + sh.idx[a]] = sh.beta[v][a];
+  }
+  if (d.coef && tid < q) {
+    const double c = (d.n_in > 1) ? sh.beta[0][tid] - sh.beta[1][tid] : sh.beta[0][tid];
+    d.coef[sh.idx[tid]] = c;
+  }
+  if (tid == 0) {
+    if (d.n_c_out) *d.n_c_out = sh.n_c;
+    if (d.status) *d.status = sh.bad;
+  }
+}
+
+void launch_reduced(const ReducedDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_reduced, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+__global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict__ dp) {
+  const Reduced0Desc d = *dp;
+  __shared__ RedShared sh;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int m = *d.m;
+    for (int a = 0; a < m; ++a) sh.idx[a] = a;
+    sh.q = m;
+    sh.bad = 0;
+  }
+  __syncthreads();
+  const int q = sh.q;
+  for (int e = tid; e < q * q; e += 256) {
+    const int a = e / q, b = e % q;
+    const double* row = d.S + (long long)a * d.ld;
+    sh.M[a][b] = row[d.off_M + b];
+    sh.K[a][b] = row[d.off_L + b];
+  }
+  if (tid < q) sh.beta[0][tid] = d.S[(long long)tid * d.ld + d.off_U];
+  __syncthreads();
+  red_cholesky(sh, q);
+  if (tid == 0) red_solve(sh, q, sh.beta[0], 1);
+  __syncthreads();
+  red_propagator(sh, q, d.dT, d.n_c);
+  for (int n = 0; n < d.count; ++n) {
+    red_advance(sh, q, 1);
+    for (int e = tid; e < d.ld_out; e += 256)
+      d.betas[(long long)n * d.ld_out + e] = (e < q) ? sh.beta[0][e] : 0.0;
+  }
+  if (tid == 0 && d.n_c_out) *d.n_c_out = sh.n_c;
+}
+
+void launch_reduced0(const Reduced0Desc* d, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduced0, dim3(1), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_aug_decide(const AugDesc* __restrict__ descs) {
+  const AugDesc d = descs[blockIdx.x];
+  if (threadIdx.x != 0) return;
+  const double nd2 = *d.nd2, nu2 = *d.nu2;
+  const int flag = (nd2 > 0.0 && nd2 > kTauAug * kTauAug * nu2) ? 1 : 0;
+  *d.flag = flag;
+  *d.scale = flag ? 1.0 / sqrt(nd2) : 0.0;
+  if (d.m_aug) *d.m_aug = *d.m + flag;
+}
+
+void launch_aug_decide(const AugDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_aug_decide, dim3(nd), dim3(64), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+}  // namespace pr

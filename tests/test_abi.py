@@ -1,0 +1,54 @@
+"""The C ABI library loads and exports every entry point include/pr.h
+declares (no device calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2601_10981_amd", "libpr.so")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pr_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2601_10981_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ["pr_fine_propagate", "pr_pod_build", "pr_coarse_propagate", "pr_parareal_solve",
+              "pr_ctx_create", "pr_ctx_destroy", "pr_last_error", "pr_footprint"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_exports():
+    from paper_2601_10981_amd import _lib
+    assert sorted(_lib.EXPORTS) == _declared()
+
+
+def test_footprint_is_host_only():
+    import workloads as W
+    import paper_2601_10981_amd as pr
+    w = W.KOL_128_F64
+    b = pr.pr_footprint(pr.problem_of(w.problem), w.opts)
+    ng = 128 ** 3
+    # at least the two state sets, F_n and two slots of stage-1 bases
+    assert b >= (2 * 64 + 63) * ng * 8 + 2 * 63 * 20 * ng * 8
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_footprint(pr.problem_of(w.problem), W.PararealOpts(T=10.0, N=64, dt=10.0))
+    assert e.value.name == "PR_EUNSTABLE"

@@ -1,0 +1,191 @@
+"""GPU parity of the whole adaptive parareal solve (pr_parareal_solve,
+formula4 / Algorithm 2) against the oracle.
+
+* finite termination: after N - 1 iterations the GPU result equals the GPU
+  serial fine solve bitwise (same kernels) and the oracle's serial solve to
+  1e-12;
+* the converged prefix U^k_j, j <= k, equals the serial fine solve bitwise;
+* iterate by iterate (max_iter = k stops after k iterations and returns the
+  iterate) against the oracle, with identical stage-2 ranks;
+* the 32^3 ABC workload end to end.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import fd, parareal
+from gpu_helpers import rel_l2, say, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2601_10981_amd as pr
+    c = pr.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_serial(ctx, prob, opts, u0):
+    """Serial fine solution on the GPU at t = j DeltaT (N + 1 fields)."""
+    import torch
+    import paper_2601_10981_amd as pr
+    n_f, dt = fd.steps_per_subinterval(opts.T / opts.N, opts.dt)
+    ng = prob.n ** 3
+    out = torch.empty((opts.N + 1, ng), dtype=torch.float64, device="cuda")
+    out[0].copy_(to_dev(u0))
+    for j in range(opts.N):
+        pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=n_f, u_in=out[j], u_out=out[j + 1])])
+    torch.cuda.synchronize()
+    return out
+
+
+def _tiny(n=12, N=6, T=0.6, tol=0.0, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0), kappa=0.05,
+          cap0=6, cap=8, max_iter=0, prec=W.PREC_F64):
+    prob = W.Problem(n=n, kappa=kappa, flow=flow, fp=fp, precision=prec)
+    opts = W.PararealOpts(T=T, N=N, dt=0.01, cap0=cap0, cap=cap, tol=tol, max_iter=max_iter)
+    return prob, opts
+
+
+def test_parareal_finite_termination(ctx):
+    import paper_2601_10981_amd as pr
+    say("parareal finite termination")
+    prob, opts = _tiny()
+    u0 = W.blob_field(prob.n, 7)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.iters == opts.N - 1 and rep.converged
+    assert np.array_equal(to_np(U), to_np(ref))
+    oref = parareal.reference(prob, opts, u0)
+    for j in range(opts.N + 1):
+        assert rel_l2(to_np(U[j]), oref[j]) <= 1e-12
+    assert rep.err[-1] == 0.0
+
+
+def _roundoff_envelope(prob, opts, u0, base, kmax, seeds=(0, 1)):
+    """How far the oracle's own iterates move when every snapshot matrix is
+    perturbed by one unit in the last place (relative 2.2e-16, seeded): the
+    POD modes near the rank cut (lambda ~ 1e-13 lambda_1) are fixed by the
+    data only to about eps lambda_1 / gap, so intermediate iterates of any
+    FP64 implementation agree only to this envelope. Returns env[k]."""
+    from oracle import pod
+    orig = pod.gram
+    env = [0.0] * (kmax + 1)
+    try:
+        for sd in seeds:
+            rng = np.random.Generator(np.random.PCG64(1000 + sd))
+
+            def g(Wm, h3):
+                return orig(Wm * (1.0 + 2.2e-16 * rng.uniform(-1.0, 1.0, Wm.shape)), h3)
+            pod.gram = g
+            alt = parareal.solve(prob, opts, u0, keep_history=True)
+            pod.gram = orig
+            for k in range(1, kmax + 1):
+                e = max(rel_l2(a, b) for a, b in zip(alt.history[k], base.history[k]))
+                env[k] = max(env[k], e)
+    finally:
+        pod.gram = orig
+    return env
+
+
+def test_parareal_prefix_and_iterates_match_oracle(ctx):
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    ores = parareal.solve(prob, opts, u0, keep_history=True)
+    env = _roundoff_envelope(prob, opts, u0, ores, 3)
+    for k in range(1, 4):
+        say(f"parareal iterate k={k}")
+        o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
+        U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+        assert rep.iters == k
+        Un = to_np(U)
+        # converged prefix: time index j + 1 <= k + 1 equals the serial solve bitwise
+        for j in range(0, k + 2):
+            assert np.array_equal(Un[j], to_np(ref[j])), (k, j)
+        # stage-2 ranks are identical to the oracle's
+        assert rep.ranks[k - 1] == ores.ranks[k], (k, rep.ranks[k - 1], ores.ranks[k])
+        hist = ores.history[k]
+        worst = max(rel_l2(Un[j + 1], hist[j]) for j in range(len(hist)))
+        say(f"  k={k} worst iterate rel L2 vs oracle {worst:.3e} (round-off envelope {env[k]:.3e})")
+        assert worst <= 10.0 * env[k] + 1e-12
+
+
+def test_parareal_abc32_workload(ctx):
+    """The 32^3 ABC FP64 workload end to end against the oracle."""
+    import paper_2601_10981_amd as pr
+    w = W.ABC_32_F64
+    u0 = W.initial_field(w)
+    p = pr.problem_of(w.problem)
+    say("parareal abc32: oracle")
+    oref = parareal.reference(w.problem, w.opts, u0)
+    ores = parareal.solve(w.problem, w.opts, u0, U_ref=oref)
+    say("parareal abc32: gpu")
+    ref = gpu_serial(ctx, p, w.opts, u0)
+    for j in range(w.opts.N + 1):
+        assert rel_l2(to_np(ref[j]), oref[j]) <= 1e-12
+    U, rep = pr.pr_parareal_solve(ctx, p, w.opts, to_dev(u0), U_ref=ref)
+    say(f"  iters gpu {rep.iters} oracle {ores.iters}; errs gpu {rep.err} oracle {ores.errors}")
+    assert rep.iters == ores.iters
+    assert rep.m0 == ores.m0
+    for j in range(w.opts.N + 1):
+        assert rel_l2(to_np(U[j]), ores.U[j]) <= 1e-12
+    for eg, eo in zip(rep.err, ores.errors):
+        assert abs(eg - eo) <= 1e-6 * max(eo, 1e-12) + 1e-12
+    for k in range(1, rep.iters + 1):
+        assert rep.ranks[k - 1] == ores.ranks[k]
+
+
+def test_parareal_converges_before_finite_termination(ctx):
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=12, T=1.2, kappa=0.3, tol=1e-7, flow=W.FLOW_KOLMOGOROV,
+                       fp=(1.0, 2.0, 0.0), cap0=8, cap=12)
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    ores = parareal.solve(prob, opts, u0)
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    say(f"converging: gpu iters {rep.iters} jumps {rep.jump}; oracle {ores.iters} {ores.jumps}")
+    assert rep.converged and rep.iters == ores.iters < opts.N - 1
+    assert rep.err[-1] <= 1e-6
+    for j in range(opts.N + 1):
+        assert rel_l2(to_np(U[j]), ores.U[j]) <= 1e-9
+
+
+def test_parareal_mixed_precision_converges(ctx):
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=16, N=8, T=0.8, kappa=0.1, tol=1e-6, prec=W.PREC_MIXED, cap0=8, cap=12)
+    u0 = W.fourier_field(prob.n, 5, n_modes=8, kmax=4.0)
+    p64 = pr.problem_of(W.Problem(n=16, kappa=0.1, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0)))
+    ref = gpu_serial(ctx, p64, opts, u0)
+    U, rep = pr.pr_parareal_solve(ctx, pr.problem_of(prob), opts, to_dev(u0), U_ref=ref)
+    say(f"mixed: iters {rep.iters} errs {rep.err}")
+    assert rep.err[-1] <= 1e-5
+    oref = parareal.reference(W.Problem(n=16, kappa=0.1, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0)),
+                              opts, u0)
+    assert rel_l2(to_np(U[-1]), oref[-1]) <= 1e-5
+
+
+def test_parareal_errors(ctx):
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny()
+    p = pr.problem_of(prob)
+    u0 = to_dev(W.blob_field(prob.n, 1))
+    # DeltaT = 1 with dt = 1: dt * rho(L) ~ 13.6 > 2.6
+    bad = W.PararealOpts(**{**opts.__dict__, "dt": 1.0, "T": 6.0})
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_parareal_solve(ctx, p, bad, u0)
+    assert e.value.name == "PR_EUNSTABLE"
+    bad = W.PararealOpts(**{**opts.__dict__, "cap": 40})
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_parareal_solve(ctx, p, bad, u0)
+    assert e.value.name == "PR_EINVAL"
+    one = W.PararealOpts(**{**opts.__dict__, "max_iter": 1, "tol": 0.0})
+    U, rep = pr.pr_parareal_solve(ctx, p, one, u0)
+    assert rep.status == -5 and rep.iters == 1
