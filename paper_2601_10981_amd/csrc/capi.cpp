@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "ctx.h"
@@ -198,57 +199,100 @@ int gram_chunk_rows(long long nrows, int items) {
 
 // ---------------------------------------------------------------------------
 // fine propagator
+// Tile configuration of the fused stencil (PR_FUSED_CFG overrides: 0 = 32 x 32
+// tiles of 512 threads, 1 = 16 x 32 tiles of 256 threads).
+static int fine_cfg() {
+  static int cfg = [] {
+    const char* e = getenv("PR_FUSED_CFG");
+    return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : 1;
+  }();
+  return cfg;
+}
+
+// x-chunk length of the fused stencil: chunks of up to 64 planes, halved
+// while the batch would give fewer than ~2048 workgroups (small batches, e.g.
+// the serial fine solve of one field, still fill the chip).
+static int fine_chunk(const std::vector<FineWork>& items, int cfg) {
+  int xc = kMaxChunk;
+  auto total = [&](int x) {
+    long long t = 0;
+    for (auto& w : items) {
+      const long long ty = (w.prob->n + fused_ty(cfg) - 1) / fused_ty(cfg);
+      const long long tz = (w.prob->n + fused_tz(cfg) - 1) / fused_tz(cfg);
+      t += ty * tz * ((w.prob->n + x - 1) / x);
+    }
+    return t;
+  };
+  while (xc > 8 && total(xc) < 2048) xc /= 2;
+  return xc;
+}
+
 template <typename T>
 static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
                        const std::string& tag) {
   const bool f32 = std::is_same<T, float>::value;
-  const int nwork = f32 ? 3 : 2;
+  const int nwork = f32 ? 3 : 1;
   size_t total = 0;
   for (auto& w : items) total += (size_t)ngrid(*w.prob) * nwork * sizeof(T);
   char* base = (char*)scratch(c, tag + "_w", total);
+  const int cfg = fine_cfg();
+  const int xc = fine_chunk(items, cfg);
   std::vector<FineDesc<T>> descs;
   long long tiles = 0;
   int max_steps = 0;
   size_t off = 0;
   for (auto& w : items) {
     const long long ng = ngrid(*w.prob);
+    const int n = w.prob->n;
     FineDesc<T> d{};
     d.g = geom_of(c, *w.prob);
     T* work = (T*)(base + off);
     off += (size_t)ng * nwork * sizeof(T);
     if (f32) {
-      d.y = work;
-      d.wa = work + ng;
-      d.wb = work + 2 * ng;
-      launch_convert_f64_to_f32(w.u_in, (float*)d.y, ng, s);
+      d.buf[0] = work;
+      d.buf[1] = work + ng;
+      T* first = work + 2 * ng;
+      launch_convert_f64_to_f32(w.u_in, (float*)first, ng, s);
+      d.first_src = first;
     } else {
-      d.y = (T*)w.u_out;
-      d.wa = work;
-      d.wb = work + ng;
-      if (w.u_in != w.u_out)
-        PR_HIP(hipMemcpyAsync(w.u_out, w.u_in, ng * 8, hipMemcpyDeviceToDevice, s));
+      d.buf[0] = (T*)w.u_out;
+      d.buf[1] = work;
+      d.first_src = (const T*)w.u_in;
+      if (w.n_steps == 0) {
+        if (w.u_in != w.u_out)
+          PR_HIP(hipMemcpyAsync(w.u_out, w.u_in, ng * 8, hipMemcpyDeviceToDevice, s));
+      } else if (w.u_in == w.u_out && (w.n_steps - 1) % 2 == 0) {
+        // the first step writes buf[0] = u_out: read the input from a copy
+        PR_HIP(hipMemcpyAsync(work, w.u_in, ng * 8, hipMemcpyDeviceToDevice, s));
+        d.first_src = work;
+      }
     }
     d.snaps = (T*)w.snaps;
     d.snap_every = w.snap_every;
-    if (w.snaps) PR_HIP(hipMemcpyAsync(w.snaps, d.y, ng * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if (w.snaps)
+      PR_HIP(hipMemcpyAsync(w.snaps, d.first_src, ng * sizeof(T), hipMemcpyDeviceToDevice, s));
     d.n_steps = w.n_steps;
     d.dt = w.dt;
-    d.tiles_q = tiles_q(w.prob->n);
-    d.tiles_x = tiles_x(w.prob->n);
+    d.tiles_y = (n + fused_ty(cfg) - 1) / fused_ty(cfg);
+    d.tiles_z = (n + fused_tz(cfg) - 1) / fused_tz(cfg);
+    d.xc = std::min(xc, n);
+    d.chunks_x = (n + d.xc - 1) / d.xc;
     d.tile_begin = tiles;
-    tiles += (long long)d.tiles_q * d.tiles_x;
+    tiles += (long long)d.tiles_y * d.tiles_z * d.chunks_x;
     max_steps = std::max(max_steps, w.n_steps);
     descs.push_back(d);
   }
   FineDesc<T>* dd = stage_push(c, descs);
   stage_flush(c, s);
   if (f32)
-    launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, s);
+    launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
   else
-    launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, s);
+    launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
   if (f32)
     for (size_t i = 0; i < items.size(); ++i)
-      launch_convert_f32_to_f64((const float*)descs[i].y, items[i].u_out, ngrid(*items[i].prob), s);
+      launch_convert_f32_to_f64(items[i].n_steps > 0 ? (const float*)descs[i].buf[0]
+                                                     : (const float*)descs[i].first_src,
+                                items[i].u_out, ngrid(*items[i].prob), s);
 }
 
 void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,

@@ -44,6 +44,21 @@ constexpr double kGuard = 2.5;
 constexpr double kStabRK4 = 2.6;
 
 // ----------------------------------------------------------------------------
+// Device pointers read from descriptors are generic; casting them to the
+// global address space lets the compiler emit global_load/store (counted by
+// vmcnt only) instead of flat accesses, which also count against lgkmcnt and
+// would make every LDS wait drain the outstanding global loads.
+#define PR_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const PR_GLOBAL T* gptr(const T* p) {
+  return (const PR_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ PR_GLOBAL T* gptr(T* p) {
+  return (PR_GLOBAL T*)p;
+}
+
+// ----------------------------------------------------------------------------
 // Grid geometry on the device. The velocity of every flow here is a sum of
 // one-dimensional functions of the two other coordinates, so it is stored as
 // six tables of n values, pre-multiplied by 1 / (2h):
@@ -67,20 +82,27 @@ struct ColDesc {
 };
 
 // ---- fine propagator -------------------------------------------------------
+// One launch advances every field of the batch by one RK4 step (all four
+// stages fused). Step j reads src(j) and writes buf[ob(j)], with
+// ob(j) = (n_steps - 1 - j) % 2, so the last step lands in buf[0];
+// src(0) = first_src and src(j) = buf[ob(j - 1)].
 template <typename T>
 struct FineDesc {
   Geom g;
-  T* y;        // state (in place)
-  T* wa;       // stage buffers
-  T* wb;
-  T* snaps;    // nullptr or N_g x n_s
+  const T* first_src;
+  T* buf[2];
+  T* snaps;        // nullptr or N_g x n_s: column j = state after j * snap_every steps
   int snap_every;
   int n_steps;
   double dt;
-  int tiles_q;      // tiles over the (y, z) plane
-  int tiles_x;      // chunks along x
+  int tiles_y, tiles_z, chunks_x, xc;  // (y, z) tiles of the launch's shape, x chunks
   long long tile_begin;
 };
+constexpr int kFusedHalo = 4;      // one halo layer per RK4 stage
+constexpr int kMaxChunk = 64;      // x planes per fused-stencil workgroup (at most)
+// output tile (y, z) of fused-stencil configuration cfg
+inline int fused_ty(int cfg) { return cfg == 1 ? 16 : 32; }
+inline int fused_tz(int) { return 32; }
 
 // ---- L applied to basis columns -------------------------------------------
 template <typename T>
@@ -141,10 +163,17 @@ struct CorrectDesc {
 };
 
 // ---- launchers -------------------------------------------------------------
+// Fused RK4 steps; cfg selects the tile shape (0: 32 x 32 tile, 512 threads;
+// 1: 16 x 32 tile, 256 threads). Every field of a launch uses one cfg.
 void launch_fine_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
-                     int max_steps, hipStream_t s);
+                     int max_steps, int cfg, hipStream_t s);
 void launch_fine_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
-                     int max_steps, hipStream_t s);
+                     int max_steps, int cfg, hipStream_t s);
+// One RK4 step (step index `step`) of every field with step < n_steps.
+void launch_fine_step_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
+                          int step, int cfg, hipStream_t s);
+void launch_fine_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
+                          int step, int cfg, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, long long n, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, long long n, hipStream_t s);
 void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, hipStream_t s);

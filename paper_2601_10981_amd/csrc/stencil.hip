@@ -1,16 +1,23 @@
-// Fine propagator kernels: RK4 stages of the periodic FD advection-diffusion
-// operator, batched over fields of different sizes in one launch per stage.
+// Fine propagator kernels of the periodic FD advection-diffusion operator
+// (L u)_p = kappa sum_d (u_{p+e_d} - 2 u_p + u_{p-e_d}) / h^2
+//           - sum_d v_d(p) (u_{p+e_d} - u_{p-e_d}) / (2 h).
 //
-// For the linear autonomous operator L one classical RK4 step is
-// P4(dt L) y with P4(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, evaluated here in
-// Horner form as four stencil sweeps that all use y as base:
+// For this linear autonomous operator one classical RK4 step is P4(dt L) y
+// with P4(z) = 1 + z + z^2/2 + z^3/6 + z^4/24, evaluated in Horner form as
+// four stencil stages that all use y as base:
 //   w1 = y + dt/4 L y,  w2 = y + dt/3 L w1,  w3 = y + dt/2 L w2,
-//   y <- y + dt L w3.
-// Stage traffic per grid point: read y (and the previous stage), write one
-// field. Each thread owns one (y, z) column of a tile and marches along x,
-// keeping the x-1, x, x+1 values of the stage input in registers; the y and
-// z neighbours come from the L1/L2 caches (z fastest, so a tile's z rows are
-// 256 consecutive points and fully coalesced).
+//   y_new = y + dt L w3.
+//
+// k_rk4_fused runs all four stages of one step in one pass over HBM (read y,
+// write y_new: 2 x s_f bytes per point instead of 11 x s_f for four separate
+// sweeps). A workgroup owns a 32 x 32 tile of the (y, z) plane and marches
+// along x through a chunk of planes. Stage s is evaluated on the tile grown
+// by 4 - s halo layers, so the 4-layer halo of y suffices; the stages form a
+// skewed pipeline along x (at march step t: w1 at plane t + 3, w2 at t + 2,
+// w3 at t + 1, y_new at t). Each thread keeps the x - 1, x, x + 1 values of
+// every stage for its columns in registers and exchanges the current plane of
+// each stage through LDS for the y and z neighbours. Workgroups are mapped to
+// XCDs in contiguous tile ranges so neighbouring tiles share an L2.
 #include "pr_internal.h"
 
 namespace pr {
@@ -71,60 +78,212 @@ __device__ __forceinline__ void march_L(const Geom& g, const T* __restrict__ in,
   }
 }
 
-// One RK4 stage for every field of the batch with step < n_steps.
-template <typename T>
-__global__ __launch_bounds__(kTileQ) void k_fine_stage(const FineDesc<T>* __restrict__ descs,
-                                                       int nd, int step, int stage) {
-  const long long t = blockIdx.x;
-  const int f = find_desc(descs, nd, t);
-  const FineDesc<T> d = descs[f];
-  if (step >= d.n_steps) return;
-  const long long lt = t - d.tile_begin;
-  const int tq = (int)(lt % d.tiles_q);
-  const int tx = (int)(lt / d.tiles_q);
-  const int n = d.g.n;
-  const int q = tq * kTileQ + threadIdx.x;
-  if (q >= n * n) return;
-  const int j = q / n, k = q - (q / n) * n;
-  const int x0 = tx * kChunkX;
-  const int x1 = min(n, x0 + kChunkX);
-  const T* in;
-  T* out;
-  T coef;
-  const T dt = (T)d.dt;
-  switch (stage) {
-    case 0: in = d.y;  out = d.wa; coef = dt * (T)0.25; break;
-    case 1: in = d.wa; out = d.wb; coef = dt / (T)3; break;
-    case 2: in = d.wb; out = d.wa; coef = dt * (T)0.5; break;
-    default: in = d.wa; out = d.y; coef = dt; break;
-  }
-  const T* y = d.y;
-  const bool snap = (stage == 3) && d.snaps != nullptr && ((step + 1) % d.snap_every == 0);
-  const long long ng = (long long)n * n * n;
-  T* snapcol = snap ? d.snaps + (long long)((step + 1) / d.snap_every) * ng : nullptr;
-  march_L<T>(d.g, in, j, k, x0, x1, [&](int, long long p, T Lv) {
-    const T v = y[p] + coef * Lv;
-    out[p] = v;
-    if (snap) snapcol[p] = v;
-  });
+// ---------------------------------------------------------------------------
+// Fused RK4 step.
+template <typename T, int RZ>
+__device__ __forceinline__ T lop(T xm, T c, T xp, const T* __restrict__ pl, int i, T clap,
+                                 T vx, T vy, T vz) {
+  const T ym = pl[i - RZ], yp = pl[i + RZ], zm = pl[i - 1], zp = pl[i + 1];
+  const T lap = ((xp + xm) + (yp + ym) + (zp + zm)) - (T)6 * c;
+  const T adv = vx * (xp - xm) + vy * (yp - ym) + vz * (zp - zm);
+  return clap * lap - adv;
 }
 
+__device__ __forceinline__ int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// TY x TZ output tile per workgroup of NT threads; the region with the
+// 4-layer halo has (TY + 8) x (TZ + 8) columns, SL per thread.
+template <typename T, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
+                                                  int step, long long total, long long per_xcd) {
+  constexpr int H = kFusedHalo;
+  constexpr int RY = TY + 2 * H, RZ = TZ + 2 * H;
+  constexpr int NR = RY * RZ;
+  constexpr int SL = (NR + NT - 1) / NT;
+  __shared__ T lds[4][NR];
+  // v_y(x) and v_z(x) parts of the velocity for the chunk's planes
+  // x0 - 6 .. x0 + kMaxChunk + 3
+  __shared__ T vxt[2][kMaxChunk + 10];
+
+  // blocks b, b + 8, b + 16, ... run on one XCD: give them consecutive tiles
+  const long long b = blockIdx.x;
+  const long long t = (b % 8) * per_xcd + b / 8;
+  if (t >= total) return;
+  const int f = find_desc(descs, nd, t);
+  const FineDesc<T>& d = descs[f];
+  if (step >= d.n_steps) return;
+  const long long lt = t - d.tile_begin;
+  const int tz = (int)(lt % d.tiles_z);
+  const long long rest = lt / d.tiles_z;
+  const int ty = (int)(rest % d.tiles_y);
+  const int tx = (int)(rest / d.tiles_y);
+  const int n = d.g.n;
+  const long long plane = (long long)n * n;
+  const int y0 = ty * TY, z0 = tz * TZ;
+  const int x0 = tx * d.xc, x1 = min(n, x0 + d.xc);
+  const int nst = d.n_steps;
+  const PR_GLOBAL T* src = gptr((step == 0) ? d.first_src : (const T*)d.buf[(nst - step) % 2]);
+  PR_GLOBAL T* dst = gptr(d.buf[(nst - 1 - step) % 2]);
+  PR_GLOBAL T* snap = nullptr;
+  if (d.snaps != nullptr && (step + 1) % d.snap_every == 0)
+    snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * plane * n);
+  const PR_GLOBAL T* tab = gptr(tab_of<T>(d.g));
+  const T clap = (T)d.g.c_lap;
+  const T dt = (T)d.dt;
+  const T c1 = dt * (T)0.25, c2 = dt / (T)3, c3 = dt * (T)0.5, c4 = dt;
+
+  int off[SL];   // gy * n + gz of the slot's column
+  int lev[SL];   // ring distance from the output tile (0 inside), 99 = no column
+  bool outp[SL];
+  T vx[SL], vyz[SL], vzy[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+    const int c = threadIdx.x + s * NT;
+    lev[s] = 99;
+    outp[s] = false;
+    off[s] = 0;
+    vx[s] = vyz[s] = vzy[s] = (T)0;
+    if (c < NR) {
+      const int dy = c / RZ - H, dz = c % RZ - H;
+      const int ly = dy < 0 ? -dy : (dy >= TY ? dy - TY + 1 : 0);
+      const int lz = dz < 0 ? -dz : (dz >= TZ ? dz - TZ + 1 : 0);
+      lev[s] = max(ly, lz);
+      outp[s] = lev[s] == 0 && y0 + dy < n && z0 + dz < n;
+      const int gy = wrapi(y0 + dy, n), gz = wrapi(z0 + dz, n);
+      off[s] = gy * n + gz;
+      vx[s] = tab[gy] + tab[n + gz];
+      vyz[s] = tab[3 * n + gz];
+      vzy[s] = tab[5 * n + gy];
+    }
+  }
+
+  for (int i = threadIdx.x; i < x1 - x0 + 10; i += NT) {
+    const int x = wrapi(x0 - 6 + i, n);
+    vxt[0][i] = tab[2 * n + x];
+    vxt[1][i] = tab[4 * n + x];
+  }
+
+  // Y[s][k] = y(tt + k), W1[s][k] = w1(tt + 1 + k), W2[s][k] = w2(tt + k),
+  // W3[s][k] = w3(tt - 1 + k); Yn = y(tt + 5), prefetched one step ahead.
+  T Y[SL][5], W1[SL][3], W2[SL][3], W3[SL][3], Yn[SL];
+#pragma unroll
+  for (int s = 0; s < SL; ++s) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) Y[s][k] = (T)0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) W1[s][k] = W2[s][k] = W3[s][k] = (T)0;
+    Yn[s] = (T)0;
+  }
+  {
+    const long long pa = (long long)wrapi(x0 - 4, n) * plane;
+    const long long pb = (long long)wrapi(x0 - 3, n) * plane;
+    const long long pc = (long long)wrapi(x0 - 2, n) * plane;
+    // unconditional loads (slots without a column read offset 0): a
+    // conditional load would merge values across lanes and wait at once
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      Y[s][2] = src[pa + off[s]];
+      Y[s][3] = src[pb + off[s]];
+      Yn[s] = src[pc + off[s]];
+    }
+  }
+
+  // march step tt: w1 at plane tt + 3, w2 at tt + 2, w3 at tt + 1, y_new at tt
+  for (int tt = x0 - 6; tt < x1; ++tt) {
+    const long long p5 = (long long)wrapi(tt + 5, n) * plane;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int c = threadIdx.x + s * NT;
+      Y[s][4] = Yn[s];
+      Yn[s] = src[p5 + off[s]];   // consumed next step
+      if (c < NR) {
+        lds[0][c] = Y[s][3];
+        lds[1][c] = W1[s][1];
+        lds[2][c] = W2[s][1];
+        lds[3][c] = W3[s][1];
+      }
+    }
+    __syncthreads();
+    const int xd = wrapi(tt, n);
+    const int iv = tt - (x0 - 6);
+    const T vy_a = vxt[0][iv + 3], vz_a = vxt[1][iv + 3];
+    const T vy_b = vxt[0][iv + 2], vz_b = vxt[1][iv + 2];
+    const T vy_c = vxt[0][iv + 1], vz_c = vxt[1][iv + 1];
+    const T vy_d = vxt[0][iv], vz_d = vxt[1][iv];
+    const bool s2 = tt >= x0 - 4, s3 = tt >= x0 - 2, s4 = tt >= x0;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+      const int c = threadIdx.x + s * NT;
+      const int lv = lev[s];
+      if (lv <= 3)
+        W1[s][2] = Y[s][3] + c1 * lop<T, RZ>(Y[s][2], Y[s][3], Y[s][4], lds[0], c, clap, vx[s],
+                                             vy_a + vyz[s], vz_a + vzy[s]);
+      if (s2 && lv <= 2)
+        W2[s][2] = Y[s][2] + c2 * lop<T, RZ>(W1[s][0], W1[s][1], W1[s][2], lds[1], c, clap, vx[s],
+                                             vy_b + vyz[s], vz_b + vzy[s]);
+      if (s3 && lv <= 1)
+        W3[s][2] = Y[s][1] + c3 * lop<T, RZ>(W2[s][0], W2[s][1], W2[s][2], lds[2], c, clap, vx[s],
+                                             vy_c + vyz[s], vz_c + vzy[s]);
+      if (s4 && outp[s]) {
+        const T yn = Y[s][0] + c4 * lop<T, RZ>(W3[s][0], W3[s][1], W3[s][2], lds[3], c, clap,
+                                               vx[s], vy_d + vyz[s], vz_d + vzy[s]);
+        const long long gi = (long long)xd * plane + off[s];
+        dst[gi] = yn;
+        if (snap) snap[gi] = yn;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Y[s][k] = Y[s][k + 1];
+      W1[s][0] = W1[s][1];
+      W1[s][1] = W1[s][2];
+      W2[s][0] = W2[s][1];
+      W2[s][1] = W2[s][2];
+      W3[s][0] = W3[s][1];
+      W3[s][1] = W3[s][2];
+    }
+  }
+}
+
+// Tile configurations of the fused step (index = FineDesc::cfg).
 template <typename T>
-static void launch_fine_impl(const FineDesc<T>* d, int nd, long long total_tiles, int max_steps,
+static void launch_step_impl(const FineDesc<T>* d, int nd, long long total, int step, int cfg,
                              hipStream_t s) {
-  if (total_tiles <= 0) return;
-  for (int step = 0; step < max_steps; ++step)
-    for (int stage = 0; stage < 4; ++stage)
-      hipLaunchKernelGGL(k_fine_stage<T>, dim3((unsigned)total_tiles), dim3(kTileQ), 0, s, d, nd,
-                         step, stage);
+  if (total <= 0) return;
+  const long long g8 = (total + 7) / 8 * 8;
+  if (cfg == 1)
+    hipLaunchKernelGGL((k_rk4_fused<T, 16, 32, 256>), dim3((unsigned)g8), dim3(256), 0, s, d, nd,
+                       step, total, g8 / 8);
+  else
+    hipLaunchKernelGGL((k_rk4_fused<T, 32, 32, 512>), dim3((unsigned)g8), dim3(512), 0, s, d, nd,
+                       step, total, g8 / 8);
+}
+
+void launch_fine_step_f64(const FineDesc<double>* d, int nd, long long total, int step, int cfg,
+                          hipStream_t s) {
+  launch_step_impl<double>(d, nd, total, step, cfg, s);
+  PR_HIP(hipGetLastError());
+}
+void launch_fine_step_f32(const FineDesc<float>* d, int nd, long long total, int step, int cfg,
+                          hipStream_t s) {
+  launch_step_impl<float>(d, nd, total, step, cfg, s);
   PR_HIP(hipGetLastError());
 }
 
-void launch_fine_f64(const FineDesc<double>* d, int nd, long long tt, int ms, hipStream_t s) {
-  launch_fine_impl<double>(d, nd, tt, ms, s);
+void launch_fine_f64(const FineDesc<double>* d, int nd, long long total, int max_steps, int cfg,
+                     hipStream_t s) {
+  for (int step = 0; step < max_steps; ++step) launch_step_impl<double>(d, nd, total, step, cfg, s);
+  PR_HIP(hipGetLastError());
 }
-void launch_fine_f32(const FineDesc<float>* d, int nd, long long tt, int ms, hipStream_t s) {
-  launch_fine_impl<float>(d, nd, tt, ms, s);
+void launch_fine_f32(const FineDesc<float>* d, int nd, long long total, int max_steps, int cfg,
+                     hipStream_t s) {
+  for (int step = 0; step < max_steps; ++step) launch_step_impl<float>(d, nd, total, step, cfg, s);
+  PR_HIP(hipGetLastError());
 }
 
 // out = L(in) for each valid column; invalid columns are written as zero.
