@@ -121,7 +121,7 @@ pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, v
  *   3. r = #{lambda_i > tau_r lambda_1} (tau_r = 1e-13 F64, 1e-6 MIXED);
  *      m = min(cap, min{k : sum_{i<=k} sqrt(lambda_i) >= gamma
  *      sum_{i<=r} sqrt(lambda_i)}); force_m >= 0 gives min(force_m, r, cap)
- *   4. R = W Y_m Lambda_m^{-1/2}, then two CholQR passes in the M inner
+ *   4. R = W Y_m Lambda_m^{-1/2}, then a CholQR pass in the M inner
  *      product (a column whose Cholesky pivot falls below 1e-8 is dropped
  *      with all later ones, lowering m)
  *   blocks[b]    device pointer to block_cols[b] columns of N_g values each

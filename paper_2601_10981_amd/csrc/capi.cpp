@@ -189,7 +189,7 @@ Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
 }
 
 int gram_chunk_rows(long long nrows, int items) {
-  const long long target = std::max(1, 2048 / std::max(1, items));
+  const long long target = std::max(1, 1024 / std::max(1, items));
   long long ch = (nrows + target - 1) / target;
   ch = std::max<long long>(ch, 1024);
   ch = (ch + 63) / 64 * 64;
@@ -413,7 +413,7 @@ static ColDesc col_of(const void* base, int idx, long long ng, bool f32, const i
 }
 static ColDesc col_null() { return ColDesc{nullptr, nullptr, 0, 0}; }
 
-static long long tsmm_wgs(long long nrows) { return (nrows + 255) / 256; }
+static long long tsmm_wgs(long long nrows) { return (nrows + 511) / 512; }
 
 void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
                  const std::string& tag) {
@@ -499,9 +499,10 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   stage_flush(c, s);
   launch_tsmm(tdd, nitems, wg, s);
 
-  // 5. two CholQR passes in the M inner product (FP64 MFMA)
-  std::vector<ColDesc> rcols_all;
-  for (int pass = 0; pass < 2; ++pass) {
+  // 5. CholQR in the M inner product (FP64 MFMA Gram, FP64 Cholesky). The
+  // modes enter with kappa(R) ~ 1 + eps lambda_1 / lambda_m <= 1 + 1e-3, so
+  // one pass already leaves eps kappa^2 ~ eps loss of orthogonality.
+  for (int pass = 0; pass < kCholQRPasses; ++pass) {
     std::vector<GramWork> g2;
     std::vector<std::vector<ColDesc>> rcols(nitems);
     for (int i = 0; i < nitems; ++i) {

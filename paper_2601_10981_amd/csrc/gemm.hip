@@ -31,7 +31,7 @@ __device__ __forceinline__ bool col_valid(const ColDesc& c) {
 
 template <typename In>
 __device__ __forceinline__ In load_col(const void* p, int f32, long long row) {
-  return f32 ? (In)((const float*)p)[row] : (In)((const double*)p)[row];
+  return f32 ? (In)gptr((const float*)p)[row] : (In)gptr((const double*)p)[row];
 }
 
 // ---------------------------------------------------------------------------
@@ -124,23 +124,37 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   const long long r_end = min(d.nrows, r_begin + (long long)d.chunk_rows);
   int since_flush = 0;
   for (long long r0 = r_begin + wave * 16; r0 < r_end; r0 += 64) {
-    In v[NT][4];
+    // wide tile sets hold one row per column at a time (register pressure);
+    // narrow ones load the lane's four consecutive rows at once
+    constexpr int UL = (NT > 5) ? 1 : 4;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int u0 = 0; u0 < 4; u0 += UL) {
+      In v[NT][UL];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const long long row = r0 + 4 * kq + u;
-        v[t][u] = (cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+      for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const long long row = r0 + 4 * kq + u0 + u;
+          v[t][u] = (cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+        }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < UL; ++u) {
+        // pairs in PairList order, as nested compile-time loops so every
+        // register index is a constant after unrolling
 #pragma unroll
-      for (int p = 0; p < P; ++p) {
-        if constexpr (F32)
-          acc32[p] = M::op(v[PL::a(p)][u], v[PL::b(p)][u], acc32[p]);
-        else
-          acc[p] = M::op(v[PL::a(p)][u], v[PL::b(p)][u], acc[p]);
+        for (int ia = 0; ia < NA; ++ia) {
+#pragma unroll
+          for (int jb = 0; jb < (NB == 0 ? NA : NB); ++jb) {
+            if (NB == 0 && jb < ia) continue;
+            const int p = (NB == 0) ? ia * NA - ia * (ia - 1) / 2 + (jb - ia) : ia * NB + jb;
+            const int ib = (NB == 0) ? jb : NA + jb;
+            if constexpr (F32)
+              acc32[p] = M::op(v[ia][u], v[ib][u], acc32[p]);
+            else
+              acc[p] = M::op(v[ia][u], v[ib][u], acc[p]);
+          }
+        }
       }
     }
     if constexpr (F32) {
@@ -166,7 +180,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   const int tv = threadIdx.x >> 6, tl = threadIdx.x & 63;
   const int e_row = F32 ? 4 * (tl >> 4) + tv : (tl >> 4) + 4 * tv;
   const int e_out = e_row * 16 + (tl & 15);
-  double* part = d.partial + (long long)chunk * P * 256;
+  PR_GLOBAL double* part = gptr(d.partial) + (long long)chunk * P * 256;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
 #pragma unroll
@@ -181,32 +195,38 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 
 // Fixed-order reduction of the chunk partials, scaled, into the output
 // matrix (row = A column, column = B column; the symmetric form mirrors).
+// 1024 threads per (pair, item): thread group q = t / 256 sums the chunks
+// c = q, q + 4, ... of element t % 256, then the four sums are combined as
+// (s0 + s1) + (s2 + s3).
 template <int NA, int NB>
-__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
+__global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
   using PL = PairList<NA, NB>;
   constexpr int P = PL::P;
+  __shared__ double red[4][256];
   const GemmDesc& d = descs[blockIdx.y];
   const int p = blockIdx.x;
-  const int e = threadIdx.x;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  const double* src = d.partial + (long long)p * 256 + e;
+  const int e = threadIdx.x & 255, q = threadIdx.x >> 8;
+  const PR_GLOBAL double* src = gptr(d.partial) + (long long)p * 256 + e;
   const long long stride = (long long)P * 256;
-  int c = 0;
-  for (; c + 4 <= d.nchunks; c += 4) {
-    s0 += src[(long long)(c + 0) * stride];
-    s1 += src[(long long)(c + 1) * stride];
-    s2 += src[(long long)(c + 2) * stride];
-    s3 += src[(long long)(c + 3) * stride];
+  double a0 = 0, a1 = 0;
+  int c = q;
+  for (; c + 4 < d.nchunks; c += 8) {
+    a0 += src[(long long)c * stride];
+    a1 += src[(long long)(c + 4) * stride];
   }
-  for (; c < d.nchunks; ++c) s0 += src[(long long)c * stride];
-  const double s = d.scale * ((s0 + s1) + (s2 + s3));
+  if (c < d.nchunks) a0 += src[(long long)c * stride];
+  red[q][e] = a0 + a1;
+  __syncthreads();
+  if (q != 0) return;
+  const double sum = d.scale * ((red[0][e] + red[1][e]) + (red[2][e] + red[3][e]));
   const int row = e >> 4, col = e & 15;
   const int ta = PL::a(p), tb = PL::b(p);
+  PR_GLOBAL double* out = gptr(d.out);
   if (NB == 0) {
-    d.out[(long long)(ta * 16 + row) * d.ld + tb * 16 + col] = s;
-    if (ta != tb) d.out[(long long)(tb * 16 + col) * d.ld + ta * 16 + row] = s;
+    out[(long long)(ta * 16 + row) * d.ld + tb * 16 + col] = sum;
+    if (ta != tb) out[(long long)(tb * 16 + col) * d.ld + ta * 16 + row] = sum;
   } else {
-    d.out[(long long)(ta * 16 + row) * d.ld + (tb - NA) * 16 + col] = s;
+    out[(long long)(ta * 16 + row) * d.ld + (tb - NA) * 16 + col] = sum;
   }
 }
 
@@ -222,7 +242,7 @@ static void launch_gemm_shape(const GemmDesc* d, int nd, long long total_wg, boo
 
 template <int NA, int NB>
 static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P, nd), dim3(256), 0, s, d);
+  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P, nd), dim3(1024), 0, s, d);
 }
 
 #define PR_GEMM_SHAPES(X) \
@@ -259,36 +279,82 @@ void launch_gemm_reduce(const GemmDesc* d, int nd, int na, int nb, hipStream_t s
 // out[:, j] = alpha * sum_c in_c * C[c][j] (+ add for j = 0); j < nout, and
 // columns j >= *out_mptr are zero. Rows are private to a thread, so the
 // output may alias the input columns (all reads of a row precede its writes).
+// The column descriptors, their validity (which may depend on a device rank)
+// and C are staged in LDS once per workgroup; each thread owns two rows.
 constexpr int kTsmmMaxOut = 32;
+constexpr int kTsmmMaxIn = 64;
+constexpr int kTsmmRowsPerWg = 512;
 
 __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs, int nd) {
+  __shared__ const void* sp[kTsmmMaxIn];
+  __shared__ int sf[kTsmmMaxIn];
+  __shared__ int sv[kTsmmMaxIn];
+  __shared__ double sC[kTsmmMaxIn * kTsmmMaxOut];
+  __shared__ int s_mo;
   const long long w = blockIdx.x;
   const int f = find_wg(descs, nd, w);
   const TsmmDesc& d = descs[f];
-  const long long row = (w - d.wg_begin) * 256 + threadIdx.x;
-  if (row >= d.nrows) return;
-  double acc[kTsmmMaxOut];
+  const int nin = d.nin, nout = d.nout;
+  if (threadIdx.x < nin) {
+    const ColDesc cd = d.in[threadIdx.x];
+    sp[threadIdx.x] = cd.ptr;
+    sf[threadIdx.x] = cd.f32;
+    sv[threadIdx.x] = col_valid(cd) ? 1 : 0;
+  }
+  for (int e = threadIdx.x; e < nin * nout; e += 256)
+    sC[e] = gptr(d.C)[(long long)(e / nout) * d.ldc + (e % nout)];
+  if (threadIdx.x == 0) s_mo = d.out_mptr ? *d.out_mptr : nout;
+  __syncthreads();
+  const long long r0 = (w - d.wg_begin) * kTsmmRowsPerWg + threadIdx.x;
+  const long long r1 = r0 + 256;
+  const bool v0 = r0 < d.nrows, v1 = r1 < d.nrows;
+  if (!v0) return;
+  const long long q1 = v1 ? r1 : r0;
+  double a0[kTsmmMaxOut], a1[kTsmmMaxOut];
 #pragma unroll
-  for (int j = 0; j < kTsmmMaxOut; ++j) acc[j] = 0.0;
-  const int nout = d.nout;
-  for (int c = 0; c < d.nin; ++c) {
-    const ColDesc cd = d.in[c];
-    if (!col_valid(cd)) continue;
-    const double x = load_col<double>(cd.ptr, cd.f32, row);
-    const double* Cr = d.C + (long long)c * d.ldc;
+  for (int j = 0; j < kTsmmMaxOut; ++j) a0[j] = a1[j] = 0.0;
+  for (int c = 0; c < nin; ++c) {
+    if (!sv[c]) continue;
+    double x0, x1;
+    if (sf[c]) {
+      const PR_GLOBAL float* p = gptr((const float*)sp[c]);
+      x0 = p[r0];
+      x1 = p[q1];
+    } else {
+      const PR_GLOBAL double* p = gptr((const double*)sp[c]);
+      x0 = p[r0];
+      x1 = p[q1];
+    }
+    const double* Cr = sC + c * nout;
 #pragma unroll
     for (int j = 0; j < kTsmmMaxOut; ++j)
-      if (j < nout) acc[j] += x * Cr[j];
+      if (j < nout) {
+        a0[j] += x0 * Cr[j];
+        a1[j] += x1 * Cr[j];
+      }
   }
-  const int mo = d.out_mptr ? *d.out_mptr : nout;
+  const int mo = s_mo;
   const long long ng = d.nrows;
+  const PR_GLOBAL double* add = d.add ? gptr(d.add) : nullptr;
+  const double ad0 = add ? add[r0] : 0.0, ad1 = add ? add[q1] : 0.0;
 #pragma unroll
   for (int j = 0; j < kTsmmMaxOut; ++j) {
     if (j < nout) {
-      double v = (j < mo) ? d.alpha * acc[j] : 0.0;
-      if (j == 0 && d.add != nullptr) v += d.add[row];
-      if (d.out_f32) ((float*)d.out)[(long long)j * ng + row] = (float)v;
-      else ((double*)d.out)[(long long)j * ng + row] = v;
+      double y0 = (j < mo) ? d.alpha * a0[j] : 0.0;
+      double y1 = (j < mo) ? d.alpha * a1[j] : 0.0;
+      if (j == 0) {
+        y0 += ad0;
+        y1 += ad1;
+      }
+      if (d.out_f32) {
+        PR_GLOBAL float* o = gptr((float*)d.out) + (long long)j * ng;
+        o[r0] = (float)y0;
+        if (v1) o[r1] = (float)y1;
+      } else {
+        PR_GLOBAL double* o = gptr((double*)d.out) + (long long)j * ng;
+        o[r0] = y0;
+        if (v1) o[r1] = y1;
+      }
     }
   }
 }
@@ -309,32 +375,53 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __global__ __launch_bounds__(256) void k_correct(const CorrectDesc* __restrict__ descs, int nd) {
   __shared__ double red[4][4];
+  __shared__ const void* sp[kTsmmMaxOut + 1];
+  __shared__ int sf[kTsmmMaxOut + 1];
+  __shared__ double sc[kTsmmMaxOut + 1];
+  __shared__ int s_np;
   const long long w = blockIdx.x;
   const int f = find_wg(descs, nd, w);
   const CorrectDesc& d = descs[f];
+  if (threadIdx.x == 0) {
+    // compact the valid basis columns (their coefficients are read once)
+    int k = 0;
+    for (int c = 0; c < d.npsi; ++c) {
+      const ColDesc cd = d.psi[c];
+      if (!col_valid(cd)) continue;
+      sp[k] = cd.ptr;
+      sf[k] = cd.f32;
+      sc[k] = d.coef[c];
+      ++k;
+    }
+    s_np = k;
+  }
+  __syncthreads();
+  const int np = s_np;
   const long long wl = w - d.wg_begin;
   const long long rows_per_wg = (d.nrows + d.nwg - 1) / d.nwg;
   const long long r0 = wl * rows_per_wg;
   const long long r1 = min(d.nrows, r0 + rows_per_wg);
+  const PR_GLOBAL double* prev = d.prev ? gptr(d.prev) : nullptr;
+  const PR_GLOBAL double* ref = d.ref ? gptr(d.ref) : nullptr;
+  PR_GLOBAL double* out = gptr(d.out);
   double s_jump = 0, s_u = 0, s_err = 0, s_ref = 0;
   for (long long row = r0 + threadIdx.x; row < r1; row += 256) {
     double v = 0.0;
-    if (d.fine) v = d.fine_f32 ? (double)((const float*)d.fine)[row] : ((const double*)d.fine)[row];
+    if (d.fine) v = d.fine_f32 ? (double)gptr((const float*)d.fine)[row] : gptr((const double*)d.fine)[row];
     double g = 0.0;
-    for (int c = 0; c < d.npsi; ++c) {
-      const ColDesc cd = d.psi[c];
-      if (!col_valid(cd)) continue;
-      g += d.coef[c] * load_col<double>(cd.ptr, cd.f32, row);
+    for (int c = 0; c < np; ++c) {
+      const double x = sf[c] ? (double)gptr((const float*)sp[c])[row] : gptr((const double*)sp[c])[row];
+      g += sc[c] * x;
     }
     v += g;
-    d.out[row] = v;
+    out[row] = v;
     s_u += v * v;
-    if (d.prev) {
-      const double dj = v - d.prev[row];
+    if (prev) {
+      const double dj = v - prev[row];
       s_jump += dj * dj;
     }
-    if (d.ref) {
-      const double r = d.ref[row];
+    if (ref) {
+      const double r = ref[row];
       const double de = v - r;
       s_err += de * de;
       s_ref += r * r;
@@ -354,7 +441,7 @@ __global__ __launch_bounds__(256) void k_correct(const CorrectDesc* __restrict__
   __syncthreads();
   if (threadIdx.x < 4) {
     const int i = threadIdx.x;
-    d.partial[wl * 4 + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+    gptr(d.partial)[wl * 4 + i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
   }
 }
 

@@ -40,6 +40,7 @@ constexpr double kTauRankF64 = 1e-13;
 constexpr double kTauRankF32 = 1e-6;
 constexpr double kTauAug = 1e-12;
 constexpr double kDropPivot = 1e-8;
+constexpr int kCholQRPasses = 1;
 constexpr double kGuard = 2.5;
 constexpr double kStabRK4 = 2.6;
 

@@ -45,11 +45,11 @@ __device__ __forceinline__ int find_desc(const D* d, int nd, long long t) {
 // Evaluate (L in) along x for one (j, k) column over planes [x0, x1),
 // calling emit(x, p, Lv) for each plane. Periodic wrap on every axis.
 template <typename T, typename Emit>
-__device__ __forceinline__ void march_L(const Geom& g, const T* __restrict__ in, int j, int k,
-                                        int x0, int x1, Emit emit) {
+__device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __restrict__ in, int j,
+                                        int k, int x0, int x1, Emit emit) {
   const int n = g.n;
   const long long plane = (long long)n * n;
-  const T* tab = tab_of<T>(g);
+  const PR_GLOBAL T* tab = gptr(tab_of<T>(g));
   const T clap = (T)g.c_lap;
   const int jm = (j == 0) ? n - 1 : j - 1, jp = (j == n - 1) ? 0 : j + 1;
   const int km = (k == 0) ? n - 1 : k - 1, kp = (k == n - 1) ? 0 : k + 1;
@@ -103,7 +103,10 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
   constexpr int RY = TY + 2 * H, RZ = TZ + 2 * H;
   constexpr int NR = RY * RZ;
   constexpr int SL = (NR + NT - 1) / NT;
-  __shared__ T lds[4][NR];
+  // two sets of the four stage planes, alternating per march step, so one
+  // barrier per step suffices (a set is rewritten two steps later, after
+  // every thread has passed the intermediate barrier)
+  __shared__ T lds[2][4][NR];
   // v_y(x) and v_z(x) parts of the velocity for the chunk's planes
   // x0 - 6 .. x0 + kMaxChunk + 3
   __shared__ T vxt[2][kMaxChunk + 10];
@@ -192,18 +195,20 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
   }
 
   // march step tt: w1 at plane tt + 3, w2 at tt + 2, w3 at tt + 1, y_new at tt
+  __syncthreads();   // vxt visible
   for (int tt = x0 - 6; tt < x1; ++tt) {
     const long long p5 = (long long)wrapi(tt + 5, n) * plane;
+    T (*pl)[NR] = lds[(tt - x0) & 1];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const int c = threadIdx.x + s * NT;
       Y[s][4] = Yn[s];
       Yn[s] = src[p5 + off[s]];   // consumed next step
       if (c < NR) {
-        lds[0][c] = Y[s][3];
-        lds[1][c] = W1[s][1];
-        lds[2][c] = W2[s][1];
-        lds[3][c] = W3[s][1];
+        pl[0][c] = Y[s][3];
+        pl[1][c] = W1[s][1];
+        pl[2][c] = W2[s][1];
+        pl[3][c] = W3[s][1];
       }
     }
     __syncthreads();
@@ -219,23 +224,22 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
       const int c = threadIdx.x + s * NT;
       const int lv = lev[s];
       if (lv <= 3)
-        W1[s][2] = Y[s][3] + c1 * lop<T, RZ>(Y[s][2], Y[s][3], Y[s][4], lds[0], c, clap, vx[s],
+        W1[s][2] = Y[s][3] + c1 * lop<T, RZ>(Y[s][2], Y[s][3], Y[s][4], pl[0], c, clap, vx[s],
                                              vy_a + vyz[s], vz_a + vzy[s]);
       if (s2 && lv <= 2)
-        W2[s][2] = Y[s][2] + c2 * lop<T, RZ>(W1[s][0], W1[s][1], W1[s][2], lds[1], c, clap, vx[s],
+        W2[s][2] = Y[s][2] + c2 * lop<T, RZ>(W1[s][0], W1[s][1], W1[s][2], pl[1], c, clap, vx[s],
                                              vy_b + vyz[s], vz_b + vzy[s]);
       if (s3 && lv <= 1)
-        W3[s][2] = Y[s][1] + c3 * lop<T, RZ>(W2[s][0], W2[s][1], W2[s][2], lds[2], c, clap, vx[s],
+        W3[s][2] = Y[s][1] + c3 * lop<T, RZ>(W2[s][0], W2[s][1], W2[s][2], pl[2], c, clap, vx[s],
                                              vy_c + vyz[s], vz_c + vzy[s]);
       if (s4 && outp[s]) {
-        const T yn = Y[s][0] + c4 * lop<T, RZ>(W3[s][0], W3[s][1], W3[s][2], lds[3], c, clap,
+        const T yn = Y[s][0] + c4 * lop<T, RZ>(W3[s][0], W3[s][1], W3[s][2], pl[3], c, clap,
                                                vx[s], vy_d + vyz[s], vz_d + vzy[s]);
         const long long gi = (long long)xd * plane + off[s];
         dst[gi] = yn;
         if (snap) snap[gi] = yn;
       }
     }
-    __syncthreads();
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
 #pragma unroll
@@ -304,8 +308,8 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   const int j = q / n, k = q - (q / n) * n;
   const int x0 = tx * kChunkX, x1 = min(n, x0 + kChunkX);
   const long long ng = (long long)n * n * n;
-  const T* in = d.in + (long long)col * ng;
-  T* out = d.out + (long long)col * ng;
+  const PR_GLOBAL T* in = gptr(d.in) + (long long)col * ng;
+  PR_GLOBAL T* out = gptr(d.out) + (long long)col * ng;
   const bool valid = (d.mptr == nullptr) || (col < *d.mptr);
   if (!valid) {
     const long long plane = (long long)n * n;
