@@ -199,7 +199,11 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  * [0, T] is split into N subintervals of DeltaT = T / N; subinterval 0 is the
  * warm-up window [0, T_0] (T_0 = DeltaT) whose fine solve gives G_0 (Case I);
  * the parareal partition of [T_0, T] has N - 1 subintervals.
- *   fine steps    n_f = ceil(DeltaT / dt - 1e-9), delta_t = DeltaT / n_f
+ *   fine steps    n_f = ceil(DeltaT / dt - 1e-9), delta_t = DeltaT / n_f;
+ *                 dt <= 0 requests min(2e-3, 1.3 / rho) with the bound
+ *                 rho = 12 kappa / h^2 + sum_d max|v_d| / h (max|v_d| from
+ *                 the flow's coefficients: ABC |A|+|C|, |B|+|A|, |C|+|B|;
+ *                 Kolmogorov |amplitude|; uniform |c_d|)
  *   snapshots     every dM steps (0: ceil(n_f / 16))
  *   coarse steps  n_c = max(1, ceil(n_f / coarse_ratio)) (then the guard)
  *   POD           gamma1 (k = 0), gamma2 (per subinterval), gamma3 (local
@@ -249,9 +253,58 @@ pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,
                             const pr_parareal_opts* opts, const double* u0,
                             double* U_out, pr_report* report, void* stream);
 
-/* Device bytes pr_parareal_solve needs for (prob, opts) (pure host function). */
+/* Device bytes pr_parareal_solve needs for (prob, opts) with every wave at
+ * full width (pure host function); a solve under a smaller budget runs its
+ * fine solves and local POD in narrower waves. */
 pr_status pr_footprint(const pr_grid_problem* prob, const pr_parareal_opts* opts,
                        size_t* bytes);
+
+/* ---------------------------------------------------------------------------
+ * Incremental solves for serving: the iteration of formula4 / Algorithm 2
+ * split at its stopping test, so that one host loop can advance many
+ * independent solves (different problems, sizes and precisions) together.
+ *
+ * pr_solve_begin   validates (prob, opts) as pr_parareal_solve does, allocates
+ *                  the solve's own device memory on the context's budget
+ *                  (PR_ENOMEM when it does not fit: admission control), copies
+ *                  u0 (device, N_g doubles) and runs k = 0 (Algorithm 2's
+ *                  initial POD basis and coarse sweep); synchronises `stream`.
+ *                  opts->U_ref, when given, must stay alive until
+ *                  pr_solve_end. On success *out is a new handle.
+ * pr_solve_step_batch  one parareal iteration of every handle in
+ *                  solves[0..count) that has not stopped: the fine solves
+ *                  and per-subinterval POD of all of them share launches,
+ *                  the sweeps run one solve after another; one
+ *                  synchronisation of `stream` at the end. done[i] (host,
+ *                  nullable) = 1 when handle i has stopped (tol reached,
+ *                  finite termination, max_iter or a NaN/Inf jump). Each
+ *                  solve's iterates are bitwise those of pr_parareal_solve
+ *                  whatever else is in the batch. A handle may appear once
+ *                  per call.
+ * pr_solve_state   enqueues a copy of the latest iterate's state at
+ *                  t = j DeltaT (0 <= j <= N; j = 0 is u0) into out (device,
+ *                  N_g doubles).
+ * pr_solve_done    1 when the handle has stopped (or is NULL).
+ * pr_solve_bytes   device bytes the handle owns.
+ * pr_solve_end     writes the last iterate to U_out (device, (N + 1) x N_g
+ *                  doubles, nullable) and the report (nullable, as for
+ *                  pr_parareal_solve), frees the handle (also on error) and
+ *                  returns PR_OK, PR_ENOTCONV or PR_ENUMERIC as
+ *                  pr_parareal_solve would.
+ * Handles belong to the context that made them; end every handle before
+ * destroying the context. */
+typedef struct pr_solve pr_solve;
+pr_status pr_solve_begin(pr_ctx* ctx, const pr_grid_problem* prob,
+                         const pr_parareal_opts* opts, const double* u0,
+                         pr_solve** out, void* stream);
+pr_status pr_solve_step_batch(pr_ctx* ctx, int count, pr_solve* const* solves,
+                              int* done, void* stream);
+pr_status pr_solve_state(pr_ctx* ctx, const pr_solve* solve, int j, double* out,
+                         void* stream);
+int pr_solve_done(const pr_solve* solve);
+size_t pr_solve_bytes(const pr_solve* solve);
+pr_status pr_solve_end(pr_ctx* ctx, pr_solve* solve, double* U_out,
+                       pr_report* report, void* stream);
 
 #ifdef __cplusplus
 }

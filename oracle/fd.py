@@ -97,6 +97,25 @@ def rk4_step(op: Operator, phi: np.ndarray, dt: float) -> np.ndarray:
     return phi + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
 
 
+def velocity_bound(flow: int, fp) -> float:
+    """sum_d max|v_d| from the flow's coefficients (not from grid samples):
+    ABC (|A|+|C|) + (|B|+|A|) + (|C|+|B|), Kolmogorov |a|, uniform sum |c_d|."""
+    if flow == 1:
+        A, B, C = (abs(float(v)) for v in fp)
+        return (A + C) + (B + A) + (C + B)
+    if flow == 2:
+        return abs(float(fp[0]))
+    return abs(float(fp[0])) + abs(float(fp[1])) + abs(float(fp[2]))
+
+
+def auto_dt(prob) -> float:
+    """Requested fine step when none is given: half of RK4's stability radius
+    2.6 over rho = 12 kappa / h^2 + sum_d max|v_d| / h, at most 2e-3."""
+    h = prob.L / prob.n
+    rho = 12.0 * prob.kappa / (h * h) + velocity_bound(prob.flow, prob.fp) / h
+    return min(2e-3, 0.5 * 2.6 / rho)
+
+
 def steps_per_subinterval(dT_sub: float, dt_req: float):
     """Reading of the step count: n_f = ceil(DeltaT / dt_req - 1e-9) and the
     fine step delta_t = DeltaT / n_f, never larger than the requested step."""

@@ -59,6 +59,11 @@ def _norm_m(x: np.ndarray, h3: float) -> float:
     return math.sqrt(h3 * float(np.vdot(x, x)))
 
 
+def requested_dt(prob, opts) -> float:
+    """opts.dt, or the automatic rule when it is <= 0."""
+    return opts.dt if opts.dt > 0 else fd.auto_dt(prob)
+
+
 def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
           tau_r: float = P.TAU_R_F64, keep_history: bool = False) -> Result:
     op = fd.Operator.of(prob)
@@ -66,7 +71,7 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     h3 = op.h ** 3
     N = opts.N
     dT_sub = opts.T / N
-    n_f, dt = fd.steps_per_subinterval(dT_sub, opts.dt)
+    n_f, dt = fd.steps_per_subinterval(dT_sub, requested_dt(prob, opts))
     dM = fd.snapshot_stride(n_f, opts.dM)
     Np = N - 1
     n_c0 = C.coarse_steps(n_f, opts.coarse_ratio)
@@ -194,5 +199,5 @@ def reference(prob, opts, u0: np.ndarray) -> List[np.ndarray]:
     """Serial fine solution at t = j DeltaT, j = 0..N (eq. error's U_n)."""
     op = fd.Operator.of(prob)
     out = fd.serial_fine(op, np.asarray(u0, dtype=np.float64).reshape(prob.n, prob.n, prob.n),
-                         opts.T / opts.N, opts.N, opts.dt)
+                         opts.T / opts.N, opts.N, requested_dt(prob, opts))
     return [o.reshape(-1) for o in out]

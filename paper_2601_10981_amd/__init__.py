@@ -18,7 +18,9 @@ from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
 
 __all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_gram", "pr_pod_build",
-           "pr_coarse_propagate", "pr_parareal_solve", "pr_footprint", "costmodel"]
+           "pr_coarse_propagate", "pr_parareal_solve", "pr_footprint", "pr_solve_begin",
+           "pr_solve_step_batch", "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end",
+           "SolveHandle", "costmodel"]
 
 
 class PrError(RuntimeError):
@@ -287,6 +289,38 @@ class Report:
     seconds: float
 
 
+class _ReportBuffers:
+    """Host arrays a pr_report points into, sized for at most kmax iterations."""
+
+    def __init__(self, N: int, max_iter: int):
+        self.N = N
+        self.n_sub = max(N - 1, 1)
+        kmax = max_iter if max_iter > 0 else N - 1
+        kmax = max(0, min(kmax, N - 1))
+        cap = kmax + 1
+        self.jump = (ctypes.c_double * cap)()
+        self.err = (ctypes.c_double * cap)()
+        self.t_iter = (ctypes.c_double * cap)()
+        self.ranks = (ctypes.c_int * (cap * self.n_sub))()
+        self.rep = L.pr_report()
+        self.rep.jump = self.jump
+        self.rep.err = self.err
+        self.rep.t_iter = self.t_iter
+        self.rep.ranks = self.ranks
+
+    def report(self, st: int, has_ref: bool) -> "Report":
+        rep, k, n_sub, N = self.rep, self.rep.iters, self.n_sub, self.N
+        return Report(status=st, iters=k, converged=bool(rep.converged), n_f=rep.n_f, dM=rep.dM,
+                      n_s=rep.n_s, n_c=rep.n_c, n_sub=rep.n_sub, m0=rep.m0,
+                      jump=[self.jump[i] for i in range(k)],
+                      err=[self.err[i] for i in range(k + 1)] if has_ref else [],
+                      t_iter=[self.t_iter[i] for i in range(k + 1)],
+                      ranks=[[self.ranks[kk * n_sub + n] for n in range(kk, N - 1)]
+                             for kk in range(1, k + 1)],
+                      t_phase=dict(zip("FCUAG", list(rep.t_phase))),
+                      fine_updates=rep.fine_updates, seconds=rep.seconds)
+
+
 def pr_parareal_solve(ctx: Context, prob: L.pr_grid_problem, opts, u0, U_out=None,
                       U_ref=None, stream=None, allow_notconv: bool = True):
     """Whole solve. Returns (U_out of shape (N + 1, N_g), Report)."""
@@ -300,33 +334,106 @@ def pr_parareal_solve(ctx: Context, prob: L.pr_grid_problem, opts, u0, U_out=Non
     if U_ref is not None:
         _check_dev(U_ref, torch.float64, (N + 1) * ng, "U_ref")
     o = opts_struct(opts, U_ref)
-    n_sub = max(N - 1, 1)
-    kmax = (int(opts.max_iter) if getattr(opts, "max_iter", 0) > 0 else N - 1)
-    kmax = max(0, min(kmax, N - 1))
-    cap = kmax + 1
-    jump = (ctypes.c_double * cap)()
-    err = (ctypes.c_double * cap)()
-    t_iter = (ctypes.c_double * cap)()
-    ranks = (ctypes.c_int * (cap * n_sub))()
-    rep = L.pr_report()
-    rep.jump = jump
-    rep.err = err
-    rep.t_iter = t_iter
-    rep.ranks = ranks
+    rb = _ReportBuffers(N, int(getattr(opts, "max_iter", 0)))
     st = ctx.lib.pr_parareal_solve(ctx.h, ctypes.byref(prob), ctypes.byref(o), _ptr(u0),
-                                   _ptr(U_out), ctypes.byref(rep), _stream(stream))
+                                   _ptr(U_out), ctypes.byref(rb.rep), _stream(stream))
     if st != L.PR_OK and not (allow_notconv and st == -5):
         raise PrError(st, ctx.error())
-    k = rep.iters
-    r = Report(status=st, iters=k, converged=bool(rep.converged), n_f=rep.n_f, dM=rep.dM,
-               n_s=rep.n_s, n_c=rep.n_c, n_sub=rep.n_sub, m0=rep.m0,
-               jump=[jump[i] for i in range(k)],
-               err=[err[i] for i in range(k + 1)] if U_ref is not None else [],
-               t_iter=[t_iter[i] for i in range(k + 1)],
-               ranks=[[ranks[kk * n_sub + n] for n in range(kk, N - 1)] for kk in range(1, k + 1)],
-               t_phase=dict(zip("FCUAG", list(rep.t_phase))),
-               fine_updates=rep.fine_updates, seconds=rep.seconds)
-    return U_out, r
+    return U_out, rb.report(st, U_ref is not None)
+
+
+class SolveHandle:
+    """An incremental solve (pr_solve_begin .. pr_solve_end). Keeps U_ref
+    alive for the library, which reads it on every iteration."""
+
+    def __init__(self, ctx: Context, h: int, prob, opts, U_ref):
+        self.ctx = ctx
+        self.h = h
+        self.prob = prob
+        self.opts = opts
+        self.U_ref = U_ref
+
+    @property
+    def done(self) -> bool:
+        return bool(self.ctx.lib.pr_solve_done(ctypes.c_void_p(self.h)))
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.ctx.lib.pr_solve_bytes(ctypes.c_void_p(self.h)))
+
+
+def pr_solve_begin(ctx: Context, prob: L.pr_grid_problem, opts, u0, U_ref=None,
+                   stream=None) -> SolveHandle:
+    """Admit a solve and run its k = 0 step. Raises PrError (PR_ENOMEM when
+    the context's budget cannot hold it)."""
+    torch = _torch()
+    ng = prob.n ** 3
+    N = int(opts.N)
+    _check_dev(u0, torch.float64, ng, "u0")
+    if U_ref is not None:
+        _check_dev(U_ref, torch.float64, (N + 1) * ng, "U_ref")
+    o = opts_struct(opts, U_ref)
+    out = ctypes.c_void_p()
+    st = ctx.lib.pr_solve_begin(ctx.h, ctypes.byref(prob), ctypes.byref(o), _ptr(u0),
+                                ctypes.byref(out), _stream(stream))
+    if st != L.PR_OK:
+        raise PrError(st, ctx.error())
+    return SolveHandle(ctx, out.value, prob, opts, U_ref)
+
+
+def pr_solve_step_batch(ctx: Context, handles, stream=None) -> List[bool]:
+    """One parareal iteration of every unfinished handle; returns done flags."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * max(n, 1))(*[h.h for h in handles])
+    done = (ctypes.c_int * max(n, 1))()
+    st = ctx.lib.pr_solve_step_batch(ctx.h, n, arr, done, _stream(stream))
+    if st != L.PR_OK:
+        raise PrError(st, ctx.error())
+    return [bool(done[i]) for i in range(n)]
+
+
+def pr_solve_state(ctx: Context, handle: SolveHandle, j: int, out=None, stream=None):
+    """Copy of the latest iterate's state at t = j DeltaT (device tensor)."""
+    torch = _torch()
+    ng = handle.prob.n ** 3
+    if out is None:
+        out = torch.empty(ng, dtype=torch.float64, device="cuda")
+    _check_dev(out, torch.float64, ng, "out")
+    st = ctx.lib.pr_solve_state(ctx.h, ctypes.c_void_p(handle.h), int(j), _ptr(out),
+                                _stream(stream))
+    if st != L.PR_OK:
+        raise PrError(st, ctx.error())
+    return out
+
+
+def pr_solve_done(handle: SolveHandle) -> bool:
+    return handle.done
+
+
+def pr_solve_bytes(handle: SolveHandle) -> int:
+    return handle.nbytes
+
+
+def pr_solve_end(ctx: Context, handle: SolveHandle, U_out=None, stream=None,
+                 allow_notconv: bool = True):
+    """Finish a handle: (U_out of shape (N + 1, N_g), Report); U_out=False
+    copies nothing out (returns None). The handle is freed whatever the
+    status."""
+    torch = _torch()
+    N = int(handle.opts.N)
+    ng = handle.prob.n ** 3
+    if U_out is None:
+        U_out = torch.empty((N + 1, ng), dtype=torch.float64, device="cuda")
+    if U_out is not False:
+        _check_dev(U_out, torch.float64, (N + 1) * ng, "U_out")
+    rb = _ReportBuffers(N, int(getattr(handle.opts, "max_iter", 0)))
+    h = handle.h
+    handle.h = None
+    st = ctx.lib.pr_solve_end(ctx.h, ctypes.c_void_p(h), None if U_out is False else _ptr(U_out),
+                              ctypes.byref(rb.rep), _stream(stream))
+    if st != L.PR_OK and not (allow_notconv and st == -5):
+        raise PrError(st, ctx.error())
+    return (None if U_out is False else U_out), rb.report(st, handle.U_ref is not None)
 
 
 def pr_footprint(prob: L.pr_grid_problem, opts) -> int:

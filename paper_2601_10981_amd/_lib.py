@@ -59,7 +59,8 @@ class pr_report(Structure):
 
 EXPORTS = ["pr_ctx_create", "pr_ctx_destroy", "pr_last_error", "pr_ctx_scratch_bytes",
            "pr_fine_propagate", "pr_gram", "pr_pod_build", "pr_coarse_propagate",
-           "pr_parareal_solve", "pr_footprint"]
+           "pr_parareal_solve", "pr_footprint", "pr_solve_begin", "pr_solve_step_batch",
+           "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end"]
 
 _lib = None
 
@@ -105,5 +106,19 @@ def load(path: str = LIB_PATH):
     lib.pr_footprint.argtypes = [POINTER(pr_grid_problem), POINTER(pr_parareal_opts),
                                  POINTER(c_size_t)]
     lib.pr_footprint.restype = c_int
+    lib.pr_solve_begin.argtypes = [c_void_p, POINTER(pr_grid_problem), POINTER(pr_parareal_opts),
+                                   c_void_p, POINTER(c_void_p), c_void_p]
+    lib.pr_solve_begin.restype = c_int
+    lib.pr_solve_step_batch.argtypes = [c_void_p, c_int, POINTER(c_void_p), POINTER(c_int),
+                                        c_void_p]
+    lib.pr_solve_step_batch.restype = c_int
+    lib.pr_solve_state.argtypes = [c_void_p, c_void_p, c_int, c_void_p, c_void_p]
+    lib.pr_solve_state.restype = c_int
+    lib.pr_solve_done.argtypes = [c_void_p]
+    lib.pr_solve_done.restype = c_int
+    lib.pr_solve_bytes.argtypes = [c_void_p]
+    lib.pr_solve_bytes.restype = c_size_t
+    lib.pr_solve_end.argtypes = [c_void_p, c_void_p, c_void_p, POINTER(pr_report), c_void_p]
+    lib.pr_solve_end.restype = c_int
     _lib = lib
     return lib

@@ -13,6 +13,37 @@ namespace pr {
 
 // ---------------------------------------------------------------------------
 // scratch memory
+
+// Free idle pooled blocks, largest first, until `bytes` more fit the budget.
+static void make_room(pr_ctx* c, size_t bytes) {
+  while (c->used + bytes > c->budget && !c->pool.empty()) {
+    auto it = std::prev(c->pool.end());
+    PR_HIP(hipFree(it->second));
+    c->used -= it->first;
+    c->pool.erase(it);
+  }
+}
+
+void* pool_get(pr_ctx* c, size_t bytes, size_t* got) {
+  bytes = std::max<size_t>(256, (bytes + 4095) & ~size_t(4095));
+  auto it = c->pool.lower_bound(bytes);
+  if (it != c->pool.end() && it->first <= bytes + bytes / 8) {
+    void* p = it->second;
+    *got = it->first;
+    c->pool.erase(it);
+    return p;
+  }
+  make_room(c, bytes);
+  if (c->used + bytes > c->budget) fail(PR_ENOMEM, "solve memory exceeds the HBM budget");
+  void* p = nullptr;
+  PR_HIP(hipMalloc(&p, bytes));
+  c->used += bytes;
+  *got = bytes;
+  return p;
+}
+
+void pool_put(pr_ctx* c, void* p, size_t bytes) { c->pool.insert({bytes, p}); }
+
 void* scratch(pr_ctx* c, const std::string& name, size_t bytes) {
   bytes = std::max<size_t>(bytes, 256);
   bytes = (bytes + 4095) & ~size_t(4095);
@@ -24,6 +55,7 @@ void* scratch(pr_ctx* c, const std::string& name, size_t bytes) {
     c->used -= b.bytes;
     b = pr_ctx::Buf{};
   }
+  make_room(c, bytes);
   if (c->used + bytes > c->budget) {
     char msg[256];
     snprintf(msg, sizeof msg, "scratch '%s' of %zu bytes exceeds the budget (%zu of %zu used)",
@@ -40,11 +72,18 @@ void release_all(pr_ctx* c) {
   for (auto& kv : c->bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   c->bufs.clear();
+  for (auto& kv : c->pool) (void)hipFree(kv.second);
+  c->pool.clear();
   c->used = 0;
 }
 
 // ---------------------------------------------------------------------------
 // descriptor staging
+void stage_begin(pr_ctx* c, hipStream_t s) {
+  c->stream = s;
+  stage_begin(c);
+}
+
 void stage_begin(pr_ctx* c) {
   c->slot = (c->slot + 1) % pr_ctx::kSlots;
   PR_HIP(hipEventSynchronize(c->slot_ev[c->slot]));
@@ -53,14 +92,22 @@ void stage_begin(pr_ctx* c) {
 }
 
 void* stage_push_bytes(pr_ctx* c, const void* src, size_t bytes) {
-  const size_t o = (c->off + 255) & ~size_t(255);
-  if (o + bytes > pr_ctx::kSlotBytes) fail(PR_ENOMEM, "descriptor staging slot overflow");
+  if (bytes > pr_ctx::kSlotBytes) fail(PR_ENOMEM, "descriptor block larger than a staging slot");
+  size_t o = (c->off + 255) & ~size_t(255);
+  if (o + bytes > pr_ctx::kSlotBytes) {
+    // rotate to a fresh slot; what was pushed so far is copied first
+    const hipStream_t s = c->stream;
+    stage_end(c, s);
+    stage_begin(c, s);
+    o = 0;
+  }
   if (bytes) memcpy(c->host_slot[c->slot] + o, src, bytes);
   c->off = o + bytes;
   return c->dev_slot[c->slot] + o;
 }
 
 void stage_flush(pr_ctx* c, hipStream_t s) {
+  c->stream = s;
   if (c->off > c->flushed) {
     PR_HIP(hipMemcpyAsync(c->dev_slot[c->slot] + c->flushed, c->host_slot[c->slot] + c->flushed,
                           c->off - c->flushed, hipMemcpyHostToDevice, s));
@@ -68,9 +115,14 @@ void stage_flush(pr_ctx* c, hipStream_t s) {
   }
 }
 
+// The slot's event is recorded at its end and again at the end of the next
+// slot: a helper that rotated mid-way may launch, in the next slot, a kernel
+// still reading descriptors of this one.
 void stage_end(pr_ctx* c, hipStream_t s) {
   stage_flush(c, s);
   PR_HIP(hipEventRecord(c->slot_ev[c->slot], s));
+  const int prev = (c->slot + pr_ctx::kSlots - 1) % pr_ctx::kSlots;
+  PR_HIP(hipEventRecord(c->slot_ev[prev], s));
 }
 
 hipEvent_t event_get(pr_ctx* c) {
@@ -188,9 +240,11 @@ Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
   return g;
 }
 
-int gram_chunk_rows(long long nrows, int items) {
-  const long long target = std::max(1, 1024 / std::max(1, items));
-  long long ch = (nrows + target - 1) / target;
+// Rows per Gram chunk: a function of the row count only (about 512 chunks,
+// at least 1024 rows, a multiple of 64), never of the batch composition, so
+// a result is bitwise the same whatever else shares the launch.
+int gram_chunk_rows(long long nrows) {
+  long long ch = (nrows + 511) / 512;
   ch = std::max<long long>(ch, 1024);
   ch = (ch + 63) / 64 * 64;
   const long long cap = (nrows + 63) / 64 * 64;
@@ -329,7 +383,7 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
     PR_CHECK(it.cols.size() == ncol, "Gram column list size mismatch");
     GemmDesc d{};
     d.nrows = it.nrows;
-    d.chunk_rows = gram_chunk_rows(it.nrows, (int)items.size());
+    d.chunk_rows = gram_chunk_rows(it.nrows);
     d.nchunks = (int)((it.nrows + d.chunk_rows - 1) / d.chunk_rows);
     d.wg_begin = wg;
     wg += d.nchunks;
@@ -833,7 +887,7 @@ pr_status pr_fine_propagate(pr_ctx* c, int batch, const pr_fine_item* items, voi
     const pr_fine_item& it = items[i];
     w.push_back(FineWork{it.prob, it.dt, it.n_steps, it.u_in, it.u_out, it.snap_every, it.snaps});
   }
-  stage_begin(c);
+  stage_begin(c, s);
   enqueue_fine(c, w, s, "api_fine");
   stage_end(c, s);
   return PR_OK;
@@ -871,7 +925,7 @@ pr_status pr_pod_build(pr_ctx* c, int batch, const pr_pod_item* items, void* str
   for (auto& x : w)
     PR_CHECK((int)x.cols.size() <= kMaxPodCols && !x.cols.empty(), "POD input needs 1..64 columns");
   // items of different column-tile counts go in separate launches
-  stage_begin(c);
+  stage_begin(c, s);
   for (int na = 1; na <= 4; ++na) {
     std::vector<PodWork> g;
     for (auto& x : w)
@@ -902,7 +956,7 @@ pr_status pr_gram(pr_ctx* c, const pr_grid_problem* prob, const void* W, int nco
   g.ld = ldg;
   const double h = spacing(*prob);
   g.scale = h * h * h;
-  stage_begin(c);
+  stage_begin(c, s);
   enqueue_gram(c, {g}, na, 0, f32, s, "api_gram");
   PR_HIP(hipMemcpy2DAsync(G_out, (size_t)ncols * 8, G, (size_t)ldg * 8, (size_t)ncols * 8, ncols,
                           hipMemcpyDeviceToDevice, s));
@@ -947,7 +1001,7 @@ pr_status pr_coarse_propagate(pr_ctx* c, int batch, const pr_coarse_item* items,
     w.lift[1] = it.n_in > 1 ? it.u_out[1] : nullptr;
     w.beta_out = it.beta_out;
     w.n_c_out = it.n_c_out;
-    stage_begin(c);
+    stage_begin(c, s);
     enqueue_coarse(c, w, s, nullptr);
     stage_end(c, s);
   }

@@ -21,6 +21,9 @@ struct pr_ctx {
     size_t bytes = 0;
   };
   std::map<std::string, Buf> bufs;
+  // Idle device blocks of finished solves, by size, kept for the next solve
+  // (counted in `used`; given back when the budget needs the room).
+  std::multimap<size_t, void*> pool;
   std::map<std::string, void*> tables;   // velocity tables by problem key
 
   // Descriptor staging: a ring of pinned host slots mirrored by device slots.
@@ -31,6 +34,7 @@ struct pr_ctx {
   hipEvent_t slot_ev[kSlots] = {};
   int slot = -1;
   size_t off = 0, flushed = 0;
+  hipStream_t stream = nullptr;   // stream of the current staging session
 
   // Small pinned host buffer for scalars read back by the solver.
   double* host_scalars = nullptr;
@@ -43,12 +47,17 @@ namespace pr {
 // Device scratch buffer `name` of at least `bytes` (grows; budget-checked).
 void* scratch(pr_ctx* c, const std::string& name, size_t bytes);
 void release_all(pr_ctx* c);
+// Solve-owned blocks: pool_get reuses an idle block of the same size class
+// (within 1/8) or allocates one on the budget; pool_put returns an idle one.
+void* pool_get(pr_ctx* c, size_t bytes, size_t* got);
+void pool_put(pr_ctx* c, void* p, size_t bytes);
 
 // Descriptor staging. begin() takes a fresh slot (waiting for its previous
 // use to complete), push() copies items into it and returns their device
 // address, flush() enqueues the host-to-device copy of what was pushed since
 // the last flush, end() marks the slot's use as finished on `s`.
 void stage_begin(pr_ctx* c);
+void stage_begin(pr_ctx* c, hipStream_t s);
 void* stage_push_bytes(pr_ctx* c, const void* src, size_t bytes);
 template <typename T>
 T* stage_push(pr_ctx* c, const std::vector<T>& v) {
@@ -75,9 +84,9 @@ inline size_t field_bytes(const pr_grid_problem& p) {
 inline int tiles_q(int n) { return (n * n + kTileQ - 1) / kTileQ; }
 inline int tiles_x(int n) { return (n + kChunkX - 1) / kChunkX; }
 
-// Chunking of the MFMA Gram: rows per chunk (multiple of 64) for a launch
-// of `items` items of `nrows` rows.
-int gram_chunk_rows(long long nrows, int items);
+// Chunking of the MFMA Gram: rows per chunk (multiple of 64) for an item of
+// `nrows` rows; independent of the batch.
+int gram_chunk_rows(long long nrows);
 
 // Enqueue helpers shared by the entry points and the solver.
 struct FineWork {

@@ -1,4 +1,6 @@
-// The adaptive parareal solve (formula4, Algorithm 2) on one GPU.
+// The adaptive parareal solve (formula4, Algorithm 2) on one GPU, as a
+// per-solve state advanced one iteration at a time, alone or batched with
+// other solves (continuous batching).
 //
 // Numbering: [0, T] is split into N subintervals; subinterval 0 is the
 // warm-up window [0, T_0] (T_0 = DeltaT) whose fine solve gives u_hat_0 and
@@ -7,14 +9,15 @@
 //
 // Per iteration k >= 1:
 //   (i)   fine solves F(U^{k-1}_n) with snapshots for n = k-1..N'-1, batched
-//         in waves, and POD_Mode(gamma_2) of each snapshot set (Alg. 2 l. 8-9)
+//         in waves (and across solves), and POD_Mode(gamma_2) of each
+//         snapshot set (Alg. 2 lines 8-9)
 //   (ii)  POD_Mode(gamma_3) of W^k_n = [R_{n-m_l,0} .. R_{n,0}, R^{k-1}_{n,0}]
-//         batched over n, and L applied to the modes (Alg. 2 l. 9-10)
+//         batched over n, and L applied to the modes (Alg. 2 lines 9-10)
 //   (iii) U^k_j = U^{k-1}_j (j < k) and U^k_k = F_{k-1} (the coarse terms
 //         cancel there)
 //   (iv)  the sequential sweep n = k..N'-1: augmentation by U^k_n (eq12),
 //         Galerkin system of eq13, RK4 of both projections and the
-//         correction of formula4 with jump partials (Alg. 2 l. 12-17)
+//         correction of formula4 with jump partials (Alg. 2 lines 12-17)
 //   (v)   e_k = max_n ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M read back (8 B)
 // The basis of subinterval j last computed at iteration min(k, j + 1) sits
 // in slot min(k, j + 1) % 2 of a two-slot ring, which also holds
@@ -48,7 +51,7 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   P.o = *o;
   PR_CHECK(o->N >= 1, "N must be >= 1");
   PR_CHECK(std::isfinite(o->T) && o->T > 0, "T must be positive");
-  PR_CHECK(std::isfinite(o->dt) && o->dt > 0, "dt must be positive");
+  PR_CHECK(std::isfinite(o->dt), "dt must be finite");
   PR_CHECK(o->dM >= 0, "dM must be >= 0");
   PR_CHECK(o->gamma1 > 0 && o->gamma1 <= 1 && o->gamma2 > 0 && o->gamma2 <= 1 && o->gamma3 > 0 &&
                o->gamma3 <= 1,
@@ -63,7 +66,9 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   P.N = o->N;
   P.Np = o->N - 1;
   P.dTs = o->T / o->N;
-  P.n_f = (int)std::max(1.0, std::ceil(P.dTs / o->dt - 1e-9));
+  // dt <= 0: half the RK4 stability radius over the spectral bound, at most 2e-3
+  const double dt_req = o->dt > 0 ? o->dt : std::min(2e-3, 0.5 * kStabRK4 / spectral_bound(*p));
+  P.n_f = (int)std::max(1.0, std::ceil(P.dTs / dt_req - 1e-9));
   P.dt = P.dTs / P.n_f;
   P.dM = o->dM > 0 ? o->dM : (int)std::ceil(P.n_f / 16.0);
   P.dM = std::max(1, P.dM);
@@ -77,248 +82,415 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   if (P.dt * spectral_bound(*p) > kStabRK4)
     fail(PR_EUNSTABLE, "fine step exceeds the RK4 stability bound 2.6 / rho(L)");
   const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
-  const size_t Np = (size_t)std::max(P.Np, 1);
-  P.fixed_bytes = (size_t)(P.Np + 1) * f8          // second state buffer
-                  + (size_t)P.Np * f8                // F_n
-                  + 2 * Np * o->cap0 * fs            // stage-1 bases, two slots
-                  + 2 * fs + f8                      // augmentation fields
-                  + (size_t)o->cap * fs              // L R scratch of the coarse step
-                  + ((size_t)96 << 20);              // partials, small matrices
-  P.perF = (size_t)P.n_s * fs + (P.f32 ? 3 * fs : 2 * f8);
-  P.perS = 2 * (size_t)o->cap * fs;
+  const size_t Np1 = (size_t)std::max(P.Np, 1);
+  // solve-owned memory apart from the waves: two state sets, F_n, two slots
+  // of stage-1 bases, u0, small matrices
+  P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 + 2 * Np1 * o->cap0 * fs + f8 +
+                  ((size_t)4 << 20);
+  P.perF = (size_t)P.n_s * fs;       // snapshots of one subinterval
+  P.perS = 2 * (size_t)o->cap * fs;  // stage-2 basis and L applied to it
   return P;
 }
 
-static void choose_waves(Plan& P, size_t budget) {
-  const size_t need_min = P.fixed_bytes + P.perF + P.perS;
-  if (need_min > budget) fail(PR_ENOMEM, "parareal solve does not fit the HBM budget");
-  const size_t rest = budget - P.fixed_bytes;
+// Context scratch of the helpers per batched item: the fine propagator's
+// work fields and the POD's Gram partials (two Grams: <= 10 and 3 tile
+// pairs of 256 doubles per chunk) with its small matrices.
+static size_t fine_scratch_item(long long ng, bool f32) { return (size_t)ng * (f32 ? 12 : 8); }
+static size_t pod_scratch_item(long long ng) {
+  const long long ch = gram_chunk_rows(ng);
+  const long long nch = (ng + ch - 1) / ch;
+  return (size_t)nch * 13 * 256 * 8 + ((size_t)96 << 10);
+}
+
+static size_t held_prefix(const pr_ctx* c, const std::string& prefix) {
+  size_t b = 0;
+  for (auto& kv : c->bufs)
+    if (kv.first.compare(0, prefix.size(), prefix) == 0) b += kv.second.bytes;
+  return b;
+}
+
+// Whether the helpers' scratch can grow to fine_b work-field bytes and pod_b
+// POD bytes within the budget (idle pooled blocks count as free).
+static bool helpers_fit(const pr_ctx* c, size_t fine_b, size_t pod_b) {
+  size_t pooled = 0;
+  for (auto& kv : c->pool) pooled += kv.first;
+  const size_t hf = held_prefix(c, "sol_fine"), hp = held_prefix(c, "sol_pod");
+  const size_t grow = (fine_b > hf ? fine_b - hf : 0) + (pod_b > hp ? pod_b - hp : 0);
+  return c->used + grow <= c->budget + pooled;
+}
+
+// Context scratch shared by the helpers (fine work fields, POD partials,
+// augmentation fields, L R, Gram partials of the sweep) for one solve.
+static size_t shared_scratch_bytes(const Plan& P) {
+  const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
+  const long long ch = gram_chunk_rows(P.ng);
+  const size_t nch = (size_t)((P.ng + ch - 1) / ch);
+  return fine_scratch_item(P.ng, P.f32) * (size_t)std::max(P.waveF, 1) +
+         pod_scratch_item(P.ng) * (size_t)std::max({P.waveF, P.waveS, 1}) + 2 * fs + f8 +
+         (size_t)P.o.cap * fs + nch * 10 * 256 * 8 + ((size_t)16 << 20);
+}
+
+static void choose_waves(Plan& P, size_t avail) {
   const int Np = std::max(P.Np, 1);
-  // fine waves first (they carry the batched stencil), then the POD waves
-  size_t wf = std::min<size_t>(Np, std::max<size_t>(1, (rest / 2) / P.perF));
-  size_t ws = std::min<size_t>(Np, std::max<size_t>(1, (rest - wf * P.perF) / P.perS));
-  if (ws < (size_t)Np && wf > 1) {
-    // rebalance when the POD wave would be starved
-    wf = std::min<size_t>(Np, std::max<size_t>(1, (rest - std::min<size_t>(Np, 8) * P.perS) / P.perF));
-    ws = std::min<size_t>(Np, std::max<size_t>(1, (rest - wf * P.perF) / P.perS));
+  auto need = [&](int wf, int ws) {
+    Plan Q = P;
+    Q.waveF = wf;
+    Q.waveS = ws;
+    return P.fixed_bytes + (size_t)wf * P.perF + (size_t)ws * P.perS + shared_scratch_bytes(Q);
+  };
+  if (need(1, 1) > avail) fail(PR_ENOMEM, "parareal solve does not fit the HBM budget");
+  int wf = Np, ws = Np;
+  while (need(wf, ws) > avail && (wf > 1 || ws > 1)) {
+    // halve the larger of the two wave buffers first
+    if (((size_t)wf * P.perF >= (size_t)ws * P.perS && wf > 1) || ws == 1) wf = (wf + 1) / 2;
+    else ws = (ws + 1) / 2;
   }
-  P.waveF = (int)wf;
-  P.waveS = (int)ws;
+  P.waveF = wf;
+  P.waveS = ws;
 }
 
 static ColDesc colp(const void* base, int idx, long long ng, bool f32, const int* mptr) {
   return ColDesc{(const char*)base + (size_t)idx * ng * (f32 ? 4 : 8), mptr, idx, f32 ? 1 : 0};
 }
+static ColDesc colnull() { return ColDesc{nullptr, nullptr, 0, 0}; }
 
-static void solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
-                  const double* u0, double* U_out, pr_report* rep, hipStream_t s) {
-  auto t_start = std::chrono::steady_clock::now();
-  PR_CHECK(u0 && U_out, "null state pointer");
+}  // namespace pr
+
+using namespace pr;
+
+struct pr_solve {
+  Plan P;
+  const double* U_ref = nullptr;
+  double* U[2] = {nullptr, nullptr};  // state sets (N' + 1 fields each)
+  double* u0 = nullptr;               // copy of the initial field
+  double* Fn = nullptr;
+  char* R0 = nullptr;
+  char* snaps = nullptr;
+  char* Psi = nullptr;
+  char* LPsi = nullptr;
+  double *norms = nullptr, *betas0 = nullptr, *S0 = nullptr, *dscal = nullptr;
+  int *m0slot = nullptr, *mS = nullptr, *misc = nullptr, *ranks = nullptr;
+  double* host = nullptr;  // pinned: e_k, err_k
+  std::vector<std::pair<void*, size_t>> owned;
+  bool ext_out = false;    // U[0] lives in the caller's U_out
+  int k = 0;
+  int prev = 0;            // U[prev] holds the latest iterate
+  bool done = false;
+  bool numeric_bad = false;
+  pr_status fail_st = PR_OK;  // error that stopped the solve mid-iteration
+  std::vector<double> jump, err, t_iter;
+  int m0 = 0;
+  double t_phase[5] = {0, 0, 0, 0, 0};
+  double fine_updates = 0;
+  std::chrono::steady_clock::time_point t0;
+};
+
+namespace pr {
+
+static void* owned_alloc(pr_ctx* c, pr_solve* S, size_t bytes) {
+  size_t got = 0;
+  void* p = pool_get(c, bytes, &got);
+  S->owned.push_back({p, got});
+  return p;
+}
+
+// Return the solve's blocks to the context pool. `idle`: no queued work can
+// still touch them (else the device is drained first).
+static void release_solve(pr_ctx* c, pr_solve* S, bool idle) {
+  if (!S) return;
+  if (!idle) (void)hipDeviceSynchronize();
+  for (auto& o : S->owned) pool_put(c, o.first, o.second);
+  S->owned.clear();
+  if (S->host) (void)hipHostFree(S->host);
+  S->host = nullptr;
+}
+
+static double since(const pr_solve* S) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+}
+
+// Allocate the solve, enqueue k = 0 (Alg. 2 lines 3-5) and synchronise.
+static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
+                             const double* u0, double* U_out, hipStream_t s) {
+  PR_CHECK(u0 != nullptr, "null initial field");
   Plan P = make_plan(prob, opts);
   {
-    // buffers held under other names stay allocated; the solver's own
-    // (sol_*, co_*) are reused or regrown
-    size_t other = 0;
-    for (auto& kv : c->bufs)
-      if (kv.first.rfind("sol_", 0) != 0 && kv.first.rfind("co_", 0) != 0) other += kv.second.bytes;
-    choose_waves(P, c->budget > other ? c->budget - other : 0);
+    // the solve-owned memory comes on top of what the context already
+    // holds; shared helper scratch may be regrown to fit this solve
+    const size_t avail = c->budget > c->used ? c->budget - c->used : 0;
+    size_t reusable = 0;
+    for (auto& kv : c->bufs) reusable += kv.second.bytes;
+    for (auto& kv : c->pool) reusable += kv.first;
+    choose_waves(P, avail + reusable);
   }
-  const pr_grid_problem& p = P.prob;
-  const long long ng = P.ng;
-  const size_t f8 = (size_t)ng * 8, fs = (size_t)ng * P.sf;
-  const int Np = P.Np;
-  const double h = spacing(p), h3 = h * h * h;
-  const int cap = P.o.cap, cap0 = P.o.cap0;
-
-  // buffers: U_out holds u0 and one of the two state sets
-  double* Ua = U_out + ng;  // U_n at t = (n + 1) DeltaT, n = 0..Np
-  double* Ub = (double*)scratch(c, "sol_Ub", (size_t)(Np + 1) * f8);
-  double* Fn = (double*)scratch(c, "sol_F", (size_t)std::max(Np, 1) * f8);
-  char* R0 = (char*)scratch(c, "sol_R0", 2 * (size_t)std::max(Np, 1) * cap0 * fs);
-  char* snaps = (char*)scratch(c, "sol_snaps", (size_t)P.waveF * P.n_s * fs);
-  char* Psi = (char*)scratch(c, "sol_Psi", (size_t)P.waveS * cap * fs);
-  char* LPsi = (char*)scratch(c, "sol_LPsi", (size_t)P.waveS * cap * fs);
-  const int maxk = P.max_iter;
-  const size_t Np1 = (size_t)std::max(Np, 1);
-  // small device buffers: doubles first, then ints
-  const size_t o_norms = 0, n_norms = (size_t)(Np + 2) * 4;
-  const size_t o_betas = o_norms + n_norms, n_betas = Np1 * 32;
-  const size_t o_S0 = o_betas + n_betas, n_S0 = 32 * 80;
-  const size_t o_dscal = o_S0 + n_S0, n_dscal = 8;
-  const size_t n_dbl = o_dscal + n_dscal;
-  const size_t n_int = 2 * Np1 + (size_t)P.waveS + 64 + (size_t)(maxk + 1) * Np1;
-  char* small = (char*)scratch(c, "sol_small", n_dbl * 8 + n_int * 4);
-  double* norms = (double*)small + o_norms;                // (Np + 2) x 4
-  double* betas0 = (double*)small + o_betas;               // Np x 32
-  double* S0 = (double*)small + o_S0;                      // 32 x 80
-  double* dscal = (double*)small + o_dscal;                // 8
-  int* m0slot = (int*)((double*)small + n_dbl);            // 2 x Np
-  int* mS = m0slot + 2 * Np1;                              // waveS
-  int* misc = mS + P.waveS;                                // 64
-  int* ranks = misc + 64;                                  // (maxk + 1) x Np
-  PR_HIP(hipMemsetAsync(small, 0, n_dbl * 8 + n_int * 4, s));
-  // pre-size the helpers' partial buffers (no reallocation mid-solve)
-  {
-    const int items_max = std::max(P.waveF, P.waveS);
-    const long long chunk = gram_chunk_rows(ng, 1);
-    const long long nch = (ng + chunk - 1) / chunk;
+  pr_solve* S = new pr_solve();
+  S->P = P;
+  S->U_ref = opts->U_ref;
+  S->t0 = std::chrono::steady_clock::now();
+  try {
+    const long long ng = P.ng;
+    const size_t f8 = (size_t)ng * 8, fs = (size_t)ng * P.sf;
+    const int Np = P.Np;
+    const size_t Np1 = (size_t)std::max(Np, 1);
+    if (U_out) {
+      S->ext_out = true;
+      S->U[0] = U_out + ng;
+      S->u0 = U_out;
+    } else {
+      S->U[0] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
+      S->u0 = (double*)owned_alloc(c, S, f8);
+    }
+    S->U[1] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
+    S->Fn = (double*)owned_alloc(c, S, Np1 * f8);
+    S->R0 = (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
+    S->snaps = (char*)owned_alloc(c, S, (size_t)P.waveF * P.n_s * fs);
+    S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+    S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+    const int maxk = P.max_iter;
+    const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 80, n_dscal = 8;
+    const size_t n_dbl = n_norms + n_betas + n_S0 + n_dscal;
+    const size_t n_int = 2 * Np1 + (size_t)P.waveS + 64 + (size_t)(maxk + 1) * Np1;
+    char* small = (char*)owned_alloc(c, S, n_dbl * 8 + n_int * 4);
+    S->norms = (double*)small;
+    S->betas0 = S->norms + n_norms;
+    S->S0 = S->betas0 + n_betas;
+    S->dscal = S->S0 + n_S0;
+    S->m0slot = (int*)((double*)small + n_dbl);
+    S->mS = S->m0slot + 2 * Np1;
+    S->misc = S->mS + P.waveS;
+    S->ranks = S->misc + 64;
+    PR_HIP(hipHostMalloc((void**)&S->host, 64));
+    // shared helper scratch, pre-sized so nothing regrows mid-iteration
+    const long long nch = (ng + gram_chunk_rows(ng) - 1) / gram_chunk_rows(ng);
     scratch(c, "co_g_part", (size_t)nch * 10 * 256 * 8);
     scratch(c, "co_fields", fs * 2 + f8);
-    (void)items_max;
-  }
+    scratch(c, "co_LR", (size_t)P.o.cap * fs);
 
-  pr_report local{};
-  pr_report& R = rep ? *rep : local;
-  R.iters = 0;
-  R.converged = 0;
-  R.n_f = P.n_f;
-  R.dM = P.dM;
-  R.n_s = P.n_s;
-  R.n_c = P.n_c;
-  R.n_sub = Np;
-  for (int i = 0; i < 5; ++i) R.t_phase[i] = 0;
-  R.fine_updates = 0;
+    PR_HIP(hipMemsetAsync(small, 0, n_dbl * 8 + n_int * 4, s));
+    if (S->u0 != u0) PR_HIP(hipMemcpyAsync(S->u0, u0, f8, hipMemcpyDeviceToDevice, s));
+    S->err.assign(1, 0.0);
 
-  PhaseEvents ph;
-  ph.c = c;
-  ph.s = s;
-  double* hs = c->host_scalars;
-  auto elapsed = [&]() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  };
-
-  // ---- k = 0 (Algorithm 2, lines 3-5) -----------------------------------
-  stage_begin(c);
-  PR_HIP(hipMemcpyAsync(U_out, u0, f8, hipMemcpyDeviceToDevice, s));
-  ph.begin(0);
-  enqueue_fine(c, {FineWork{&p, P.dt, P.n_f, u0, Ua, P.dM, snaps}}, s, "sol_fine");
-  R.fine_updates += (double)P.n_f * ng;
-  if (Np == 0) {
+    const pr_grid_problem& p = S->P.prob;
+    const double h = spacing(p), h3 = h * h * h;
+    const int cap = P.o.cap;
+    double* Ua = S->U[0];
+    PhaseEvents ph;
+    ph.c = c;
+    ph.s = s;
+    stage_begin(c, s);
+    ph.begin(0);
+    enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.dM, S->snaps}}, s, "sol_fine");
+    S->fine_updates += (double)P.n_f * ng;
+    if (Np > 0) {
+      ph.begin(1);
+      PodWork pw;
+      pw.prob = &S->P.prob;
+      for (int j = 0; j < P.n_s; ++j) pw.cols.push_back(colp(S->snaps, j, ng, P.f32, nullptr));
+      pw.gamma = P.o.gamma1;
+      pw.cap = cap;
+      pw.force_m = -1;
+      pw.R_out = S->Psi;
+      pw.m_out = S->mS;
+      pw.lambda_out = nullptr;
+      enqueue_pod(c, {pw}, s, "sol_pod");
+      ph.begin(2);
+      enqueue_applyL(c, p, S->Psi, S->LPsi, cap, S->mS, s);
+      GramWork g;
+      g.nrows = ng;
+      std::vector<ColDesc> a;
+      for (int j = 0; j < 32; ++j) a.push_back(j < cap ? colp(S->Psi, j, ng, P.f32, S->mS) : colnull());
+      g.cols = a;
+      g.cols.insert(g.cols.end(), a.begin(), a.end());
+      for (int j = 0; j < 32; ++j)
+        g.cols.push_back(j < cap ? colp(S->LPsi, j, ng, P.f32, S->mS) : colnull());
+      g.cols.push_back(ColDesc{Ua, nullptr, 0, 0});
+      g.cols.resize((2 + 5) * 16, colnull());
+      g.out = S->S0;
+      g.ld = 80;
+      g.scale = h3;
+      enqueue_gram(c, {g}, 2, 5, false, s, "co_g");
+      ph.begin(4);
+      Reduced0Desc d{};
+      d.S = S->S0;
+      d.ld = 80;
+      d.cap = cap;
+      d.m = S->mS;
+      d.off_M = 0;
+      d.off_L = 32;
+      d.off_U = 64;
+      d.dT = P.dTs;
+      d.n_c = P.n_c;
+      d.count = Np;
+      d.betas = S->betas0;
+      d.ld_out = 32;
+      d.n_c_out = S->misc + 1;
+      Reduced0Desc* dd = stage_push1(c, d);
+      stage_flush(c, s);
+      launch_reduced0(dd, s);
+      std::vector<ColDesc> psi;
+      for (int j = 0; j < cap; ++j) psi.push_back(colp(S->Psi, j, ng, P.f32, S->mS));
+      for (int n = 0; n < Np; ++n)
+        enqueue_correct(c, ng, psi, S->betas0 + (size_t)n * 32, nullptr, 0,
+                        Ua + (size_t)(n + 1) * ng, nullptr,
+                        S->U_ref ? S->U_ref + (size_t)(n + 2) * ng : nullptr,
+                        S->norms + 4 * (n + 1), h3, s, "sol");
+    }
+    enqueue_correct(c, ng, {}, nullptr, Ua, 0, Ua, nullptr,
+                    S->U_ref ? S->U_ref + (size_t)1 * ng : nullptr, S->norms, h3, s, "sol");
     ph.end();
+    PR_HIP(hipMemcpyAsync(S->U[1], Ua, f8, hipMemcpyDeviceToDevice, s));
+    launch_jump_max(S->norms, Np + 1, S->dscal, s);
+    PR_HIP(hipMemcpyAsync(S->host, S->dscal, 2 * 8, hipMemcpyDeviceToHost, s));
+    PR_HIP(hipMemcpyAsync((char*)S->host + 16, S->mS, 4, hipMemcpyDeviceToHost, s));
     stage_end(c, s);
     PR_HIP(hipStreamSynchronize(s));
     ph.collect();
-    for (int i = 0; i < 5; ++i) R.t_phase[i] = ph.t[i];
-    R.converged = 1;
-    R.seconds = elapsed();
-    if (R.t_iter) R.t_iter[0] = R.seconds;
-    return;
+    for (int i = 0; i < 5; ++i) S->t_phase[i] += ph.t[i];
+    S->m0 = Np > 0 ? *(int*)((char*)S->host + 16) : 0;
+    S->err[0] = S->host[1];
+    S->t_iter.push_back(since(S));
+    S->prev = 0;
+    S->k = 0;
+    S->done = (Np == 0) || (P.max_iter == 0);
+  } catch (...) {
+    release_solve(c, S, false);
+    delete S;
+    throw;
   }
-  ph.begin(1);
-  {
-    PodWork pw;
-    pw.prob = &p;
-    for (int j = 0; j < P.n_s; ++j) pw.cols.push_back(colp(snaps, j, ng, P.f32, nullptr));
-    pw.gamma = P.o.gamma1;
-    pw.cap = cap;
-    pw.force_m = -1;
-    pw.R_out = Psi;
-    pw.m_out = mS;
-    pw.lambda_out = nullptr;
-    enqueue_pod(c, {pw}, s, "sol_pod0");
-  }
-  ph.begin(2);
-  enqueue_applyL(c, p, Psi, LPsi, cap, mS, s);
-  {
-    GramWork g;
-    g.nrows = ng;
-    std::vector<ColDesc> a;
-    for (int j = 0; j < 32; ++j)
-      a.push_back(j < cap ? colp(Psi, j, ng, P.f32, mS) : ColDesc{nullptr, nullptr, 0, 0});
-    g.cols = a;
-    g.cols.insert(g.cols.end(), a.begin(), a.end());
-    for (int j = 0; j < 32; ++j)
-      g.cols.push_back(j < cap ? colp(LPsi, j, ng, P.f32, mS) : ColDesc{nullptr, nullptr, 0, 0});
-    g.cols.push_back(ColDesc{Ua, nullptr, 0, 0});
-    g.cols.resize((2 + 5) * 16, ColDesc{nullptr, nullptr, 0, 0});
-    g.out = S0;
-    g.ld = 80;
-    g.scale = h3;
-    enqueue_gram(c, {g}, 2, 5, false, s, "co_g");
-  }
-  ph.begin(4);
-  {
-    Reduced0Desc d{};
-    d.S = S0;
-    d.ld = 80;
-    d.cap = cap;
-    d.m = mS;
-    d.off_M = 0;
-    d.off_L = 32;
-    d.off_U = 64;
-    d.dT = P.dTs;
-    d.n_c = P.n_c;
-    d.count = Np;
-    d.betas = betas0;
-    d.ld_out = 32;
-    d.n_c_out = misc + 1;
-    Reduced0Desc* dd = stage_push1(c, d);
-    stage_flush(c, s);
-    launch_reduced0(dd, s);
-    std::vector<ColDesc> psi;
-    for (int j = 0; j < cap; ++j) psi.push_back(colp(Psi, j, ng, P.f32, mS));
-    const double* Uref = opts->U_ref;
-    for (int n = 0; n < Np; ++n)
-      enqueue_correct(c, ng, psi, betas0 + (size_t)n * 32, nullptr, 0, Ua + (size_t)(n + 1) * ng,
-                      nullptr, Uref ? Uref + (size_t)(n + 2) * ng : nullptr,
-                      norms + 4 * (n + 1), h3, s, "sol");
-    enqueue_correct(c, ng, {}, nullptr, Ua, 0, Ua, nullptr, Uref ? Uref + (size_t)1 * ng : nullptr,
-                    norms, h3, s, "sol");
-  }
-  ph.end();
-  PR_HIP(hipMemcpyAsync(Ub, Ua, f8, hipMemcpyDeviceToDevice, s));
-  launch_jump_max(norms, Np + 1, dscal, s);
-  PR_HIP(hipMemcpyAsync(hs, dscal, 2 * 8, hipMemcpyDeviceToHost, s));
-  PR_HIP(hipMemcpyAsync(hs + 2, mS, 4, hipMemcpyDeviceToHost, s));
-  stage_end(c, s);
-  PR_HIP(hipStreamSynchronize(s));
-  ph.collect();
-  R.m0 = *(int*)(hs + 2);
-  if (R.err) R.err[0] = hs[1];
-  if (R.t_iter) R.t_iter[0] = elapsed();
+  return S;
+}
 
-  double* Uprev = Ua;
-  double* Ucur = Ub;
-  const double* Uref = opts->U_ref;
-  bool converged = false;
-  bool numeric_bad = false;
-  int k = 0;
-  while (!converged && k < P.max_iter) {
-    ++k;
-    stage_begin(c);
-    // (i) fine solves and stage-1 POD, in waves
-    for (int n0 = k - 1; n0 < Np; n0 += P.waveF) {
+// One parareal iteration of every unfinished solve in `ss`: the fine solves
+// and stage-1 POD of all of them share launches (rounds of their waves),
+// stage 2 and the sweep run solve by solve; one synchronisation at the end.
+static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hipStream_t s);
+
+// A failure inside an iteration leaves the affected solves mid-iteration:
+// they are stopped with the error, which pr_solve_end then returns.
+static void iterate_batch(pr_ctx* c, const std::vector<pr_solve*>& ss, hipStream_t s) {
+  std::vector<pr_solve*> live;
+  for (auto* S : ss)
+    if (!S->done) live.push_back(S);
+  if (live.empty()) return;
+  try {
+    iterate_batch_impl(c, live, s);
+  } catch (const Error& e) {
+    (void)hipDeviceSynchronize();
+    for (auto* S : live) {
+      S->done = true;
+      S->fail_st = e.st;
+    }
+    throw;
+  } catch (...) {
+    (void)hipDeviceSynchronize();
+    for (auto* S : live) {
+      S->done = true;
+      S->fail_st = PR_EDEVICE;
+    }
+    throw;
+  }
+}
+
+static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hipStream_t s) {
+  PhaseEvents shared;  // phases shared by the batch are charged to each solve
+  shared.c = c;
+  shared.s = s;
+  std::vector<PhaseEvents> own(live.size());
+  stage_begin(c, s);
+  for (auto* S : live) ++S->k;
+
+  // (i) fine solves and stage-1 POD, in rounds of every solve's waves
+  for (int round = 0;; ++round) {
+    std::vector<FineWork> fw;
+    std::vector<PodWork> pw;
+    for (auto* S : live) {
+      const Plan& P = S->P;
+      const int k = S->k, Np = P.Np;
+      const int n0 = (k - 1) + round * P.waveF;
+      if (n0 >= Np) continue;
       const int n1 = std::min(Np, n0 + P.waveF);
-      std::vector<FineWork> fw;
-      std::vector<PodWork> pw;
+      const size_t fs = (size_t)P.ng * P.sf;
+      const double* Uprev = S->U[S->prev];
       for (int n = n0; n < n1; ++n) {
-        void* sn = snaps + (size_t)(n - n0) * P.n_s * fs;
-        fw.push_back(FineWork{&p, P.dt, P.n_f, Uprev + (size_t)n * ng, Fn + (size_t)n * ng, P.dM, sn});
+        void* sn = S->snaps + (size_t)(n - n0) * P.n_s * fs;
+        fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
+                              S->Fn + (size_t)n * P.ng, P.dM, sn});
         PodWork w;
-        w.prob = &p;
-        for (int j = 0; j < P.n_s; ++j) w.cols.push_back(colp(sn, j, ng, P.f32, nullptr));
+        w.prob = &S->P.prob;
+        for (int j = 0; j < P.n_s; ++j) w.cols.push_back(colp(sn, j, P.ng, P.f32, nullptr));
         w.gamma = P.o.gamma2;
-        w.cap = cap0;
+        w.cap = P.o.cap0;
         w.force_m = -1;
         const int slot = k % 2;
-        w.R_out = R0 + ((size_t)slot * Np + n) * cap0 * fs;
-        w.m_out = m0slot + slot * Np + n;
+        w.R_out = S->R0 + ((size_t)slot * Np + n) * P.o.cap0 * fs;
+        w.m_out = S->m0slot + slot * Np + n;
         w.lambda_out = nullptr;
         pw.push_back(w);
       }
-      ph.begin(0);
-      enqueue_fine(c, fw, s, "sol_fine");
-      R.fine_updates += (double)(n1 - n0) * P.n_f * ng;
-      ph.begin(1);
-      enqueue_pod(c, pw, s, "sol_pod1");
+      S->fine_updates += (double)(n1 - n0) * P.n_f * P.ng;
     }
+    if (fw.empty()) break;
+    // one launch sequence per precision
+    for (int prec = 0; prec < 2; ++prec) {
+      std::vector<FineWork> f2;
+      std::vector<PodWork> p2;
+      for (size_t i = 0; i < fw.size(); ++i)
+        if (fw[i].prob->precision == prec) {
+          f2.push_back(fw[i]);
+          p2.push_back(pw[i]);
+        }
+      // launches of as many items as the helpers' scratch can hold (the
+      // waves of one solve always fit: its admission reserved them)
+      size_t i0 = 0;
+      while (i0 < f2.size()) {
+        size_t i1 = i0 + 1, fb = 0, pb = 0;
+        fb += fine_scratch_item(ngrid(*f2[i0].prob), prec == PR_MIXED);
+        pb += pod_scratch_item(ngrid(*f2[i0].prob));
+        for (; i1 < f2.size(); ++i1) {
+          const long long ng1 = ngrid(*f2[i1].prob);
+          const size_t fb1 = fb + fine_scratch_item(ng1, prec == PR_MIXED);
+          const size_t pb1 = pb + pod_scratch_item(ng1);
+          if (!helpers_fit(c, fb1, pb1)) break;
+          fb = fb1;
+          pb = pb1;
+        }
+        std::vector<FineWork> fsub(f2.begin() + i0, f2.begin() + i1);
+        std::vector<PodWork> psub(p2.begin() + i0, p2.begin() + i1);
+        shared.begin(0);
+        enqueue_fine(c, fsub, s, "sol_fine");
+        shared.begin(1);
+        for (int na = 1; na <= 4; ++na) {
+          std::vector<PodWork> g;
+          for (auto& x : psub)
+            if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
+          if (!g.empty()) enqueue_pod(c, g, s, "sol_pod");
+        }
+        i0 = i1;
+      }
+    }
+  }
+  shared.end();
+
+  for (size_t si = 0; si < live.size(); ++si) {
+    pr_solve* S = live[si];
+    PhaseEvents& ph = own[si];
+    ph.c = c;
+    ph.s = s;
+    const Plan& P = S->P;
+    const int k = S->k, Np = P.Np, cap = P.o.cap, cap0 = P.o.cap0;
+    const long long ng = P.ng;
+    const size_t f8 = (size_t)ng * 8, fs = (size_t)ng * P.sf;
+    const double h = spacing(P.prob), h3 = h * h * h;
+    double* Uprev = S->U[S->prev];
+    double* Ucur = S->U[1 - S->prev];
+    const double* Uref = S->U_ref;
     // (iii) converged prefix
     ph.begin(4);
     PR_HIP(hipMemcpyAsync(Ucur + (size_t)(k - 1) * ng, Uprev + (size_t)(k - 1) * ng, f8,
                           hipMemcpyDeviceToDevice, s));
-    enqueue_correct(c, ng, {}, nullptr, Fn + (size_t)(k - 1) * ng, 0, Ucur + (size_t)k * ng,
+    enqueue_correct(c, ng, {}, nullptr, S->Fn + (size_t)(k - 1) * ng, 0, Ucur + (size_t)k * ng,
                     Uprev + (size_t)k * ng, Uref ? Uref + (size_t)(k + 1) * ng : nullptr,
-                    norms + 4 * k, h3, s, "sol");
+                    S->norms + 4 * k, h3, s, "sol");
     // (ii) + (iv)
     for (int n0 = k; n0 < Np; n0 += P.waveS) {
       const int n1 = std::min(Np, n0 + P.waveS);
@@ -326,46 +498,47 @@ static void solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts
       std::vector<ApplyLWork> aw;
       for (int n = n0; n < n1; ++n) {
         PodWork w;
-        w.prob = &p;
+        w.prob = &S->P.prob;
         for (int j = std::max(0, n - P.o.ml); j <= n; ++j) {
           const int slot = std::min(k, j + 1) % 2;
-          const char* base = R0 + ((size_t)slot * Np + j) * cap0 * fs;
-          const int* mp = m0slot + slot * Np + j;
+          const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * fs;
+          const int* mp = S->m0slot + slot * Np + j;
           for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, ng, P.f32, mp));
         }
         if (P.o.p >= 1 && k - 1 >= 1) {
           const int slot = (k - 1) % 2;
-          const char* base = R0 + ((size_t)slot * Np + n) * cap0 * fs;
-          const int* mp = m0slot + slot * Np + n;
+          const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * fs;
+          const int* mp = S->m0slot + slot * Np + n;
           for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, ng, P.f32, mp));
         }
         w.gamma = P.o.gamma3;
         w.cap = cap;
         w.force_m = -1;
-        w.R_out = Psi + (size_t)(n - n0) * cap * fs;
-        w.m_out = mS + (n - n0);
+        w.R_out = S->Psi + (size_t)(n - n0) * cap * fs;
+        w.m_out = S->mS + (n - n0);
         w.lambda_out = nullptr;
         pw.push_back(w);
-        aw.push_back(ApplyLWork{&p, w.R_out, LPsi + (size_t)(n - n0) * cap * fs, cap, w.m_out});
+        aw.push_back(ApplyLWork{&S->P.prob, w.R_out, S->LPsi + (size_t)(n - n0) * cap * fs, cap,
+                                w.m_out});
       }
       ph.begin(1);
-      // items with equal column counts share one launch
       for (int na = 1; na <= 4; ++na) {
         std::vector<PodWork> g;
         for (auto& x : pw)
           if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
-        if (!g.empty()) enqueue_pod(c, g, s, "sol_pod2");
+        if (!g.empty()) enqueue_pod(c, g, s, "sol_pod");
       }
       ph.begin(2);
       enqueue_applyL_batch(c, aw, s);
       for (int n = n0; n < n1; ++n) {
-        PR_HIP(hipMemcpyAsync(ranks + (size_t)k * Np + n, mS + (n - n0), 4, hipMemcpyDeviceToDevice, s));
+        PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + n, S->mS + (n - n0), 4,
+                              hipMemcpyDeviceToDevice, s));
         CoarseWork w{};
-        w.prob = &p;
-        w.R = Psi + (size_t)(n - n0) * cap * fs;
-        w.LR = LPsi + (size_t)(n - n0) * cap * fs;
+        w.prob = &S->P.prob;
+        w.R = S->Psi + (size_t)(n - n0) * cap * fs;
+        w.LR = S->LPsi + (size_t)(n - n0) * cap * fs;
         w.cap = cap;
-        w.m = mS + (n - n0);
+        w.m = S->mS + (n - n0);
         w.u_aug = Ucur + (size_t)n * ng;
         w.n_in = 2;
         w.u_in[0] = Ucur + (size_t)n * ng;
@@ -373,70 +546,199 @@ static void solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts
         w.dT = P.dTs;
         w.n_c = P.n_c;
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
-        w.fine = Fn + (size_t)n * ng;
+        w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;
         w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
-        w.norms4 = norms + 4 * (n + 1);
+        w.norms4 = S->norms + 4 * (n + 1);
         enqueue_coarse(c, w, s, &ph);
       }
     }
     ph.end();
     // (v) jump and error
-    launch_jump_max(norms + 4 * k, Np - k + 1, dscal, s);
-    launch_jump_max(norms, Np + 1, dscal + 2, s);
-    PR_HIP(hipMemcpyAsync(hs, dscal, 4 * 8, hipMemcpyDeviceToHost, s));
-    stage_end(c, s);
-    PR_HIP(hipStreamSynchronize(s));
-    ph.collect();
-    const double e_k = hs[0], err_k = hs[3];
-    if (R.jump) R.jump[k - 1] = e_k;
-    if (R.err) R.err[k] = err_k;
-    if (R.t_iter) R.t_iter[k] = elapsed();
-    std::swap(Uprev, Ucur);
-    R.iters = k;
-    if (!(e_k == e_k) || std::isinf(e_k)) {
-      numeric_bad = true;
-      break;
-    }
-    converged = (e_k <= P.o.tol) || (k == Np);
+    launch_jump_max(S->norms + 4 * k, Np - k + 1, S->dscal, s);
+    launch_jump_max(S->norms, Np + 1, S->dscal + 2, s);
+    PR_HIP(hipMemcpyAsync(S->host, S->dscal, 4 * 8, hipMemcpyDeviceToHost, s));
   }
-  if (Np > 0 && Uprev != Ua)
-    PR_HIP(hipMemcpyAsync(Ua, Uprev, (size_t)(Np + 1) * f8, hipMemcpyDeviceToDevice, s));
-  if (R.ranks && k > 0)
-    PR_HIP(hipMemcpyAsync(R.ranks, ranks, (size_t)(k + 1) * Np * 4, hipMemcpyDeviceToHost, s));
+  stage_end(c, s);
   PR_HIP(hipStreamSynchronize(s));
-  for (int i = 0; i < 5; ++i) R.t_phase[i] = ph.t[i];
-  R.converged = converged ? 1 : 0;
-  R.seconds = elapsed();
-  if (numeric_bad) fail(PR_ENUMERIC, "NaN or Inf in a parareal jump");
-  if (!converged) fail(PR_ENOTCONV, "max_iter reached above tol");
+  shared.collect();
+  for (size_t si = 0; si < live.size(); ++si) {
+    pr_solve* S = live[si];
+    own[si].collect();
+    for (int i = 0; i < 5; ++i) S->t_phase[i] += own[si].t[i] + shared.t[i];
+    const double e_k = S->host[0], err_k = S->host[3];
+    S->jump.push_back(e_k);
+    S->err.push_back(err_k);
+    S->t_iter.push_back(since(S));
+    S->prev = 1 - S->prev;
+    if (!(e_k == e_k) || std::isinf(e_k)) {
+      S->numeric_bad = true;
+      S->done = true;
+      continue;
+    }
+    const bool conv = (e_k <= S->P.o.tol) || (S->k == S->P.Np);
+    S->done = conv || S->k >= S->P.max_iter;
+  }
+}
+
+static bool converged(const pr_solve* S) {
+  if (S->numeric_bad || S->fail_st != PR_OK) return false;
+  if (S->P.Np == 0) return true;
+  if (S->k == 0) return false;
+  return S->jump.back() <= S->P.o.tol || S->k == S->P.Np;
+}
+
+// Copy the result into U_out ((N + 1) x N_g; may be the buffer given at
+// begin) and fill the report.
+static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* rep,
+                              hipStream_t s) {
+  (void)c;
+  const Plan& P = S->P;
+  const long long ng = P.ng;
+  const size_t f8 = (size_t)ng * 8;
+  const int Np = P.Np;
+  if (U_out) {
+    if (U_out != S->u0) PR_HIP(hipMemcpyAsync(U_out, S->u0, f8, hipMemcpyDeviceToDevice, s));
+    if (U_out + ng != S->U[S->prev])
+      PR_HIP(hipMemcpyAsync(U_out + ng, S->U[S->prev], (size_t)(Np + 1) * f8,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  if (rep) {
+    rep->iters = S->k;
+    rep->converged = converged(S) ? 1 : 0;
+    rep->n_f = P.n_f;
+    rep->dM = P.dM;
+    rep->n_s = P.n_s;
+    rep->n_c = P.n_c;
+    rep->n_sub = Np;
+    rep->m0 = S->m0;
+    for (int i = 0; i < S->k; ++i)
+      if (rep->jump) rep->jump[i] = S->jump[i];
+    for (int i = 0; i <= S->k; ++i) {
+      if (rep->err) rep->err[i] = S->err[i];
+      if (rep->t_iter) rep->t_iter[i] = S->t_iter[i];
+    }
+    if (rep->ranks && S->k > 0 && Np > 0)
+      PR_HIP(hipMemcpyAsync(rep->ranks, S->ranks, (size_t)(S->k + 1) * Np * 4,
+                            hipMemcpyDeviceToHost, s));
+    for (int i = 0; i < 5; ++i) rep->t_phase[i] = S->t_phase[i];
+    rep->fine_updates = S->fine_updates;
+  }
+  PR_HIP(hipStreamSynchronize(s));
+  if (rep) rep->seconds = since(S);
+  if (S->fail_st != PR_OK) return S->fail_st;
+  if (S->numeric_bad) return PR_ENUMERIC;
+  return converged(S) ? PR_OK : PR_ENOTCONV;
 }
 
 static size_t footprint(const pr_grid_problem* p, const pr_parareal_opts* o) {
   Plan P = make_plan(p, o);
-  return P.fixed_bytes + P.perF * std::max(P.Np, 1) + P.perS * std::max(P.Np, 1);
+  P.waveF = P.waveS = std::max(P.Np, 1);
+  return P.fixed_bytes + P.perF * P.waveF + P.perS * P.waveS + shared_scratch_bytes(P);
 }
 
 }  // namespace pr
 
-using namespace pr;
+#define PR_TRY(ctx, body)                        \
+  if (!(ctx)) return PR_EINVAL;                  \
+  try {                                          \
+    body                                         \
+  } catch (const pr::Error& e) {                 \
+    (ctx)->err = e.msg;                          \
+    return e.st;                                 \
+  } catch (const std::exception& e) {            \
+    (ctx)->err = e.what();                       \
+    return PR_EDEVICE;                           \
+  }
 
 extern "C" {
 
 pr_status pr_parareal_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
                             const double* u0, double* U_out, pr_report* report, void* stream) {
-  if (!c) return PR_EINVAL;
-  try {
+  PR_TRY(c, {
+    PR_CHECK(U_out != nullptr, "null output");
     PR_HIP(hipSetDevice(c->device));
-    pr::solve(c, prob, opts, u0, U_out, report, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    pr_solve* S = begin_solve(c, prob, opts, u0, U_out, s);
+    pr_status st = PR_OK;
+    try {
+      while (!S->done) iterate_batch(c, {S}, s);
+      st = finish_solve(c, S, U_out, report, s);
+    } catch (...) {
+      release_solve(c, S, false);
+      delete S;
+      throw;
+    }
+    release_solve(c, S, true);
+    delete S;
+    if (st != PR_OK)
+      c->err = st == PR_ENOTCONV ? "max_iter reached above tol" : "NaN or Inf in a parareal jump";
+    return st;
+  })
+}
+
+pr_status pr_solve_begin(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
+                         const double* u0, pr_solve** out, void* stream) {
+  PR_TRY(c, {
+    PR_CHECK(out != nullptr, "null handle");
+    *out = nullptr;
+    PR_HIP(hipSetDevice(c->device));
+    *out = begin_solve(c, prob, opts, u0, nullptr, (hipStream_t)stream);
     return PR_OK;
-  } catch (const pr::Error& e) {
-    c->err = e.msg;
-    return e.st;
-  } catch (const std::exception& e) {
-    c->err = e.what();
-    return PR_EDEVICE;
-  }
+  })
+}
+
+pr_status pr_solve_step_batch(pr_ctx* c, int count, pr_solve* const* solves, int* done,
+                              void* stream) {
+  PR_TRY(c, {
+    PR_CHECK(count >= 0 && (count == 0 || solves), "bad solve list");
+    PR_HIP(hipSetDevice(c->device));
+    std::vector<pr_solve*> ss(solves, solves + count);
+    for (auto* S : ss) PR_CHECK(S != nullptr, "null solve handle");
+    iterate_batch(c, ss, (hipStream_t)stream);
+    if (done)
+      for (int i = 0; i < count; ++i) done[i] = ss[i]->done ? 1 : 0;
+    return PR_OK;
+  })
+}
+
+pr_status pr_solve_state(pr_ctx* c, const pr_solve* S, int j, double* out, void* stream) {
+  PR_TRY(c, {
+    PR_CHECK(S != nullptr && out != nullptr, "null handle or output");
+    PR_CHECK(j >= 0 && j <= S->P.N, "state index out of range");
+    PR_HIP(hipSetDevice(c->device));
+    const double* src = j == 0 ? S->u0 : S->U[S->prev] + (size_t)(j - 1) * S->P.ng;
+    PR_HIP(hipMemcpyAsync(out, src, (size_t)S->P.ng * 8, hipMemcpyDeviceToDevice,
+                          (hipStream_t)stream));
+    return PR_OK;
+  })
+}
+
+int pr_solve_done(const pr_solve* S) { return S ? (S->done ? 1 : 0) : 1; }
+
+size_t pr_solve_bytes(const pr_solve* S) {
+  size_t b = 0;
+  if (S)
+    for (auto& o : S->owned) b += o.second;
+  return b;
+}
+
+pr_status pr_solve_end(pr_ctx* c, pr_solve* S, double* U_out, pr_report* report, void* stream) {
+  PR_TRY(c, {
+    PR_CHECK(S != nullptr, "null solve handle");
+    PR_HIP(hipSetDevice(c->device));
+    pr_status st = PR_OK;
+    try {
+      st = finish_solve(c, S, U_out, report, (hipStream_t)stream);
+    } catch (...) {
+      release_solve(c, S, false);
+      delete S;
+      throw;
+    }
+    release_solve(c, S, true);
+    delete S;
+    return st;
+  })
 }
 
 pr_status pr_footprint(const pr_grid_problem* prob, const pr_parareal_opts* opts, size_t* bytes) {

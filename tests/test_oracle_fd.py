@@ -7,6 +7,7 @@
   with A 1 = 0 and the Laplacian sums to zero: the field's sum is conserved.
 * The ABC flow with A = B = C commutes with the cyclic permutation of axes.
 """
+import itertools
 import math
 
 import numpy as np
@@ -119,6 +120,37 @@ def test_step_count_reading():
     assert fd.snapshot_stride(157) == 10
     assert fd.snapshot_stride(782) == 49
     assert fd.snapshot_stride(500, 5) == 5
+
+
+def test_automatic_step_rule():
+    """dt <= 0 requests min(2e-3, 1.3 / rho) with rho = 12 kappa / h^2 +
+    sum_d max|v_d| / h (values worked out by hand), and the step it gives
+    is inside RK4's stability region for every discrete Fourier mode of a
+    uniform flow (closed-form eigenvalues of L)."""
+    P = W.Problem
+    # n = 256, kappa = 0.1, ABC(1,1,1): rho = 1992.06 + 244.46 -> 5.8126e-4
+    assert abs(fd.auto_dt(P(n=256, kappa=0.1, flow=fd.FLOW_ABC, fp=(1.0, 1.0, 1.0)))
+               - 5.812608166e-4) <= 1e-12
+    # n = 64, kappa = 0.01: rho = 73.57, 1.3 / rho > 2e-3 -> capped
+    assert fd.auto_dt(P(n=64, kappa=0.01, flow=fd.FLOW_ABC, fp=(1.0, 1.0, 1.0))) == 2e-3
+    # Kolmogorov counts only |a| (k_f does not enter): n = 128, kappa = 0.5,
+    # a = -2: rho = 2490.07 + 40.74 -> 5.136689e-4
+    a = fd.auto_dt(P(n=128, kappa=0.5, flow=fd.FLOW_KOLMOGOROV, fp=(-2.0, 1.0, 0.0)))
+    b = fd.auto_dt(P(n=128, kappa=0.5, flow=fd.FLOW_KOLMOGOROV, fp=(-2.0, 4.0, 0.0)))
+    assert a == b and abs(a - 5.136689e-4) <= 1e-10
+    # stability: |P4(dt lambda(k))| <= 1 for every mode, uniform flow
+    n, kappa, c = 16, 0.3, (3.0, -2.0, 1.5)
+    prob = P(n=n, kappa=kappa, flow=fd.FLOW_UNIFORM, fp=c)
+    dt = fd.auto_dt(prob)
+    h = 2 * math.pi / n
+    worst = 0.0
+    for k in itertools.product(range(n), repeat=3):
+        th = [2 * math.pi * kk / n for kk in k]
+        lam = (-(4 * kappa / h ** 2) * sum(math.sin(t / 2) ** 2 for t in th)
+               - 1j * sum(cd * math.sin(t) for cd, t in zip(c, th)) / h)
+        z = dt * lam
+        worst = max(worst, abs(1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24))
+    assert worst <= 1.0
 
 
 def test_snapshots_are_states_at_multiples_of_dM():

@@ -96,22 +96,47 @@ def _canonical_wavevectors(kmax: float) -> np.ndarray:
     return np.array(out, dtype=np.int64)
 
 
-def fourier_field(n: int, seed: int, n_modes: int = 16, kmax: float = 8.0,
-                  L: float = TWO_PI) -> np.ndarray:
-    """Sum of ``n_modes`` distinct random Fourier modes with |k| <= kmax and
-    amplitude |k|^-2: phi = sum_k |k|^-2 cos(k.x + theta_k), theta ~ U[0, 2pi)."""
+def fourier_modes(seed: int, n_modes: int = 16, kmax: float = 8.0):
+    """The seeded draw of fourier_field: wavevectors (n_modes x 3 ints) and
+    phases theta ~ U[0, 2pi)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     ks = _canonical_wavevectors(kmax)
     pick = rng.choice(len(ks), size=n_modes, replace=False)
     theta = rng.uniform(0.0, TWO_PI, size=n_modes)
+    return ks[pick], theta
+
+
+def fourier_field(n: int, seed: int, n_modes: int = 16, kmax: float = 8.0,
+                  L: float = TWO_PI) -> np.ndarray:
+    """Sum of ``n_modes`` distinct random Fourier modes with |k| <= kmax and
+    amplitude |k|^-2: phi = sum_k |k|^-2 cos(k.x + theta_k), theta ~ U[0, 2pi)."""
+    ks, theta = fourier_modes(seed, n_modes, kmax)
     x = np.arange(n, dtype=np.float64) * (L / n)
     X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
     scale = TWO_PI / L
     phi = np.zeros((n, n, n), dtype=np.float64)
-    for idx, th in zip(pick, theta):
-        k = ks[idx].astype(np.float64)
+    for k, th in zip(ks, theta):
+        k = k.astype(np.float64)
         amp = 1.0 / float(k @ k)
         phi += amp * np.cos(scale * (k[0] * X + k[1] * Y + k[2] * Z) + th)
+    return phi
+
+
+def fourier_field_device(n: int, seed: int, device, n_modes: int = 16, kmax: float = 8.0,
+                         L: float = TWO_PI):
+    """fourier_field evaluated with torch on ``device`` (the same seeded
+    draw; values agree with the host version to FP64 rounding). For large
+    grids in serving runs, where host generation would dominate."""
+    import torch
+    ks, theta = fourier_modes(seed, n_modes, kmax)
+    x = torch.arange(n, dtype=torch.float64, device=device) * (L / n)
+    scale = TWO_PI / L
+    phi = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    for k, th in zip(ks, theta):
+        amp = 1.0 / float(k @ k)
+        arg = (scale * float(k[0]) * x).view(n, 1, 1) + (scale * float(k[1]) * x).view(1, n, 1) \
+            + (scale * float(k[2]) * x).view(1, 1, n)
+        phi += amp * torch.cos(arg + float(th))
     return phi
 
 
@@ -199,3 +224,19 @@ def ensemble(count: int = 48, seed_base: int = 4000,
             opts=PararealOpts(T=T, N=N, dt=0.0, cap0=10, cap=20, tol=1e-6),
             seed=seed_base + i, init="fourier"))
     return out
+
+
+def serving_requests(count: int = 256, seed_base: int = 5000,
+                     grids=tuple(range(64, 257, 32))) -> List[Workload]:
+    """Requests of the serving stream: as ``ensemble`` (flow, kappa, T, N,
+    automatic dt, mixed precision) with the grid uniform over 64..256 in
+    steps of 32 and tolerance 1e-6. Request i uses seed seed_base + i."""
+    out = ensemble(count, seed_base, grids)
+    return [dataclasses.replace(w, name=f"request{i}") for i, w in enumerate(out)]
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from 0) of a Poisson stream of ``rate``
+    requests per second: cumulative sums of exponential gaps."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
