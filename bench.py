@@ -39,6 +39,10 @@ def parse():
                     help="time only the batched fine propagator (profiling runs)")
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the serial fine reference (no error history; profiling runs)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the fine step in every stencil tiling (stderr and JSON)")
+    ap.add_argument("--serve-requests", type=int, default=6,
+                    help="requests per serving phase (closed loop, then Poisson); 0 = skip")
     return ap.parse_args()
 
 
@@ -50,9 +54,10 @@ STENCIL_SRC = os.path.join(ROOT, "paper_2601_10981_amd", "csrc", "stencil.hip")
 STENCIL_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_fused_f64_kolmogorov128_batch63.md")
 
 
-def profiled_traffic():
+def profiled_traffic(kernel):
     """HBM bytes per launch of the stencil kernel from the committed PMC
-    summary, or None when the kernel source changed since it was taken."""
+    summary, or None when the kernel source or tiling changed since it was
+    taken."""
     import hashlib
     try:
         sha = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
@@ -61,7 +66,7 @@ def profiled_traffic():
             if ":" in line and not line.startswith(("|", "#", " ")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-        if fields.get("source_sha256_16") == sha:
+        if fields.get("source_sha256_16") == sha and fields.get("kernel") == kernel:
             return float(fields["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         pass
@@ -91,6 +96,40 @@ def cpu_baseline(w, budget_s):
                       f"(oracle fine propagator, numpy FP64, {el:.1f} s)"}
 
 
+def serving_sample(pr, ctx, budget, k):
+    """The serving stream: requests drawn as the ensemble (grid 64..256 in
+    steps of 32, random flow, kappa, horizon, N; tolerance 1e-6; mixed
+    precision). Phase 1 submits k requests at once (closed loop) to measure
+    capacity; phase 2 feeds the next k as a Poisson stream at 0.7 x that
+    capacity and reports arrival-to-result latency."""
+    import workloads as W
+    from paper_2601_10981_amd import serving
+    ws = W.serving_requests(2 * k)
+
+    def req(i, arrival):
+        w = ws[i]
+        return serving.Request(i, float(arrival), pr.problem_of(w.problem), w.opts,
+                               lambda w=w: W.fourier_field_device(w.problem.n, w.seed,
+                                                                  "cuda").reshape(-1))
+    log(f"serving: closed loop, {k} requests")
+    closed = serving.serve(ctx, [req(i, 0.0) for i in range(k)], budget)
+    capacity = k / closed.wall
+    rate = 0.7 * capacity
+    arrivals = W.poisson_arrivals(k, rate, seed=5)
+    log(f"serving: Poisson at {rate:.4f}/s, {k} requests")
+    openl = serving.serve(ctx, [req(k + i, arrivals[i]) for i in range(k)], budget)
+    lat = openl.latencies()
+    P = serving.ServeStats.percentile
+    return {"requests_per_phase": k, "closed_loop_solves_per_s": round(capacity, 4),
+            "rate_per_s": round(rate, 4), "p50_latency_s": round(P(lat, 50), 3),
+            "p99_latency_s": round(P(lat, 99), 3), "solves_per_s": round(k / openl.wall, 4),
+            "mean_live": round(openl.mean_live, 2), "max_live": openl.max_live,
+            "grids": [c.n for c in sorted(openl.completed, key=lambda c: c.rid)],
+            "iters": [c.iters for c in sorted(openl.completed, key=lambda c: c.rid)],
+            "sample": f"{k} closed-loop then {k} Poisson requests of the serving stream "
+                      f"(seeds 5000..{5000 + 2 * k - 1}); no warm-up exclusion"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,7 +147,9 @@ def main():
     n = w.problem.n
     ng = n ** 3
     N = opts.N
-    ctx = pr.Context(0)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+    ctx = pr.Context(0, budget_bytes=budget)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     u0 = torch.from_numpy(W.initial_field(w).reshape(-1).copy()).cuda()
@@ -159,12 +200,28 @@ def main():
     bytes_per_launch = 16 * ng * B
     achieved = bytes_per_launch / avg_launch_s / 1e9
     stencil_gpts = B * ng * n_f / (fine_ms * 1e-3) / 1e9
+    tiling = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
+    kname = "k_rk4_fused<double,%d,%d,%d>" % tiling if tiling else "k_rk4_fused<double>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(),
-                "kernel": "k_rk4_fused<double>", "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "bytes_per_launch": bytes_per_launch,
-                "tile_cfg": os.environ.get("PR_FUSED_CFG", "1")}
+                "traffic": profiled_traffic(kname),
+                "kernel": kname, "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "bytes_per_launch": bytes_per_launch}
+    if args.sweep:
+        sweep = {}
+        for cfg in range(7):
+            os.environ["PR_FUSED_CFG"] = str(cfg)
+            pr.pr_fine_propagate(ctx, items)
+            e0.record(stream)
+            pr.pr_fine_propagate(ctx, items)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
+            sweep["%dx%dx%d" % t] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
+            log(f"  tiling {t}: {sweep['%dx%dx%d' % t]} GPts/s")
+        del os.environ["PR_FUSED_CFG"]
+        roofline["sweep_gpts"] = sweep
     del xin, xout
     if args.stencil_only:
         # calibration copy of known size for the PMC byte counters: 1 GiB read
@@ -231,6 +288,10 @@ def main():
         "m0": rep.m0,
         "roofline": roofline,
     }
+    if args.serve_requests > 0:
+        del U_ref
+        torch.cuda.empty_cache()
+        out["serving"] = serving_sample(pr, ctx, budget, args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)

@@ -110,6 +110,15 @@ typedef struct {
   void* snaps;
 } pr_fine_item;
 pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, void* stream);
+/* Tiling of the fused RK4 stencil. Every tiling gives bitwise the same
+ * values; the context picks one per (precision, largest n of the batch,
+ * floor(log2(batch))) by timing one step of the first such batch in each
+ * candidate tiling (that first call synchronises `stream`). The environment
+ * variable PR_FUSED_CFG=<index> forces one. pr_fine_tuned reports the
+ * workgroup's output tile (tile_y x tile_z points of the (y, z) plane) and
+ * thread count chosen for a key; PR_EINVAL if no batch of that key ran yet. */
+pr_status pr_fine_tuned(const pr_ctx* ctx, int precision, int n, int batch, int* tile_y,
+                        int* tile_z, int* threads);
 
 /* ---------------------------------------------------------------------------
  * POD_Mode (Algorithm 1; Sec. 3.2 Case I and Case II, eq. W^k_n): modes of

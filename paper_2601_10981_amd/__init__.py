@@ -17,7 +17,7 @@ from typing import List, Optional, Sequence
 from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
 
-__all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_gram", "pr_pod_build",
+__all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
            "pr_coarse_propagate", "pr_parareal_solve", "pr_footprint", "pr_solve_begin",
            "pr_solve_step_batch", "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end",
            "SolveHandle", "costmodel"]
@@ -145,6 +145,17 @@ def pr_fine_propagate(ctx: Context, items: Sequence[dict], stream=None):
             _check_dev(snaps, _fdtype(prob), ng * (int(it["n_steps"]) // se + 1), "snaps")
         arr[i].snaps = _ptr(snaps)
     ctx.check(ctx.lib.pr_fine_propagate(ctx.h, len(items), arr, _stream(stream)))
+
+
+def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int):
+    """(tile_y, tile_z, threads) of the fused stencil tiling chosen for a
+    batch key, or None if no such batch ran yet."""
+    ty, tz, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    st = ctx.lib.pr_fine_tuned(ctx.h, int(precision), int(n), int(batch), ctypes.byref(ty),
+                               ctypes.byref(tz), ctypes.byref(nt))
+    if st != L.PR_OK:
+        return None
+    return ty.value, tz.value, nt.value
 
 
 def pr_gram(ctx: Context, prob: L.pr_grid_problem, W, ncols: int, G_out=None, stream=None):

@@ -58,7 +58,7 @@ class pr_report(Structure):
 
 
 EXPORTS = ["pr_ctx_create", "pr_ctx_destroy", "pr_last_error", "pr_ctx_scratch_bytes",
-           "pr_fine_propagate", "pr_gram", "pr_pod_build", "pr_coarse_propagate",
+           "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build", "pr_coarse_propagate",
            "pr_parareal_solve", "pr_footprint", "pr_solve_begin", "pr_solve_step_batch",
            "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end"]
 
@@ -92,6 +92,9 @@ def load(path: str = LIB_PATH):
     lib.pr_ctx_scratch_bytes.restype = c_size_t
     lib.pr_fine_propagate.argtypes = [c_void_p, c_int, POINTER(pr_fine_item), c_void_p]
     lib.pr_fine_propagate.restype = c_int
+    lib.pr_fine_tuned.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int),
+                                  POINTER(c_int)]
+    lib.pr_fine_tuned.restype = c_int
     lib.pr_gram.argtypes = [c_void_p, POINTER(pr_grid_problem), c_void_p, c_int, c_void_p,
                             c_void_p]
     lib.pr_gram.restype = c_int

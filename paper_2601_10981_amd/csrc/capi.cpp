@@ -253,14 +253,14 @@ int gram_chunk_rows(long long nrows) {
 
 // ---------------------------------------------------------------------------
 // fine propagator
-// Tile configuration of the fused stencil (PR_FUSED_CFG overrides: 0 = 32 x 32
-// tiles of 512 threads, 1 = 16 x 32 tiles of 256 threads).
-static int fine_cfg() {
-  static int cfg = [] {
-    const char* e = getenv("PR_FUSED_CFG");
-    return (e && (e[0] == '0' || e[0] == '1')) ? e[0] - '0' : 1;
-  }();
-  return cfg;
+// Tile configuration of the fused stencil: PR_FUSED_CFG=<index> forces one;
+// otherwise each (precision, largest grid, batch size class) is tuned once
+// per context (see tune_fine).
+static int forced_cfg() {
+  const char* e = getenv("PR_FUSED_CFG");
+  if (!e || !*e) return -1;
+  const int v = atoi(e);
+  return (v >= 0 && v < kNumFusedCfgs) ? v : -1;
 }
 
 // x-chunk length of the fused stencil: chunks of up to 64 planes, halved
@@ -281,6 +281,81 @@ static int fine_chunk(const std::vector<FineWork>& items, int cfg) {
   return xc;
 }
 
+// Descriptors of one launch shape: per-item buffers fixed in `base`, tiles
+// of configuration cfg filled in. Returns the number of workgroup tiles.
+template <typename T>
+static long long shape_descs(const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
+                             int cfg) {
+  const int xc = fine_chunk(items, cfg);
+  long long tiles = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int n = items[i].prob->n;
+    d[i].tiles_y = (n + fused_ty(cfg) - 1) / fused_ty(cfg);
+    d[i].tiles_z = (n + fused_tz(cfg) - 1) / fused_tz(cfg);
+    d[i].xc = std::min(xc, n);
+    d[i].chunks_x = (n + d[i].xc - 1) / d[i].xc;
+    d[i].tile_begin = tiles;
+    tiles += (long long)d[i].tiles_y * d[i].tiles_z * d[i].chunks_x;
+  }
+  return tiles;
+}
+
+template <typename T>
+static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step, int cfg,
+                        hipStream_t s) {
+  if (std::is_same<T, float>::value)
+    launch_fine_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, s);
+  else
+    launch_fine_step_f64((const FineDesc<double>*)d, nd, tiles, step, cfg, s);
+}
+
+// Tuning key: value size, largest grid, batch size class floor(log2(batch)).
+static std::string tune_key(int value_bytes, int nmax, int batch) {
+  int cls = 0;
+  while ((1LL << (cls + 1)) <= batch) ++cls;
+  char key[64];
+  snprintf(key, sizeof key, "%d|%d|%d", value_bytes, nmax, cls);
+  return key;
+}
+
+// Autotuner: time step 0 of the actual batch in every configuration (one
+// warm-up and one timed launch each) and keep the fastest for this key.
+// Step 0 reads the inputs and writes buffers no other step 0 reads, so
+// repeating it is harmless; every configuration gives bitwise the same
+// values. Synchronises `s` once, at the first batch of a key.
+template <typename T>
+static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
+                     hipStream_t s) {
+  int nmax = 0;
+  for (auto& w : items) nmax = std::max(nmax, w.prob->n);
+  const std::string key = tune_key((int)sizeof(T), nmax, (int)items.size());
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) return it->second;
+  hipEvent_t e0 = event_get(c), e1 = event_get(c);
+  float best_ms = 0;
+  int best = 1;
+  for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg) {
+    const long long tiles = shape_descs<T>(items, d, cfg);
+    FineDesc<T>* dd = stage_push(c, d);
+    stage_flush(c, s);
+    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
+    PR_HIP(hipEventRecord(e0, s));
+    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
+    PR_HIP(hipEventRecord(e1, s));
+    PR_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    PR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (cfg == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cfg;
+    }
+  }
+  event_put(c, e0);
+  event_put(c, e1);
+  c->tuned[key] = best;
+  return best;
+}
+
 template <typename T>
 static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
                        const std::string& tag) {
@@ -289,15 +364,11 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_
   size_t total = 0;
   for (auto& w : items) total += (size_t)ngrid(*w.prob) * nwork * sizeof(T);
   char* base = (char*)scratch(c, tag + "_w", total);
-  const int cfg = fine_cfg();
-  const int xc = fine_chunk(items, cfg);
   std::vector<FineDesc<T>> descs;
-  long long tiles = 0;
   int max_steps = 0;
   size_t off = 0;
   for (auto& w : items) {
     const long long ng = ngrid(*w.prob);
-    const int n = w.prob->n;
     FineDesc<T> d{};
     d.g = geom_of(c, *w.prob);
     T* work = (T*)(base + off);
@@ -327,21 +398,20 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_
       PR_HIP(hipMemcpyAsync(w.snaps, d.first_src, ng * sizeof(T), hipMemcpyDeviceToDevice, s));
     d.n_steps = w.n_steps;
     d.dt = w.dt;
-    d.tiles_y = (n + fused_ty(cfg) - 1) / fused_ty(cfg);
-    d.tiles_z = (n + fused_tz(cfg) - 1) / fused_tz(cfg);
-    d.xc = std::min(xc, n);
-    d.chunks_x = (n + d.xc - 1) / d.xc;
-    d.tile_begin = tiles;
-    tiles += (long long)d.tiles_y * d.tiles_z * d.chunks_x;
     max_steps = std::max(max_steps, w.n_steps);
     descs.push_back(d);
   }
-  FineDesc<T>* dd = stage_push(c, descs);
-  stage_flush(c, s);
-  if (f32)
-    launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
-  else
-    launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+  if (max_steps > 0) {
+    int cfg = forced_cfg();
+    if (cfg < 0) cfg = tune_fine<T>(c, items, descs, s);
+    const long long tiles = shape_descs<T>(items, descs, cfg);
+    FineDesc<T>* dd = stage_push(c, descs);
+    stage_flush(c, s);
+    if (f32)
+      launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+    else
+      launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+  }
   if (f32)
     for (size_t i = 0; i < items.size(); ++i)
       launch_convert_f32_to_f64(items[i].n_steps > 0 ? (const float*)descs[i].buf[0]
@@ -870,6 +940,21 @@ void pr_ctx_destroy(pr_ctx* c) {
   if (c->host_scalars) (void)hipHostFree(c->host_scalars);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
+}
+
+pr_status pr_fine_tuned(const pr_ctx* c, int precision, int n, int batch, int* tile_y,
+                        int* tile_z, int* threads) {
+  if (!c || batch < 1 || (precision != PR_F64 && precision != PR_MIXED)) return PR_EINVAL;
+  int cfg = forced_cfg();
+  if (cfg < 0) {
+    auto it = c->tuned.find(tune_key(precision == PR_MIXED ? 4 : 8, n, batch));
+    if (it == c->tuned.end()) return PR_EINVAL;
+    cfg = it->second;
+  }
+  if (tile_y) *tile_y = kFusedCfgs[cfg].ty;
+  if (tile_z) *tile_z = kFusedCfgs[cfg].tz;
+  if (threads) *threads = kFusedCfgs[cfg].nt;
+  return PR_OK;
 }
 
 const char* pr_last_error(const pr_ctx* c) { return c ? c->err.c_str() : "null context"; }

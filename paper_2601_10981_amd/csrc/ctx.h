@@ -25,6 +25,7 @@ struct pr_ctx {
   // (counted in `used`; given back when the budget needs the room).
   std::multimap<size_t, void*> pool;
   std::map<std::string, void*> tables;   // velocity tables by problem key
+  std::map<std::string, int> tuned;      // fused-stencil configuration by batch key
 
   // Descriptor staging: a ring of pinned host slots mirrored by device slots.
   static constexpr int kSlots = 8;

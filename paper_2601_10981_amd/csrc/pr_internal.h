@@ -101,9 +101,19 @@ struct FineDesc {
 };
 constexpr int kFusedHalo = 4;      // one halo layer per RK4 stage
 constexpr int kMaxChunk = 64;      // x planes per fused-stencil workgroup (at most)
-// output tile (y, z) of fused-stencil configuration cfg
-inline int fused_ty(int cfg) { return cfg == 1 ? 16 : 32; }
-inline int fused_tz(int) { return 32; }
+// Tile configurations of the fused stencil: output tile TY x TZ of the
+// (y, z) plane per workgroup of NT threads. Every configuration computes
+// bitwise the same values (each point's arithmetic does not depend on the
+// tiling), so the choice is a pure performance knob.
+struct FusedCfg {
+  int ty, tz, nt;
+};
+constexpr int kNumFusedCfgs = 7;
+constexpr FusedCfg kFusedCfgs[kNumFusedCfgs] = {
+    {32, 32, 512}, {16, 32, 256}, {16, 32, 512}, {32, 32, 1024},
+    {8, 32, 256},  {16, 64, 512}, {8, 64, 512}};
+inline int fused_ty(int cfg) { return kFusedCfgs[cfg].ty; }
+inline int fused_tz(int cfg) { return kFusedCfgs[cfg].tz; }
 
 // ---- L applied to basis columns -------------------------------------------
 template <typename T>

@@ -254,18 +254,29 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
   }
 }
 
-// Tile configurations of the fused step (index = FineDesc::cfg).
+// Launch of one fused step in tile configuration cfg (kFusedCfgs).
+template <typename T, int TY, int TZ, int NT>
+static void launch_cfg(const FineDesc<T>* d, int nd, long long total, int step, hipStream_t s) {
+  const long long g8 = (total + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_rk4_fused<T, TY, TZ, NT>), dim3((unsigned)g8), dim3(NT), 0, s, d, nd, step,
+                     total, g8 / 8);
+}
+
 template <typename T>
 static void launch_step_impl(const FineDesc<T>* d, int nd, long long total, int step, int cfg,
                              hipStream_t s) {
   if (total <= 0) return;
-  const long long g8 = (total + 7) / 8 * 8;
-  if (cfg == 1)
-    hipLaunchKernelGGL((k_rk4_fused<T, 16, 32, 256>), dim3((unsigned)g8), dim3(256), 0, s, d, nd,
-                       step, total, g8 / 8);
-  else
-    hipLaunchKernelGGL((k_rk4_fused<T, 32, 32, 512>), dim3((unsigned)g8), dim3(512), 0, s, d, nd,
-                       step, total, g8 / 8);
+  static_assert(kNumFusedCfgs == 7, "one case per configuration");
+  switch (cfg) {
+    case 0: launch_cfg<T, 32, 32, 512>(d, nd, total, step, s); break;
+    case 1: launch_cfg<T, 16, 32, 256>(d, nd, total, step, s); break;
+    case 2: launch_cfg<T, 16, 32, 512>(d, nd, total, step, s); break;
+    case 3: launch_cfg<T, 32, 32, 1024>(d, nd, total, step, s); break;
+    case 4: launch_cfg<T, 8, 32, 256>(d, nd, total, step, s); break;
+    case 5: launch_cfg<T, 16, 64, 512>(d, nd, total, step, s); break;
+    case 6: launch_cfg<T, 8, 64, 512>(d, nd, total, step, s); break;
+    default: fail(PR_EINVAL, "unknown fused stencil configuration");
+  }
 }
 
 void launch_fine_step_f64(const FineDesc<double>* d, int nd, long long total, int step, int cfg,

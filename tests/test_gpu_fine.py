@@ -88,6 +88,23 @@ def test_fine_batch_uneven_is_bitwise_batch_invariant(ctx):
         assert rel_l2(to_np(outs_b[i]), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
+def test_fine_every_tile_configuration_is_bitwise_identical(ctx, prec, monkeypatch):
+    """Each point's arithmetic is independent of the tiling, so every tile
+    configuration the autotuner may pick gives the same bits (the first
+    batch of each key also runs the tuner itself)."""
+    say(f"fine tile configurations prec={prec}")
+    cases = CASES + [(40, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.05, 0.005, 3, 1, 6)]
+    ref_outs, ref_snaps = _run(ctx, cases, prec)          # autotuned
+    for cfg in range(7):
+        monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
+        outs, snaps = _run(ctx, cases, prec)
+        for i in range(len(cases)):
+            assert np.array_equal(to_np(outs[i]), to_np(ref_outs[i])), (cfg, i)
+            assert np.array_equal(to_np(snaps[i]), to_np(ref_snaps[i])), (cfg, i)
+    monkeypatch.delenv("PR_FUSED_CFG")
+
+
 def test_fine_run_to_run_bitwise(ctx):
     a, _ = _run(ctx, CASES[:2])
     b, _ = _run(ctx, CASES[:2])
