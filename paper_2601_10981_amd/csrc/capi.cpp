@@ -234,6 +234,8 @@ Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
   const double h = spacing(p);
   Geom g;
   g.n = n;
+  g.xonly = (p.flow == PR_FLOW_KOLMOGOROV) ||
+            (p.flow == PR_FLOW_UNIFORM && p.fp[1] == 0.0 && p.fp[2] == 0.0);
   g.c_lap = p.kappa / (h * h);
   g.tab64 = (const double*)dev;
   g.tab32 = (const float*)((char*)dev + 6 * (size_t)n * 8);
@@ -309,6 +311,8 @@ static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step,
     launch_fine_step_f64((const FineDesc<double>*)d, nd, tiles, step, cfg, s);
 }
 
+constexpr int kTuneReps = 3;
+
 // Tuning key: value size, largest grid, batch size class floor(log2(batch)).
 static std::string tune_key(int value_bytes, int nmax, int batch) {
   int cls = 0;
@@ -319,7 +323,8 @@ static std::string tune_key(int value_bytes, int nmax, int batch) {
 }
 
 // Autotuner: time step 0 of the actual batch in every configuration (one
-// warm-up and one timed launch each) and keep the fastest for this key.
+// warm-up and kTuneReps timed launches each) and keep the fastest for this
+// key.
 // Step 0 reads the inputs and writes buffers no other step 0 reads, so
 // repeating it is harmless; every configuration gives bitwise the same
 // values. Synchronises `s` once, at the first batch of a key.
@@ -340,7 +345,7 @@ static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<
     stage_flush(c, s);
     launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
     PR_HIP(hipEventRecord(e0, s));
-    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
+    for (int r = 0; r < kTuneReps; ++r) launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
     PR_HIP(hipEventRecord(e1, s));
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0;

@@ -68,6 +68,7 @@ __device__ __forceinline__ PR_GLOBAL T* gptr(T* p) {
 // tab64 holds them in double, tab32 in float (for the FP32 stencil).
 struct Geom {
   int n;
+  int xonly;             // velocity has only an x component (v_y = v_z = 0)
   double c_lap;          // kappa / h^2
   const double* tab64;   // 6 n doubles
   const float* tab32;    // 6 n floats

@@ -10,14 +10,13 @@
 //
 // k_rk4_fused runs all four stages of one step in one pass over HBM (read y,
 // write y_new: 2 x s_f bytes per point instead of 11 x s_f for four separate
-// sweeps). A workgroup owns a 32 x 32 tile of the (y, z) plane and marches
-// along x through a chunk of planes. Stage s is evaluated on the tile grown
-// by 4 - s halo layers, so the 4-layer halo of y suffices; the stages form a
-// skewed pipeline along x (at march step t: w1 at plane t + 3, w2 at t + 2,
-// w3 at t + 1, y_new at t). Each thread keeps the x - 1, x, x + 1 values of
-// every stage for its columns in registers and exchanges the current plane of
-// each stage through LDS for the y and z neighbours. Workgroups are mapped to
-// XCDs in contiguous tile ranges so neighbouring tiles share an L2.
+// sweeps). A workgroup owns a tile of the (y, z) plane (the tiling is a
+// template parameter, chosen per batch by timing) and marches along x
+// through a chunk of planes. Stage s is evaluated on the tile grown by 4 - s
+// halo layers, so the 4-layer halo of y suffices; the stages form a skewed
+// pipeline along x (at march step t: w1 at plane t + 3, w2 at t + 2, w3 at
+// t + 1, y_new at t). Workgroups are mapped to XCDs in contiguous tile ranges
+// so neighbouring tiles share an L2.
 #include "pr_internal.h"
 
 namespace pr {
@@ -80,11 +79,16 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
 
 // ---------------------------------------------------------------------------
 // Fused RK4 step.
-template <typename T, int RZ>
+
+// L at one column of a stage plane: x neighbours from registers, y and z
+// neighbours from the LDS plane (row-major, RZ columns per row). XONLY: the
+// velocity has only an x component (v_y = v_z = 0), whose terms are skipped.
+template <typename T, int RZ, bool XONLY>
 __device__ __forceinline__ T lop(T xm, T c, T xp, const T* __restrict__ pl, int i, T clap,
                                  T vx, T vy, T vz) {
   const T ym = pl[i - RZ], yp = pl[i + RZ], zm = pl[i - 1], zp = pl[i + 1];
   const T lap = ((xp + xm) + (yp + ym) + (zp + zm)) - (T)6 * c;
+  if (XONLY) return clap * lap - vx * (xp - xm);
   const T adv = vx * (xp - xm) + vy * (yp - ym) + vz * (zp - zm);
   return clap * lap - adv;
 }
@@ -94,31 +98,65 @@ __device__ __forceinline__ int wrapi(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// TY x TZ output tile per workgroup of NT threads; the region with the
-// 4-layer halo has (TY + 8) x (TZ + 8) columns, SL per thread.
-template <typename T, int TY, int TZ, int NT>
-__global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
-                                                  int step, long long total, long long per_xcd) {
+// Column p of a workgroup's (TY + 2H) x (TZ + 2H) region in ring order: the
+// TY x TZ interior first (row-major), then the rings at distance 1, 2, ..., H
+// from it (each row-major). Region coordinates (ry, rz) and ring level.
+// Stage s of the fused step is needed on levels <= H - s, so with this order
+// whole waves skip the stages none of their columns needs.
+template <int TY, int TZ>
+__device__ __forceinline__ void ring_col(int p, int& ry, int& rz, int& lev) {
+  constexpr int H = kFusedHalo;
+  if (p < TY * TZ) {
+    ry = H + p / TZ;
+    rz = H + p % TZ;
+    lev = 0;
+    return;
+  }
+  int start = TY * TZ;
+#pragma unroll
+  for (int L = 1; L <= H; ++L) {
+    const int WY = TY + 2 * L, WZ = TZ + 2 * L;
+    const int ring = WY * WZ - (WY - 2) * (WZ - 2);
+    if (p < start + ring) {
+      int q = p - start, by, bz;
+      if (q < WZ) {
+        by = 0;
+        bz = q;
+      } else if (q < WZ + 2 * (WY - 2)) {
+        q -= WZ;
+        by = 1 + q / 2;
+        bz = (q & 1) ? WZ - 1 : 0;
+      } else {
+        by = WY - 1;
+        bz = q - WZ - 2 * (WY - 2);
+      }
+      ry = by + H - L;
+      rz = bz + H - L;
+      lev = L;
+      return;
+    }
+    start += ring;
+  }
+  ry = rz = 0;
+  lev = 99;   // beyond the region (no column)
+}
+
+// One fused RK4 step of one workgroup tile. The stages form a skewed
+// pipeline along x: at march step tt, w1 at plane tt + 3, w2 at tt + 2, w3 at
+// tt + 1 and y_new at tt. Each thread holds SL columns (slots); for each it
+// keeps the x - 1, x, x + 1 values of every stage in registers and exchanges
+// the current plane of every stage through LDS for the y and z neighbours.
+// Slots wholly inside the interior are known at compile time and skip the
+// ring tests.
+template <typename T, int TY, int TZ, int NT, bool XONLY>
+__device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long long lt,
+                                         T (*lds)[4][(TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo)],
+                                         T (*vxt)[kMaxChunk + 10]) {
   constexpr int H = kFusedHalo;
   constexpr int RY = TY + 2 * H, RZ = TZ + 2 * H;
   constexpr int NR = RY * RZ;
   constexpr int SL = (NR + NT - 1) / NT;
-  // two sets of the four stage planes, alternating per march step, so one
-  // barrier per step suffices (a set is rewritten two steps later, after
-  // every thread has passed the intermediate barrier)
-  __shared__ T lds[2][4][NR];
-  // v_y(x) and v_z(x) parts of the velocity for the chunk's planes
-  // x0 - 6 .. x0 + kMaxChunk + 3
-  __shared__ T vxt[2][kMaxChunk + 10];
-
-  // blocks b, b + 8, b + 16, ... run on one XCD: give them consecutive tiles
-  const long long b = blockIdx.x;
-  const long long t = (b % 8) * per_xcd + b / 8;
-  if (t >= total) return;
-  const int f = find_desc(descs, nd, t);
-  const FineDesc<T>& d = descs[f];
-  if (step >= d.n_steps) return;
-  const long long lt = t - d.tile_begin;
+  constexpr int NI = TY * TZ;
   const int tz = (int)(lt % d.tiles_z);
   const long long rest = lt / d.tiles_z;
   const int ty = (int)(rest % d.tiles_y);
@@ -138,36 +176,31 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
   const T dt = (T)d.dt;
   const T c1 = dt * (T)0.25, c2 = dt / (T)3, c3 = dt * (T)0.5, c4 = dt;
 
+  int ci[SL];    // row-major LDS index of the slot's column
   int off[SL];   // gy * n + gz of the slot's column
-  int lev[SL];   // ring distance from the output tile (0 inside), 99 = no column
+  int lev[SL];   // ring level (0 = interior), 99 = no column
   bool outp[SL];
   T vx[SL], vyz[SL], vzy[SL];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
-    const int c = threadIdx.x + s * NT;
-    lev[s] = 99;
-    outp[s] = false;
-    off[s] = 0;
-    vx[s] = vyz[s] = vzy[s] = (T)0;
-    if (c < NR) {
-      const int dy = c / RZ - H, dz = c % RZ - H;
-      const int ly = dy < 0 ? -dy : (dy >= TY ? dy - TY + 1 : 0);
-      const int lz = dz < 0 ? -dz : (dz >= TZ ? dz - TZ + 1 : 0);
-      lev[s] = max(ly, lz);
-      outp[s] = lev[s] == 0 && y0 + dy < n && z0 + dz < n;
-      const int gy = wrapi(y0 + dy, n), gz = wrapi(z0 + dz, n);
-      off[s] = gy * n + gz;
-      vx[s] = tab[gy] + tab[n + gz];
-      vyz[s] = tab[3 * n + gz];
-      vzy[s] = tab[5 * n + gy];
+    int ry, rz, lv;
+    ring_col<TY, TZ>((int)threadIdx.x + s * NT, ry, rz, lv);
+    lev[s] = lv;
+    ci[s] = ry * RZ + rz;
+    const int dy = ry - H, dz = rz - H;
+    outp[s] = lv == 0 && y0 + dy < n && z0 + dz < n;
+    const int gy = wrapi(y0 + dy, n), gz = wrapi(z0 + dz, n);
+    off[s] = lv <= H ? gy * n + gz : 0;
+    vx[s] = tab[gy] + tab[n + gz];
+    vyz[s] = XONLY ? (T)0 : tab[3 * n + gz];
+    vzy[s] = XONLY ? (T)0 : tab[5 * n + gy];
+  }
+  if (!XONLY)
+    for (int i = threadIdx.x; i < x1 - x0 + 10; i += NT) {
+      const int x = wrapi(x0 - 6 + i, n);
+      vxt[0][i] = tab[2 * n + x];
+      vxt[1][i] = tab[4 * n + x];
     }
-  }
-
-  for (int i = threadIdx.x; i < x1 - x0 + 10; i += NT) {
-    const int x = wrapi(x0 - 6 + i, n);
-    vxt[0][i] = tab[2 * n + x];
-    vxt[1][i] = tab[4 * n + x];
-  }
 
   // Y[s][k] = y(tt + k), W1[s][k] = w1(tt + 1 + k), W2[s][k] = w2(tt + k),
   // W3[s][k] = w3(tt - 1 + k); Yn = y(tt + 5), prefetched one step ahead.
@@ -193,51 +226,54 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
       Yn[s] = src[pc + off[s]];
     }
   }
+  // plane offsets of x = tt + 5 (load) and x = tt (store), wrapped by
+  // stepping instead of dividing
+  long long o5 = (long long)wrapi(x0 - 1, n) * plane;
+  long long od = (long long)wrapi(x0 - 6, n) * plane;
+  const long long ng = plane * n;
 
-  // march step tt: w1 at plane tt + 3, w2 at tt + 2, w3 at tt + 1, y_new at tt
   __syncthreads();   // vxt visible
   for (int tt = x0 - 6; tt < x1; ++tt) {
-    const long long p5 = (long long)wrapi(tt + 5, n) * plane;
     T (*pl)[NR] = lds[(tt - x0) & 1];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      const int c = threadIdx.x + s * NT;
+      const bool inner = (s + 1) * NT <= NI;
       Y[s][4] = Yn[s];
-      Yn[s] = src[p5 + off[s]];   // consumed next step
-      if (c < NR) {
-        pl[0][c] = Y[s][3];
-        pl[1][c] = W1[s][1];
-        pl[2][c] = W2[s][1];
-        pl[3][c] = W3[s][1];
-      }
+      Yn[s] = src[o5 + off[s]];   // consumed next step
+      if (inner || lev[s] <= H) pl[0][ci[s]] = Y[s][3];
+      if (inner || lev[s] <= H - 1) pl[1][ci[s]] = W1[s][1];
+      if (inner || lev[s] <= H - 2) pl[2][ci[s]] = W2[s][1];
+      if (inner || lev[s] <= H - 3) pl[3][ci[s]] = W3[s][1];
     }
     __syncthreads();
-    const int xd = wrapi(tt, n);
     const int iv = tt - (x0 - 6);
-    const T vy_a = vxt[0][iv + 3], vz_a = vxt[1][iv + 3];
-    const T vy_b = vxt[0][iv + 2], vz_b = vxt[1][iv + 2];
-    const T vy_c = vxt[0][iv + 1], vz_c = vxt[1][iv + 1];
-    const T vy_d = vxt[0][iv], vz_d = vxt[1][iv];
+    T vy_a = 0, vz_a = 0, vy_b = 0, vz_b = 0, vy_c = 0, vz_c = 0, vy_d = 0, vz_d = 0;
+    if (!XONLY) {
+      vy_a = vxt[0][iv + 3]; vz_a = vxt[1][iv + 3];
+      vy_b = vxt[0][iv + 2]; vz_b = vxt[1][iv + 2];
+      vy_c = vxt[0][iv + 1]; vz_c = vxt[1][iv + 1];
+      vy_d = vxt[0][iv];     vz_d = vxt[1][iv];
+    }
     const bool s2 = tt >= x0 - 4, s3 = tt >= x0 - 2, s4 = tt >= x0;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
-      const int c = threadIdx.x + s * NT;
+      const bool inner = (s + 1) * NT <= NI;
+      const int c = ci[s];
       const int lv = lev[s];
-      if (lv <= 3)
-        W1[s][2] = Y[s][3] + c1 * lop<T, RZ>(Y[s][2], Y[s][3], Y[s][4], pl[0], c, clap, vx[s],
-                                             vy_a + vyz[s], vz_a + vzy[s]);
-      if (s2 && lv <= 2)
-        W2[s][2] = Y[s][2] + c2 * lop<T, RZ>(W1[s][0], W1[s][1], W1[s][2], pl[1], c, clap, vx[s],
-                                             vy_b + vyz[s], vz_b + vzy[s]);
-      if (s3 && lv <= 1)
-        W3[s][2] = Y[s][1] + c3 * lop<T, RZ>(W2[s][0], W2[s][1], W2[s][2], pl[2], c, clap, vx[s],
-                                             vy_c + vyz[s], vz_c + vzy[s]);
+      if (inner || lv <= H - 1)
+        W1[s][2] = Y[s][3] + c1 * lop<T, RZ, XONLY>(Y[s][2], Y[s][3], Y[s][4], pl[0], c, clap,
+                                                    vx[s], vy_a + vyz[s], vz_a + vzy[s]);
+      if (s2 && (inner || lv <= H - 2))
+        W2[s][2] = Y[s][2] + c2 * lop<T, RZ, XONLY>(W1[s][0], W1[s][1], W1[s][2], pl[1], c, clap,
+                                                    vx[s], vy_b + vyz[s], vz_b + vzy[s]);
+      if (s3 && (inner || lv <= H - 3))
+        W3[s][2] = Y[s][1] + c3 * lop<T, RZ, XONLY>(W2[s][0], W2[s][1], W2[s][2], pl[2], c, clap,
+                                                    vx[s], vy_c + vyz[s], vz_c + vzy[s]);
       if (s4 && outp[s]) {
-        const T yn = Y[s][0] + c4 * lop<T, RZ>(W3[s][0], W3[s][1], W3[s][2], pl[3], c, clap,
-                                               vx[s], vy_d + vyz[s], vz_d + vzy[s]);
-        const long long gi = (long long)xd * plane + off[s];
-        dst[gi] = yn;
-        if (snap) snap[gi] = yn;
+        const T yn = Y[s][0] + c4 * lop<T, RZ, XONLY>(W3[s][0], W3[s][1], W3[s][2], pl[3], c,
+                                                      clap, vx[s], vy_d + vyz[s], vz_d + vzy[s]);
+        dst[od + off[s]] = yn;
+        if (snap) snap[od + off[s]] = yn;
       }
     }
 #pragma unroll
@@ -251,7 +287,38 @@ __global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict_
       W3[s][0] = W3[s][1];
       W3[s][1] = W3[s][2];
     }
+    o5 += plane;
+    if (o5 == ng) o5 = 0;
+    od += plane;
+    if (od == ng) od = 0;
   }
+}
+
+// TY x TZ output tile per workgroup of NT threads; the region with the
+// 4-layer halo has (TY + 8) x (TZ + 8) columns.
+template <typename T, int TY, int TZ, int NT>
+__global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
+                                                  int step, long long total, long long per_xcd) {
+  constexpr int NR = (TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo);
+  // two sets of the four stage planes, alternating per march step, so one
+  // barrier per step suffices (a set is rewritten two steps later, after
+  // every thread has passed the intermediate barrier)
+  __shared__ T lds[2][4][NR];
+  // v_y(x) and v_z(x) parts of the velocity for the chunk's planes
+  // x0 - 6 .. x0 + kMaxChunk + 3
+  __shared__ T vxt[2][kMaxChunk + 10];
+
+  // blocks b, b + 8, b + 16, ... run on one XCD: give them consecutive tiles
+  const long long b = blockIdx.x;
+  const long long t = (b % 8) * per_xcd + b / 8;
+  if (t >= total) return;
+  const int f = find_desc(descs, nd, t);
+  const FineDesc<T>& d = descs[f];
+  if (step >= d.n_steps) return;
+  if (d.g.xonly)
+    rk4_tile<T, TY, TZ, NT, true>(d, step, t - d.tile_begin, lds, vxt);
+  else
+    rk4_tile<T, TY, TZ, NT, false>(d, step, t - d.tile_begin, lds, vxt);
 }
 
 // Launch of one fused step in tile configuration cfg (kFusedCfgs).
