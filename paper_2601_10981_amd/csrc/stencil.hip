@@ -17,6 +17,8 @@
 // pipeline along x (at march step t: w1 at plane t + 3, w2 at t + 2, w3 at
 // t + 1, y_new at t). Workgroups are mapped to XCDs in contiguous tile ranges
 // so neighbouring tiles share an L2.
+#include <type_traits>
+
 #include "pr_internal.h"
 
 namespace pr {
@@ -80,17 +82,31 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
 // ---------------------------------------------------------------------------
 // Fused RK4 step.
 
-// L at one column of a stage plane: x neighbours from registers, y and z
-// neighbours from the LDS plane (row-major, RZ columns per row). XONLY: the
-// velocity has only an x component (v_y = v_z = 0), whose terms are skipped.
-template <typename T, int RZ, bool XONLY>
+// L at one column of a stage plane, general velocity: x neighbours from
+// registers, y and z neighbours from the LDS plane (row-major, RZ columns per
+// row).
+// Every multiply-add is an explicit fma and nothing else is contracted, so
+// each value is bitwise the same in every instantiation and tiling.
+template <typename T, int RZ>
 __device__ __forceinline__ T lop(T xm, T c, T xp, const T* __restrict__ pl, int i, T clap,
                                  T vx, T vy, T vz) {
+#pragma clang fp contract(off)
   const T ym = pl[i - RZ], yp = pl[i + RZ], zm = pl[i - 1], zp = pl[i + 1];
-  const T lap = ((xp + xm) + (yp + ym) + (zp + zm)) - (T)6 * c;
-  if (XONLY) return clap * lap - vx * (xp - xm);
-  const T adv = vx * (xp - xm) + vy * (yp - ym) + vz * (zp - zm);
-  return clap * lap - adv;
+  const T lap = fma((T)-6, c, ((xp + xm) + (yp + ym)) + (zp + zm));
+  const T adv = fma(vz, zp - zm, fma(vy, yp - ym, vx * (xp - xm)));
+  return fma(clap, lap, -adv);
+}
+
+// L for a velocity with only an x component, regrouped per neighbour:
+// (clap - v_x) u_{x+1} + (clap + v_x) u_{x-1} + clap (y and z neighbours)
+// - 6 clap u, with a = clap - v_x, b = clap + v_x and e = -6 clap.
+template <typename T, int RZ>
+__device__ __forceinline__ T lop_x(T xm, T c, T xp, const T* __restrict__ pl, int i, T clap,
+                                   T e, T a, T b) {
+#pragma clang fp contract(off)
+  const T ym = pl[i - RZ], yp = pl[i + RZ], zm = pl[i - 1], zp = pl[i + 1];
+  const T syz = (yp + ym) + (zp + zm);
+  return fma(a, xp, fma(b, xm, fma(clap, syz, e * c)));
 }
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -144,19 +160,23 @@ __device__ __forceinline__ void ring_col(int p, int& ry, int& rz, int& lev) {
 // One fused RK4 step of one workgroup tile. The stages form a skewed
 // pipeline along x: at march step tt, w1 at plane tt + 3, w2 at tt + 2, w3 at
 // tt + 1 and y_new at tt. Each thread holds SL columns (slots); for each it
-// keeps the x - 1, x, x + 1 values of every stage in registers and exchanges
-// the current plane of every stage through LDS for the y and z neighbours.
-// Slots wholly inside the interior are known at compile time and skip the
-// ring tests.
+// keeps the planes every stage still needs in registers and exchanges the
+// current plane of every stage through LDS for the y and z neighbours.
+// The per-slot plane windows are rings of six registers indexed by the
+// march step modulo 6, and the march is unrolled by 6 so every ring index
+// is a compile-time constant (no register shuffling per step). Slots wholly
+// inside the interior are known at compile time and skip the ring tests.
 template <typename T, int TY, int TZ, int NT, bool XONLY>
 __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long long lt,
                                          T (*lds)[4][(TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo)],
                                          T (*vxt)[kMaxChunk + 10]) {
+#pragma clang fp contract(off)
   constexpr int H = kFusedHalo;
   constexpr int RY = TY + 2 * H, RZ = TZ + 2 * H;
   constexpr int NR = RY * RZ;
   constexpr int SL = (NR + NT - 1) / NT;
   constexpr int NI = TY * TZ;
+  constexpr int RING = 6;
   const int tz = (int)(lt % d.tiles_z);
   const long long rest = lt / d.tiles_z;
   const int ty = (int)(rest % d.tiles_y);
@@ -173,6 +193,7 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
     snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * plane * n);
   const PR_GLOBAL T* tab = gptr(tab_of<T>(d.g));
   const T clap = (T)d.g.c_lap;
+  const T e6 = (T)-6 * clap;
   const T dt = (T)d.dt;
   const T c1 = dt * (T)0.25, c2 = dt / (T)3, c3 = dt * (T)0.5, c4 = dt;
 
@@ -180,7 +201,7 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
   int off[SL];   // gy * n + gz of the slot's column
   int lev[SL];   // ring level (0 = interior), 99 = no column
   bool outp[SL];
-  T vx[SL], vyz[SL], vzy[SL];
+  T va[SL], vb[SL], vyz[SL], vzy[SL];   // XONLY: a, b; else v_x and the y/z parts
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
     int ry, rz, lv;
@@ -191,7 +212,9 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
     outp[s] = lv == 0 && y0 + dy < n && z0 + dz < n;
     const int gy = wrapi(y0 + dy, n), gz = wrapi(z0 + dz, n);
     off[s] = lv <= H ? gy * n + gz : 0;
-    vx[s] = tab[gy] + tab[n + gz];
+    const T vx = tab[gy] + tab[n + gz];
+    va[s] = XONLY ? clap - vx : vx;
+    vb[s] = XONLY ? clap + vx : (T)0;
     vyz[s] = XONLY ? (T)0 : tab[3 * n + gz];
     vzy[s] = XONLY ? (T)0 : tab[5 * n + gy];
   }
@@ -202,16 +225,17 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
       vxt[1][i] = tab[4 * n + x];
     }
 
-  // Y[s][k] = y(tt + k), W1[s][k] = w1(tt + 1 + k), W2[s][k] = w2(tt + k),
-  // W3[s][k] = w3(tt - 1 + k); Yn = y(tt + 5), prefetched one step ahead.
-  T Y[SL][5], W1[SL][3], W2[SL][3], W3[SL][3], Yn[SL];
+  // Rings, at march step tt with phase ph = (tt - x0 + 6) % 6, logical index
+  // k at physical (k + ph) % 6: Y: y(tt + k), k = 0..5 (k = 5 is loaded
+  // during the step, one step ahead of use); W1: w1(tt + 1 + k), W2:
+  // w2(tt + k), W3: w3(tt - 1 + k), k = 0..2.
+  T Y[SL][RING], W1[SL][3], W2[SL][3], W3[SL][3];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
 #pragma unroll
-    for (int k = 0; k < 5; ++k) Y[s][k] = (T)0;
+    for (int k = 0; k < RING; ++k) Y[s][k] = (T)0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) W1[s][k] = W2[s][k] = W3[s][k] = (T)0;
-    Yn[s] = (T)0;
   }
   {
     const long long pa = (long long)wrapi(x0 - 4, n) * plane;
@@ -223,7 +247,7 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
     for (int s = 0; s < SL; ++s) {
       Y[s][2] = src[pa + off[s]];
       Y[s][3] = src[pb + off[s]];
-      Yn[s] = src[pc + off[s]];
+      Y[s][4] = src[pc + off[s]];
     }
   }
   // plane offsets of x = tt + 5 (load) and x = tt (store), wrapped by
@@ -231,19 +255,31 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
   long long o5 = (long long)wrapi(x0 - 1, n) * plane;
   long long od = (long long)wrapi(x0 - 6, n) * plane;
   const long long ng = plane * n;
+  int tt = x0 - 6;
 
-  __syncthreads();   // vxt visible
-  for (int tt = x0 - 6; tt < x1; ++tt) {
-    T (*pl)[NR] = lds[(tt - x0) & 1];
+  // phase: march step modulo 6; warm: the first six steps of the chunk,
+  // where stage s only starts once its input planes exist (w2 from the third
+  // step, w3 from the fifth, y_new after the sixth)
+  auto march = [&](auto phase, auto warm) {
+    constexpr int PH = decltype(phase)::value;
+    constexpr bool WARM = decltype(warm)::value;
+    constexpr bool s2 = !WARM || PH >= 2, s3 = !WARM || PH >= 4, s4 = !WARM;
+    // keep the scheduler from interleaving consecutive steps (which would
+    // stretch live ranges across the unrolled round)
+    __builtin_amdgcn_sched_barrier(0);
+    // Y ring positions (period 6) and W ring positions (period 3)
+    constexpr int k0 = PH % RING, k1 = (1 + PH) % RING, k2 = (2 + PH) % RING,
+                  k3 = (3 + PH) % RING, k4 = (4 + PH) % RING, k5 = (5 + PH) % RING;
+    constexpr int j0 = PH % 3, j1 = (1 + PH) % 3, j2 = (2 + PH) % 3;
+    T (*pl)[NR] = lds[PH & 1];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const bool inner = (s + 1) * NT <= NI;
-      Y[s][4] = Yn[s];
-      Yn[s] = src[o5 + off[s]];   // consumed next step
-      if (inner || lev[s] <= H) pl[0][ci[s]] = Y[s][3];
-      if (inner || lev[s] <= H - 1) pl[1][ci[s]] = W1[s][1];
-      if (inner || lev[s] <= H - 2) pl[2][ci[s]] = W2[s][1];
-      if (inner || lev[s] <= H - 3) pl[3][ci[s]] = W3[s][1];
+      Y[s][k5] = src[o5 + off[s]];   // y(tt + 5), used from the next step on
+      if (inner || lev[s] <= H) pl[0][ci[s]] = Y[s][k3];
+      if (inner || lev[s] <= H - 1) pl[1][ci[s]] = W1[s][j1];
+      if (inner || lev[s] <= H - 2) pl[2][ci[s]] = W2[s][j1];
+      if (inner || lev[s] <= H - 3) pl[3][ci[s]] = W3[s][j1];
     }
     __syncthreads();
     const int iv = tt - (x0 - 6);
@@ -254,44 +290,80 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
       vy_c = vxt[0][iv + 1]; vz_c = vxt[1][iv + 1];
       vy_d = vxt[0][iv];     vz_d = vxt[1][iv];
     }
-    const bool s2 = tt >= x0 - 4, s3 = tt >= x0 - 2, s4 = tt >= x0;
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const bool inner = (s + 1) * NT <= NI;
       const int c = ci[s];
       const int lv = lev[s];
-      if (inner || lv <= H - 1)
-        W1[s][2] = Y[s][3] + c1 * lop<T, RZ, XONLY>(Y[s][2], Y[s][3], Y[s][4], pl[0], c, clap,
-                                                    vx[s], vy_a + vyz[s], vz_a + vzy[s]);
-      if (s2 && (inner || lv <= H - 2))
-        W2[s][2] = Y[s][2] + c2 * lop<T, RZ, XONLY>(W1[s][0], W1[s][1], W1[s][2], pl[1], c, clap,
-                                                    vx[s], vy_b + vyz[s], vz_b + vzy[s]);
-      if (s3 && (inner || lv <= H - 3))
-        W3[s][2] = Y[s][1] + c3 * lop<T, RZ, XONLY>(W2[s][0], W2[s][1], W2[s][2], pl[2], c, clap,
-                                                    vx[s], vy_c + vyz[s], vz_c + vzy[s]);
+      // every ring entry is overwritten each step (zero where the stage is
+      // skipped), so no stale entry stays live across the march
+      T w1 = (T)0, w2 = (T)0, w3 = (T)0;
+      if (inner || lv <= H - 1) {
+        const T L1 = XONLY ? lop_x<T, RZ>(Y[s][k2], Y[s][k3], Y[s][k4], pl[0], c, clap, e6, va[s],
+                                          vb[s])
+                           : lop<T, RZ>(Y[s][k2], Y[s][k3], Y[s][k4], pl[0], c, clap, va[s],
+                                        vy_a + vyz[s], vz_a + vzy[s]);
+        w1 = fma(c1, L1, Y[s][k3]);
+      }
+      W1[s][j2] = w1;
+      if (s2 && (inner || lv <= H - 2)) {
+        const T L2 = XONLY ? lop_x<T, RZ>(W1[s][j0], W1[s][j1], W1[s][j2], pl[1], c, clap, e6,
+                                          va[s], vb[s])
+                           : lop<T, RZ>(W1[s][j0], W1[s][j1], W1[s][j2], pl[1], c, clap, va[s],
+                                        vy_b + vyz[s], vz_b + vzy[s]);
+        w2 = fma(c2, L2, Y[s][k2]);
+      }
+      W2[s][j2] = w2;
+      if (s3 && (inner || lv <= H - 3)) {
+        const T L3 = XONLY ? lop_x<T, RZ>(W2[s][j0], W2[s][j1], W2[s][j2], pl[2], c, clap, e6,
+                                          va[s], vb[s])
+                           : lop<T, RZ>(W2[s][j0], W2[s][j1], W2[s][j2], pl[2], c, clap, va[s],
+                                        vy_c + vyz[s], vz_c + vzy[s]);
+        w3 = fma(c3, L3, Y[s][k1]);
+      }
+      W3[s][j2] = w3;
       if (s4 && outp[s]) {
-        const T yn = Y[s][0] + c4 * lop<T, RZ, XONLY>(W3[s][0], W3[s][1], W3[s][2], pl[3], c,
-                                                      clap, vx[s], vy_d + vyz[s], vz_d + vzy[s]);
+        const T L4 = XONLY ? lop_x<T, RZ>(W3[s][j0], W3[s][j1], W3[s][j2], pl[3], c, clap, e6,
+                                          va[s], vb[s])
+                           : lop<T, RZ>(W3[s][j0], W3[s][j1], W3[s][j2], pl[3], c, clap, va[s],
+                                        vy_d + vyz[s], vz_d + vzy[s]);
+        const T yn = fma(c4, L4, Y[s][k0]);
         dst[od + off[s]] = yn;
         if (snap) snap[od + off[s]] = yn;
       }
-    }
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) Y[s][k] = Y[s][k + 1];
-      W1[s][0] = W1[s][1];
-      W1[s][1] = W1[s][2];
-      W2[s][0] = W2[s][1];
-      W2[s][1] = W2[s][2];
-      W3[s][0] = W3[s][1];
-      W3[s][1] = W3[s][2];
     }
     o5 += plane;
     if (o5 == ng) o5 = 0;
     od += plane;
     if (od == ng) od = 0;
+    ++tt;
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  using I5 = std::integral_constant<int, 5>;
+
+  using W = std::true_type;
+  using S = std::false_type;
+
+  __syncthreads();   // vxt visible
+  // (x1 - x0) + 6 march steps: the six warm-up steps, whole rounds of six,
+  // then the rest (phases continue from 0, the phase after a whole round)
+  march(I0{}, W{}); march(I1{}, W{}); march(I2{}, W{});
+  march(I3{}, W{}); march(I4{}, W{}); march(I5{}, W{});
+  const int nstep = x1 - x0;
+  for (int r = 0; r + RING <= nstep; r += RING) {
+    march(I0{}, S{}); march(I1{}, S{}); march(I2{}, S{});
+    march(I3{}, S{}); march(I4{}, S{}); march(I5{}, S{});
   }
+  const int rem = nstep % RING;
+  if (rem > 0) march(I0{}, S{});
+  if (rem > 1) march(I1{}, S{});
+  if (rem > 2) march(I2{}, S{});
+  if (rem > 3) march(I3{}, S{});
+  if (rem > 4) march(I4{}, S{});
 }
 
 // TY x TZ output tile per workgroup of NT threads; the region with the
