@@ -366,10 +366,21 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
   if (rem > 4) march(I4{}, S{});
 }
 
+// Waves per SIMD that the tiling's LDS allows on a CU (160 KiB of LDS, four
+// SIMDs), capped at 4: the register budget the kernel is compiled for.
+template <typename T, int TY, int TZ, int NT>
+constexpr int fused_waves_per_simd() {
+  constexpr long long lds = (2LL * 4 * (TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo) +
+                             2LL * (kMaxChunk + 10)) * (long long)sizeof(T);
+  constexpr long long wgs = (160LL * 1024) / lds;
+  constexpr long long w = wgs * (NT / 64) / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : (int)w);
+}
+
 // TY x TZ output tile per workgroup of NT threads; the region with the
 // 4-layer halo has (TY + 8) x (TZ + 8) columns.
 template <typename T, int TY, int TZ, int NT>
-__global__ __launch_bounds__(NT) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
+__global__ __launch_bounds__(NT, (fused_waves_per_simd<T, TY, TZ, NT>())) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
                                                   int step, long long total, long long per_xcd) {
   constexpr int NR = (TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo);
   // two sets of the four stage planes, alternating per march step, so one
