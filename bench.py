@@ -43,6 +43,14 @@ def parse():
                     help="also time the fine step in every stencil tiling (stderr and JSON)")
     ap.add_argument("--serve-requests", type=int, default=6,
                     help="requests per serving phase (closed loop, then Poisson); 0 = skip")
+    ap.add_argument("--mixed256", action="store_true",
+                    help="report run of the 256^3 ABC mixed-precision workload instead "
+                         "(its own JSON line): error per iteration against the FP64 serial "
+                         "fine solution")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="report run of K ensemble instances solved together (own JSON line)")
+    ap.add_argument("--max-iter", type=int, default=4,
+                    help="iterations of the --mixed256 run")
     return ap.parse_args()
 
 
@@ -130,16 +138,114 @@ def serving_sample(pr, ctx, budget, k):
                       f"(seeds 5000..{5000 + 2 * k - 1}); no warm-up exclusion"}
 
 
+def mixed256_run(args):
+    """256^3 ABC, kappa = 0.005, T = 50 over 128 subintervals, dt = 5e-4: the
+    stencil and the snapshot Grams in FP32, the rest in FP64. The FP64
+    serial fine solution (computed on the GPU with the FP64 stencil first)
+    is the reference of the per-iteration error."""
+    import dataclasses
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    w = W.ABC_256_MIXED
+    n, N = w.problem.n, w.opts.N
+    ng = n ** 3
+    opts = dataclasses.replace(w.opts, max_iter=args.max_iter)
+    p32 = pr.problem_of(w.problem)
+    p64 = pr.problem_of(dataclasses.replace(w.problem, precision=W.PREC_F64))
+    plan = pr.pr_plan(p32, opts)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    U_ref = torch.empty((N + 1, ng), dtype=torch.float64, device="cuda")
+    U_out = torch.empty_like(U_ref)
+    U_ref[0].copy_(W.fourier_field_device(n, w.seed, "cuda").reshape(-1))
+    free, _ = torch.cuda.mem_get_info()
+    ctx = pr.Context(0, budget_bytes=int(0.92 * free))
+    log(f"mixed256: FP64 serial reference, {N} x {plan['n_f']} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(N):
+        pr.pr_fine_propagate(ctx, [dict(prob=p64, dt=plan["dt"], n_steps=plan["n_f"],
+                                        u_in=U_ref[j], u_out=U_ref[j + 1])])
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+    log(f"mixed256: solve, max_iter {opts.max_iter}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = pr.pr_parareal_solve(ctx, p32, opts, U_ref[0], U_out=U_out, U_ref=U_ref)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # the converged prefix U_j, j <= k + 1, is the FP32-stencil serial fine
+    # solution: its distance to the FP64 one is the mixed-precision error of F
+    prefix = [float("%.3e" % (torch.linalg.vector_norm(U_out[j] - U_ref[j]) /
+                              torch.linalg.vector_norm(U_ref[j])).item())
+              for j in range(1, rep.iters + 2)]
+    out = {"mode": "mixed256", "workload": w.name, "n": n, "N": N, "n_f": plan["n_f"],
+           "dt": plan["dt"], "cap0": opts.cap0, "cap": opts.cap, "precision": "mixed",
+           "dtype": "f32 stencil and snapshot Gram; f64 eigen, re-orthogonalisation, sweep",
+           "iters": rep.iters, "status": rep.status, "m0": rep.m0,
+           "err_vs_fp64_serial": [float("%.3e" % e) for e in rep.err],
+           "jump": [float("%.3e" % e) for e in rep.jump],
+           "t_iter_s": [round(t, 2) for t in rep.t_iter],
+           "t_phase_s": {k: round(v, 3) for k, v in rep.t_phase.items()},
+           "solve_s": round(el, 2), "fine_updates": rep.fine_updates,
+           "gpts_whole_solve": round(rep.fine_updates / el / 1e9, 2),
+           "serial_fp64_s": round(serial_s, 2),
+           "serial_fp64_gpts": round(N * plan["n_f"] * ng / serial_s / 1e9, 2),
+           "fine_gpts_in_solve": round(rep.fine_updates / max(rep.t_phase["F"], 1e-9) / 1e9, 1),
+           "prefix_err_vs_fp64": prefix,
+           "ranks_last": rep.ranks[-1] if rep.ranks else None}
+    ctx.close()
+    print(json.dumps(out))
+
+
+def ensemble_run(args):
+    """K independent instances of the ensemble (grids 64..192, ABC or
+    Kolmogorov, random kappa, T, N; mixed precision; tol 1e-6) admitted at
+    once and advanced together: every step batches the fine solves and
+    per-subinterval POD of all live instances into shared launches."""
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    from paper_2601_10981_amd import serving
+    ws = W.ensemble(args.ensemble)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+    ctx = pr.Context(0, budget_bytes=budget)
+    reqs = [serving.Request(i, 0.0, pr.problem_of(w.problem), w.opts,
+                            lambda w=w: W.fourier_field_device(w.problem.n, w.seed,
+                                                               "cuda").reshape(-1))
+            for i, w in enumerate(ws)]
+    log(f"ensemble: {len(reqs)} instances")
+    st = serving.serve(ctx, reqs, budget, max_live=len(reqs),
+                       log=lambda m: log("  " + m))
+    done = sorted(st.completed, key=lambda c: c.rid)
+    out = {"mode": "ensemble", "instances": len(done), "wall_s": round(st.wall, 2),
+           "solves_per_s": round(len(done) / st.wall, 4), "steps": st.steps,
+           "fine_gpts": round(sum(c.fine_updates for c in done) / st.wall / 1e9, 1),
+           "mean_live": round(st.mean_live, 2), "max_live": st.max_live,
+           "grids": [c.n for c in done], "N": [c.N for c in done],
+           "iters": [c.iters for c in done], "status": [c.status for c in done],
+           "seeds": f"4000..{4000 + len(done) - 1}"}
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.mixed256:
+        return mixed256_run(args)
+    if args.ensemble > 0:
+        return ensemble_run(args)
     import numpy as np
     import torch
     import paper_2601_10981_amd as pr
     import workloads as W
-    from oracle import fd as ofd  # step-count reading only, for the config echo
 
     w = W.KOL_128_F64
     prob = pr.problem_of(w.problem)
@@ -154,7 +260,8 @@ def main():
     torch.cuda.set_stream(stream)
     u0 = torch.from_numpy(W.initial_field(w).reshape(-1).copy()).cuda()
 
-    n_f, dt = ofd.steps_per_subinterval(opts.T / N, opts.dt)
+    plan = pr.pr_plan(prob, opts)
+    n_f, dt = plan["n_f"], plan["dt"]
 
     U_ref = None
     serial_s = None

@@ -262,6 +262,20 @@ pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,
                             const pr_parareal_opts* opts, const double* u0,
                             double* U_out, pr_report* report, void* stream);
 
+/* Derived sizes of a solve (pure host function): the readings above applied
+ * to (prob, opts). n_c is before the stability guard, which the device may
+ * raise per coarse step. Errors as pr_parareal_solve's validation. */
+typedef struct {
+  int n_sub;      /* N - 1 parareal subintervals                             */
+  int n_f;        /* fine steps per subinterval                              */
+  double dt;      /* fine step delta_t = DeltaT / n_f                        */
+  int dM;         /* snapshot stride                                         */
+  int n_s;        /* snapshots per subinterval, floor(n_f / dM) + 1          */
+  int n_c;        /* coarse steps per subinterval                            */
+  int max_iter;   /* iteration limit after clamping to N - 1                 */
+} pr_plan_info;
+pr_status pr_plan(const pr_grid_problem* prob, const pr_parareal_opts* opts, pr_plan_info* out);
+
 /* Device bytes pr_parareal_solve needs for (prob, opts) with every wave at
  * full width (pure host function); a solve under a smaller budget runs its
  * fine solves and local POD in narrower waves. */

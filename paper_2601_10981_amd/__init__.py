@@ -18,7 +18,7 @@ from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
 
 __all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
-           "pr_coarse_propagate", "pr_parareal_solve", "pr_footprint", "pr_solve_begin",
+           "pr_coarse_propagate", "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin",
            "pr_solve_step_batch", "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end",
            "SolveHandle", "costmodel"]
 
@@ -445,6 +445,17 @@ def pr_solve_end(ctx: Context, handle: SolveHandle, U_out=None, stream=None,
     if st != L.PR_OK and not (allow_notconv and st == -5):
         raise PrError(st, ctx.error())
     return (None if U_out is False else U_out), rb.report(st, handle.U_ref is not None)
+
+
+def pr_plan(prob: L.pr_grid_problem, opts) -> dict:
+    """Derived sizes of a solve: n_sub, n_f, dt, dM, n_s, n_c, max_iter."""
+    lib = L.load()
+    o = opts_struct(opts)
+    info = L.pr_plan_info()
+    st = lib.pr_plan(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(info))
+    if st != L.PR_OK:
+        raise PrError(st, "pr_plan failed")
+    return {k: getattr(info, k) for k, _ in info._fields_}
 
 
 def pr_footprint(prob: L.pr_grid_problem, opts) -> int:

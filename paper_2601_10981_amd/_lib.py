@@ -57,9 +57,14 @@ class pr_report(Structure):
                 ("t_phase", c_double * 5), ("fine_updates", c_double), ("seconds", c_double)]
 
 
+class pr_plan_info(Structure):
+    _fields_ = [("n_sub", c_int), ("n_f", c_int), ("dt", c_double), ("dM", c_int),
+                ("n_s", c_int), ("n_c", c_int), ("max_iter", c_int)]
+
+
 EXPORTS = ["pr_ctx_create", "pr_ctx_destroy", "pr_last_error", "pr_ctx_scratch_bytes",
            "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build", "pr_coarse_propagate",
-           "pr_parareal_solve", "pr_footprint", "pr_solve_begin", "pr_solve_step_batch",
+           "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin", "pr_solve_step_batch",
            "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end"]
 
 _lib = None
@@ -106,6 +111,9 @@ def load(path: str = LIB_PATH):
                                       POINTER(pr_parareal_opts), c_void_p, c_void_p,
                                       POINTER(pr_report), c_void_p]
     lib.pr_parareal_solve.restype = c_int
+    lib.pr_plan.argtypes = [POINTER(pr_grid_problem), POINTER(pr_parareal_opts),
+                            POINTER(pr_plan_info)]
+    lib.pr_plan.restype = c_int
     lib.pr_footprint.argtypes = [POINTER(pr_grid_problem), POINTER(pr_parareal_opts),
                                  POINTER(c_size_t)]
     lib.pr_footprint.restype = c_int

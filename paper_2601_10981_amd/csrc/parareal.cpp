@@ -741,6 +741,23 @@ pr_status pr_solve_end(pr_ctx* c, pr_solve* S, double* U_out, pr_report* report,
   })
 }
 
+pr_status pr_plan(const pr_grid_problem* prob, const pr_parareal_opts* opts, pr_plan_info* out) {
+  if (!out) return PR_EINVAL;
+  try {
+    const Plan P = make_plan(prob, opts);
+    out->n_sub = P.Np;
+    out->n_f = P.n_f;
+    out->dt = P.dt;
+    out->dM = P.dM;
+    out->n_s = P.n_s;
+    out->n_c = P.n_c;
+    out->max_iter = P.max_iter;
+    return PR_OK;
+  } catch (const pr::Error& e) {
+    return e.st;
+  }
+}
+
 pr_status pr_footprint(const pr_grid_problem* prob, const pr_parareal_opts* opts, size_t* bytes) {
   if (!bytes) return PR_EINVAL;
   try {

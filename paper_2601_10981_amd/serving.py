@@ -47,6 +47,7 @@ class Completed:
     status: int
     n: int
     N: int
+    fine_updates: float = 0.0
 
     @property
     def latency(self) -> float:
@@ -123,7 +124,7 @@ def serve(ctx, requests: List[Request], budget_bytes: int, max_live: int = 16,
                 _, rep = pr_solve_end(ctx, h, U_out=False)
                 t = time.perf_counter() - t0
                 completed.append(Completed(r.rid, r.arrival, t_adm, t, rep.iters, rep.status,
-                                           r.prob.n, int(r.opts.N)))
+                                           r.prob.n, int(r.opts.N), rep.fine_updates))
                 if log:
                     log(f"done {r.rid} iters={rep.iters} status={rep.status} "
                         f"latency={t - r.arrival:.2f}s")

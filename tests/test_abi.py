@@ -52,3 +52,24 @@ def test_footprint_is_host_only():
     with pytest.raises(pr.PrError) as e:
         pr.pr_footprint(pr.problem_of(w.problem), W.PararealOpts(T=10.0, N=64, dt=10.0))
     assert e.value.name == "PR_EUNSTABLE"
+
+
+@pytest.mark.parametrize("w", ["abc32", "kol128", "abc256", "ens0", "ens7"])
+def test_plan_matches_the_oracle_reading(w):
+    """pr_plan (host only) derives n_f, delta_t, dM, n_s and n_c by the same
+    readings as the oracle: the step-count rule, the snapshot stride, the
+    coarse step rule and, for dt <= 0, the automatic step."""
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    from oracle import coarse, fd, parareal
+    wl = {"abc32": W.ABC_32_F64, "kol128": W.KOL_128_F64, "abc256": W.ABC_256_MIXED,
+          "ens0": W.ensemble(8)[0], "ens7": W.ensemble(8)[7]}[w]
+    plan = pr.pr_plan(pr.problem_of(wl.problem), wl.opts)
+    n_f, dt = fd.steps_per_subinterval(wl.opts.T / wl.opts.N,
+                                       parareal.requested_dt(wl.problem, wl.opts))
+    dM = fd.snapshot_stride(n_f, wl.opts.dM)
+    assert plan["n_f"] == n_f and plan["dM"] == dM
+    assert plan["dt"] == pytest.approx(dt, rel=1e-15)
+    assert plan["n_s"] == n_f // dM + 1
+    assert plan["n_c"] == coarse.coarse_steps(n_f, wl.opts.coarse_ratio)
+    assert plan["n_sub"] == wl.opts.N - 1
