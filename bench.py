@@ -307,8 +307,8 @@ def main():
     bytes_per_launch = 16 * ng * B
     achieved = bytes_per_launch / avg_launch_s / 1e9
     stencil_gpts = B * ng * n_f / (fine_ms * 1e-3) / 1e9
-    tiling = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
-    kname = "k_rk4_fused<double,%d,%d,%d>" % tiling if tiling else "k_rk4_fused<double>"
+    tiling = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, planes=True)
+    kname = ("k_rk4_fused<double,%d,%d,%d>/x%d" % tiling) if tiling else "k_rk4_fused<double>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": profiled_traffic(kname),
@@ -316,18 +316,22 @@ def main():
                 "bytes_per_launch": bytes_per_launch}
     if args.sweep:
         sweep = {}
-        for cfg in range(7):
-            os.environ["PR_FUSED_CFG"] = str(cfg)
-            pr.pr_fine_propagate(ctx, items)
-            e0.record(stream)
-            pr.pr_fine_propagate(ctx, items)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
-            sweep["%dx%dx%d" % t] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
-            log(f"  tiling {t}: {sweep['%dx%dx%d' % t]} GPts/s")
+        for pol in range(3):
+            os.environ["PR_FUSED_CHUNK"] = str(pol)
+            for cfg in range(7):
+                os.environ["PR_FUSED_CFG"] = str(cfg)
+                pr.pr_fine_propagate(ctx, items)
+                e0.record(stream)
+                pr.pr_fine_propagate(ctx, items)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
+                key = "%dx%dx%d/chunks%d" % (t + (pol,))
+                sweep[key] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
+                log(f"  tiling {key}: {sweep[key]} GPts/s")
         del os.environ["PR_FUSED_CFG"]
+        del os.environ["PR_FUSED_CHUNK"]
         roofline["sweep_gpts"] = sweep
     del xin, xout
     if args.stencil_only:

@@ -113,12 +113,15 @@ pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, v
 /* Tiling of the fused RK4 stencil. Every tiling gives bitwise the same
  * values; the context picks one per (precision, largest n of the batch,
  * floor(log2(batch))) by timing one step of the first such batch in each
- * candidate tiling (that first call synchronises `stream`). The environment
- * variable PR_FUSED_CFG=<index> forces one. pr_fine_tuned reports the
- * workgroup's output tile (tile_y x tile_z points of the (y, z) plane) and
- * thread count chosen for a key; PR_EINVAL if no batch of that key ran yet. */
+ * candidate tiling and x-chunk length (that first call synchronises
+ * `stream`). The environment
+ * variables PR_FUSED_CFG=<index> and PR_FUSED_CHUNK=<policy> force one.
+ * pr_fine_tuned reports, for a key, the workgroup's output tile (tile_y x
+ * tile_z points of the (y, z) plane), its thread count and the x planes it
+ * marches through (for `batch` fields of n^3); every output pointer may be
+ * NULL. PR_EINVAL if no batch of that key ran yet. */
 pr_status pr_fine_tuned(const pr_ctx* ctx, int precision, int n, int batch, int* tile_y,
-                        int* tile_z, int* threads);
+                        int* tile_z, int* threads, int* planes);
 
 /* ---------------------------------------------------------------------------
  * POD_Mode (Algorithm 1; Sec. 3.2 Case I and Case II, eq. W^k_n): modes of

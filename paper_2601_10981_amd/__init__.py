@@ -147,15 +147,16 @@ def pr_fine_propagate(ctx: Context, items: Sequence[dict], stream=None):
     ctx.check(ctx.lib.pr_fine_propagate(ctx.h, len(items), arr, _stream(stream)))
 
 
-def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int):
-    """(tile_y, tile_z, threads) of the fused stencil tiling chosen for a
-    batch key, or None if no such batch ran yet."""
-    ty, tz, nt = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int, planes: bool = False):
+    """(tile_y, tile_z, threads[, x planes per workgroup]) of the fused
+    stencil launch shape chosen for a batch key, or None if no such batch
+    ran yet."""
+    ty, tz, nt, xp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     st = ctx.lib.pr_fine_tuned(ctx.h, int(precision), int(n), int(batch), ctypes.byref(ty),
-                               ctypes.byref(tz), ctypes.byref(nt))
+                               ctypes.byref(tz), ctypes.byref(nt), ctypes.byref(xp))
     if st != L.PR_OK:
         return None
-    return ty.value, tz.value, nt.value
+    return (ty.value, tz.value, nt.value, xp.value) if planes else (ty.value, tz.value, nt.value)
 
 
 def pr_gram(ctx: Context, prob: L.pr_grid_problem, W, ncols: int, G_out=None, stream=None):

@@ -255,6 +255,11 @@ int gram_chunk_rows(long long nrows) {
 
 // ---------------------------------------------------------------------------
 // fine propagator
+// Chunk-length policies of the fused stencil (fine_chunk): the least number
+// of workgroups a launch should have before chunks are halved.
+constexpr int kChunkPolicies = 3;
+constexpr long long kChunkMinWgs[kChunkPolicies] = {2048, 768, 256};
+
 // Tile configuration of the fused stencil: PR_FUSED_CFG=<index> forces one;
 // otherwise each (precision, largest grid, batch size class) is tuned once
 // per context (see tune_fine).
@@ -262,13 +267,18 @@ static int forced_cfg() {
   const char* e = getenv("PR_FUSED_CFG");
   if (!e || !*e) return -1;
   const int v = atoi(e);
-  return (v >= 0 && v < kNumFusedCfgs) ? v : -1;
+  if (v < 0 || v >= kNumFusedCfgs) return -1;
+  const char* p = getenv("PR_FUSED_CHUNK");
+  const int pol = (p && *p) ? atoi(p) : 0;
+  return v + kNumFusedCfgs * ((pol >= 0 && pol < kChunkPolicies) ? pol : 0);
 }
 
-// x-chunk length of the fused stencil: chunks of up to 64 planes, halved
-// while the batch would give fewer than ~2048 workgroups (small batches, e.g.
-// the serial fine solve of one field, still fill the chip).
-static int fine_chunk(const std::vector<FineWork>& items, int cfg) {
+// x-chunk length of the fused stencil: chunks of up to kMaxChunk planes,
+// halved while the batch would give fewer than min_wgs workgroups (small
+// batches, e.g. the serial fine solve of one field, still fill the chip).
+// Longer chunks re-read fewer warm-up planes (6 per chunk); shorter ones give
+// more workgroups. The tuner tries both policies.
+static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min_wgs) {
   int xc = kMaxChunk;
   auto total = [&](int x) {
     long long t = 0;
@@ -279,16 +289,19 @@ static int fine_chunk(const std::vector<FineWork>& items, int cfg) {
     }
     return t;
   };
-  while (xc > 8 && total(xc) < 2048) xc /= 2;
+  while (xc > 8 && total(xc) < min_wgs) xc /= 2;
   return xc;
 }
 
 // Descriptors of one launch shape: per-item buffers fixed in `base`, tiles
 // of configuration cfg filled in. Returns the number of workgroup tiles.
+// A launch shape: tiling kFusedCfgs[code % kNumFusedCfgs], chunk policy
+// code / kNumFusedCfgs.
 template <typename T>
 static long long shape_descs(const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
-                             int cfg) {
-  const int xc = fine_chunk(items, cfg);
+                             int code) {
+  const int cfg = code % kNumFusedCfgs;
+  const int xc = fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs]);
   long long tiles = 0;
   for (size_t i = 0; i < items.size(); ++i) {
     const int n = items[i].prob->n;
@@ -339,8 +352,9 @@ static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<
   hipEvent_t e0 = event_get(c), e1 = event_get(c);
   float best_ms = 0;
   int best = 1;
-  for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg) {
-    const long long tiles = shape_descs<T>(items, d, cfg);
+  for (int code = 0; code < kNumFusedCfgs * kChunkPolicies; ++code) {
+    const int cfg = code % kNumFusedCfgs;
+    const long long tiles = shape_descs<T>(items, d, code);
     FineDesc<T>* dd = stage_push(c, d);
     stage_flush(c, s);
     launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
@@ -350,9 +364,9 @@ static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0;
     PR_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (cfg == 0 || ms < best_ms) {
+    if (code == 0 || ms < best_ms) {
       best_ms = ms;
-      best = cfg;
+      best = code;
     }
   }
   event_put(c, e0);
@@ -407,9 +421,10 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_
     descs.push_back(d);
   }
   if (max_steps > 0) {
-    int cfg = forced_cfg();
-    if (cfg < 0) cfg = tune_fine<T>(c, items, descs, s);
-    const long long tiles = shape_descs<T>(items, descs, cfg);
+    int code = forced_cfg();
+    if (code < 0) code = tune_fine<T>(c, items, descs, s);
+    const int cfg = code % kNumFusedCfgs;
+    const long long tiles = shape_descs<T>(items, descs, code);
     FineDesc<T>* dd = stage_push(c, descs);
     stage_flush(c, s);
     if (f32)
@@ -948,17 +963,25 @@ void pr_ctx_destroy(pr_ctx* c) {
 }
 
 pr_status pr_fine_tuned(const pr_ctx* c, int precision, int n, int batch, int* tile_y,
-                        int* tile_z, int* threads) {
+                        int* tile_z, int* threads, int* planes) {
   if (!c || batch < 1 || (precision != PR_F64 && precision != PR_MIXED)) return PR_EINVAL;
-  int cfg = forced_cfg();
-  if (cfg < 0) {
+  int code = forced_cfg();
+  if (code < 0) {
     auto it = c->tuned.find(tune_key(precision == PR_MIXED ? 4 : 8, n, batch));
     if (it == c->tuned.end()) return PR_EINVAL;
-    cfg = it->second;
+    code = it->second;
   }
+  const int cfg = code % kNumFusedCfgs;
   if (tile_y) *tile_y = kFusedCfgs[cfg].ty;
   if (tile_z) *tile_z = kFusedCfgs[cfg].tz;
   if (threads) *threads = kFusedCfgs[cfg].nt;
+  if (planes) {
+    // chunk length for `batch` fields of n^3 under the key's policy
+    pr_grid_problem p{};
+    p.n = n;
+    const std::vector<FineWork> items(batch, FineWork{&p, 0.0, 0, nullptr, nullptr, 0, nullptr});
+    *planes = std::min(n, fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs]));
+  }
   return PR_OK;
 }
 

@@ -101,7 +101,7 @@ struct FineDesc {
   long long tile_begin;
 };
 constexpr int kFusedHalo = 4;      // one halo layer per RK4 stage
-constexpr int kMaxChunk = 64;      // x planes per fused-stencil workgroup (at most)
+constexpr int kMaxChunk = 256;     // x planes per fused-stencil workgroup (at most)
 // Tile configurations of the fused stencil: output tile TY x TZ of the
 // (y, z) plane per workgroup of NT threads. Every configuration computes
 // bitwise the same values (each point's arithmetic does not depend on the

@@ -90,19 +90,22 @@ def test_fine_batch_uneven_is_bitwise_batch_invariant(ctx):
 
 @pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
 def test_fine_every_tile_configuration_is_bitwise_identical(ctx, prec, monkeypatch):
-    """Each point's arithmetic is independent of the tiling, so every tile
-    configuration the autotuner may pick gives the same bits (the first
-    batch of each key also runs the tuner itself)."""
+    """Each point's arithmetic is independent of the tiling and of the x-chunk
+    length, so every launch shape the autotuner may pick gives the same bits
+    (the first batch of each key also runs the tuner itself)."""
     say(f"fine tile configurations prec={prec}")
     cases = CASES + [(40, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.05, 0.005, 3, 1, 6)]
     ref_outs, ref_snaps = _run(ctx, cases, prec)          # autotuned
-    for cfg in range(7):
-        monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
-        outs, snaps = _run(ctx, cases, prec)
-        for i in range(len(cases)):
-            assert np.array_equal(to_np(outs[i]), to_np(ref_outs[i])), (cfg, i)
-            assert np.array_equal(to_np(snaps[i]), to_np(ref_snaps[i])), (cfg, i)
+    for pol in range(3):
+        monkeypatch.setenv("PR_FUSED_CHUNK", str(pol))
+        for cfg in range(7):
+            monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
+            outs, snaps = _run(ctx, cases, prec)
+            for i in range(len(cases)):
+                assert np.array_equal(to_np(outs[i]), to_np(ref_outs[i])), (pol, cfg, i)
+                assert np.array_equal(to_np(snaps[i]), to_np(ref_snaps[i])), (pol, cfg, i)
     monkeypatch.delenv("PR_FUSED_CFG")
+    monkeypatch.delenv("PR_FUSED_CHUNK")
 
 
 def test_fine_run_to_run_bitwise(ctx):
