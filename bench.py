@@ -138,6 +138,31 @@ def serving_sample(pr, ctx, budget, k):
                       f"(seeds 5000..{5000 + 2 * k - 1}); no warm-up exclusion"}
 
 
+def paper_projection(rep, serial_s, N):
+    """The paper's speedup estimate T_F N / (T_total (k + 1)) with
+    T_total = T_F + T_U + T_C + N (T_G + T_A) (Sec. 4), each term per
+    subinterval as one processor group per subinterval would see it: T_F the
+    serial fine time of one subinterval on this GPU, T_C and T_U the batched
+    POD and reduced-operator times divided by the subintervals they served,
+    T_A and T_G the sweep's augmentation and coarse times per coarse step."""
+    from paper_2601_10981_amd import costmodel
+    if serial_s is None or rep.iters < 1:
+        return None
+    Np, K = N - 1, rep.iters
+    sweep = sum(Np - k for k in range(1, K + 1)) + Np        # + the k = 0 sweep
+    pod = sum((Np - k + 1) + (Np - k) for k in range(1, K + 1)) + 1
+    T_F = serial_s / N
+    T_C = rep.t_phase["C"] / pod
+    T_U = rep.t_phase["U"] / sweep
+    T_A = rep.t_phase["A"] / sweep
+    T_G = rep.t_phase["G"] / sweep
+    T_total = costmodel.t_total(T_F, T_U, T_C, T_G, T_A, N)
+    return {"T_F_s": round(T_F, 6), "T_C_s": round(T_C, 6), "T_U_s": round(T_U, 6),
+            "T_A_s": round(T_A, 6), "T_G_s": round(T_G, 6), "T_total_s": round(T_total, 6),
+            "k": K, "speedup_estimate": round(costmodel.speedup_estimate(T_F, T_total, N, K), 4),
+            "note": "one processor group per subinterval, as the paper's estimate assumes"}
+
+
 def mixed256_run(args):
     """256^3 ABC, kappa = 0.005, T = 50 over 128 subintervals, dt = 5e-4: the
     stencil and the snapshot Grams in FP32, the rest in FP64. The FP64
@@ -399,6 +424,7 @@ def main():
         "m0": rep.m0,
         "roofline": roofline,
     }
+    out["paper_projection"] = paper_projection(rep, serial_s, N)
     if args.serve_requests > 0:
         del U_ref
         torch.cuda.empty_cache()
