@@ -51,6 +51,8 @@ def parse():
                     help="report run of K ensemble instances solved together (own JSON line)")
     ap.add_argument("--max-iter", type=int, default=4,
                     help="iterations of the --mixed256 run")
+    ap.add_argument("--study", action="store_true",
+                    help="report run of the (m_l, p) x kappa grid on 32^3 ABC (own JSON line)")
     return ap.parse_args()
 
 
@@ -258,6 +260,48 @@ def ensemble_run(args):
     print(json.dumps(out))
 
 
+def study_run(args):
+    """The paper's experimental grid on this discretisation: every local
+    collection (m_l, p) in {0,1}^2 against the diffusivity, on 32^3 ABC
+    (A = B = C = 1) with the blob initial field of seed 1, T = 2 over 16
+    subintervals, dt = 2e-3, caps 10/10, tol 1e-8. Reports iterations to
+    tol, the first iteration at or below 1e-6 relative L2 error against the
+    serial fine solution, and the solve time."""
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = pr.Context(0)
+    n, N = 32, 16
+    u0 = torch.from_numpy(W.blob_field(n, 1).reshape(-1).copy()).cuda()
+    rows = []
+    for kappa in (0.5, 0.1, 0.05, 0.01):
+        prob = pr.problem_of(W.Problem(n=n, kappa=kappa, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0)))
+        base = W.PararealOpts(T=2.0, N=N, dt=2e-3, cap0=10, cap=10, tol=1e-8)
+        plan = pr.pr_plan(prob, base)
+        ref = torch.empty((N + 1, n ** 3), dtype=torch.float64, device="cuda")
+        ref[0].copy_(u0)
+        for j in range(N):
+            pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=plan["dt"], n_steps=plan["n_f"],
+                                            u_in=ref[j], u_out=ref[j + 1])])
+        for ml, p in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            opts = W.PararealOpts(**{**base.__dict__, "ml": ml, "p": p})
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = pr.pr_parareal_solve(ctx, prob, opts, u0, U_ref=ref)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            k6 = next((k for k, e in enumerate(rep.err) if e <= 1e-6), None)
+            rows.append({"kappa": kappa, "ml": ml, "p": p, "iters": rep.iters, "m0": rep.m0,
+                         "k_err_1e-6": k6, "err_final": float("%.3e" % rep.err[-1]),
+                         "err_k1_k3": [float("%.2e" % e) for e in rep.err[1:4]],
+                         "solve_s": round(el, 3)})
+            log(f"study kappa={kappa} (m_l,p)=({ml},{p}): iters {rep.iters}, k(1e-6) {k6}")
+    ctx.close()
+    print(json.dumps({"mode": "study", "n": n, "N": N, "T": 2.0, "flow": "ABC", "rows": rows}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -267,6 +311,8 @@ def main():
         return mixed256_run(args)
     if args.ensemble > 0:
         return ensemble_run(args)
+    if args.study:
+        return study_run(args)
     import numpy as np
     import torch
     import paper_2601_10981_amd as pr

@@ -193,32 +193,44 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   }
 }
 
-// Fixed-order reduction of the chunk partials, scaled, into the output
-// matrix (row = A column, column = B column; the symmetric form mirrors).
-// 1024 threads per (pair, item): thread group q = t / 256 sums the chunks
-// c = q, q + 4, ... of element t % 256, then the four sums are combined as
-// (s0 + s1) + (s2 + s3).
+// Sum of the per-chunk partials of one tile pair, scaled, written to the
+// output (and its mirror for the symmetric form). Workgroup (x, item) owns 64
+// of the pair's 256 entries (x = pair * 4 + quarter); its 16 wave groups each
+// sum the chunks q, q + 16, q + 32, ... in that order (four accumulators, one
+// per residue of the chunk index modulo 64), and the groups' sums combine in
+// a fixed tree. The order depends only on the chunk count, so the result
+// does not depend on the batch.
 template <int NA, int NB>
 __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
   using PL = PairList<NA, NB>;
   constexpr int P = PL::P;
-  __shared__ double red[4][256];
+  __shared__ double red[16][64];
   const GemmDesc& d = descs[blockIdx.y];
-  const int p = blockIdx.x;
-  const int e = threadIdx.x & 255, q = threadIdx.x >> 8;
+  const int p = blockIdx.x >> 2;
+  const int e = ((blockIdx.x & 3) << 6) | (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;
   const PR_GLOBAL double* src = gptr(d.partial) + (long long)p * 256 + e;
   const long long stride = (long long)P * 256;
-  double a0 = 0, a1 = 0;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int c = q;
-  for (; c + 4 < d.nchunks; c += 8) {
+  for (; c + 48 < d.nchunks; c += 64) {
     a0 += src[(long long)c * stride];
-    a1 += src[(long long)(c + 4) * stride];
+    a1 += src[(long long)(c + 16) * stride];
+    a2 += src[(long long)(c + 32) * stride];
+    a3 += src[(long long)(c + 48) * stride];
   }
   if (c < d.nchunks) a0 += src[(long long)c * stride];
-  red[q][e] = a0 + a1;
+  if (c + 16 < d.nchunks) a1 += src[(long long)(c + 16) * stride];
+  if (c + 32 < d.nchunks) a2 += src[(long long)(c + 32) * stride];
+  red[q][threadIdx.x & 63] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (q != 0) return;
-  const double sum = d.scale * ((red[0][e] + red[1][e]) + (red[2][e] + red[3][e]));
+  const int l = threadIdx.x & 63;
+  double t[8];
+#pragma unroll
+  for (int g = 0; g < 8; ++g) t[g] = red[2 * g][l] + red[2 * g + 1][l];
+  const double sum =
+      d.scale * (((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])));
   const int row = e >> 4, col = e & 15;
   const int ta = PL::a(p), tb = PL::b(p);
   PR_GLOBAL double* out = gptr(d.out);
@@ -242,7 +254,8 @@ static void launch_gemm_shape(const GemmDesc* d, int nd, long long total_wg, boo
 
 template <int NA, int NB>
 static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P, nd), dim3(1024), 0, s, d);
+  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P * 4, nd), dim3(1024), 0, s,
+                     d);
 }
 
 #define PR_GEMM_SHAPES(X) \

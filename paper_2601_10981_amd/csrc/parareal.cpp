@@ -530,9 +530,9 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       }
       ph.begin(2);
       enqueue_applyL_batch(c, aw, s);
+      PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + n0, S->mS, (size_t)(n1 - n0) * 4,
+                            hipMemcpyDeviceToDevice, s));
       for (int n = n0; n < n1; ++n) {
-        PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + n, S->mS + (n - n0), 4,
-                              hipMemcpyDeviceToDevice, s));
         CoarseWork w{};
         w.prob = &S->P.prob;
         w.R = S->Psi + (size_t)(n - n0) * cap * fs;

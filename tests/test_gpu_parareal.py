@@ -92,16 +92,20 @@ def _roundoff_envelope(prob, opts, u0, base, kmax, seeds=(0, 1)):
     return env
 
 
-def test_parareal_prefix_and_iterates_match_oracle(ctx):
+@pytest.mark.parametrize("ml,p", [(1, 1), (0, 0), (1, 0), (0, 1)])
+def test_parareal_prefix_and_iterates_match_oracle(ctx, ml, p):
+    """Iterates of every local-in-time collection (m_l, p) in {0,1}^2 (the
+    grid of the paper's experiments) against the oracle."""
     import paper_2601_10981_amd as pr
     prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    opts = W.PararealOpts(**{**opts.__dict__, "ml": ml, "p": p})
     u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
     p = pr.problem_of(prob)
     ref = gpu_serial(ctx, p, opts, u0)
     ores = parareal.solve(prob, opts, u0, keep_history=True)
     env = _roundoff_envelope(prob, opts, u0, ores, 3)
     for k in range(1, 4):
-        say(f"parareal iterate k={k}")
+        say(f"parareal iterate k={k} (m_l, p) = ({ml}, {p})")
         o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
         U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
         assert rep.iters == k
