@@ -22,6 +22,12 @@ k >= 1 (lines 7-19):
   (v)   stopping ("while not converged" is unspecified): the jump
         e_k = max_{n>=1} ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M <= tol, or
         k = N' (finite termination, Sec. 2), or k = max_iter.
+
+mode = 1 is the comparison method "Parareal-I" of Sec. 4: plain parareal
+(formula4 without augmentation) whose coarse propagator is the Galerkin POD
+propagator G_0 of the k = 0 step, kept for every iteration; steps (i) and
+(ii) build no bases. Its POD window is the same warm-up subinterval
+[0, T_0], T_0 = DeltaT.
 """
 from __future__ import annotations
 
@@ -121,6 +127,7 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     ranks0: Dict[int, List[int]] = {}
     converged = Np == 0
     k = 0
+    fixed = getattr(opts, "mode", 0) == 1
     while not converged and k < max_iter:
         k += 1
         # (i) fine propagation and stage-1 POD, parallel over n
@@ -129,9 +136,14 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
         ranks0[k] = []
         for nn in range(k - 1, Np):
             t0 = time.perf_counter()
-            Fn, Wn = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f, dM)
+            if fixed:
+                Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f)
+            else:
+                Fn, Wn = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f, dM)
             t_phase["F"] += time.perf_counter() - t0
             Fk[nn] = Fn.reshape(-1)
+            if fixed:
+                continue
             t0 = time.perf_counter()
             R, m, _ = P.pod_mode(Wn, opts.gamma2, h3, opts.cap0, tau_r)
             t_phase["C"] += time.perf_counter() - t0
@@ -147,6 +159,16 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
         ranks[k] = []
         # (ii) + (iv) sequential sweep
         for nn in range(k, Np):
+            if fixed:
+                # U^k_{n+1} = G_0(P U^k_n) + F(U^{k-1}_n) - G_0(P U^{k-1}_n)
+                t0 = time.perf_counter()
+                b_new = C.reduced_rk4(Lr0, Mr0, C.project(R0, Mr0, U_cur[nn], h3), dT_sub, n_c)
+                b_old = C.reduced_rk4(Lr0, Mr0, C.project(R0, Mr0, U_prev[nn], h3), dT_sub, n_c)
+                g_new = R0 @ b_new if m0 > 0 else 0.0
+                g_old = R0 @ b_old if m0 > 0 else 0.0
+                U_cur.append(g_new + Fk[nn] - g_old)
+                t_phase["G"] += time.perf_counter() - t0
+                continue
             t0 = time.perf_counter()
             blocks = [latest(j) for j in range(nn - opts.ml, nn + 1) if j >= 0]
             blocks += [hist[k - i][nn] for i in range(1, opts.p + 1) if k - i >= 1]

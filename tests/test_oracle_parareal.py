@@ -7,6 +7,10 @@
   the fine solution.
 * The jumps of a converging run decrease and the final error is at the
   tolerance level.
+* Fixed-POD mode ("Parareal-I" of Sec. 4): the same k = 0 step as the
+  adaptive mode, finite termination, and one-iteration convergence when the
+  k = 0 basis spans an L-invariant subspace (a wrong sign or a dropped term in
+  the correction would leave the iterate off by a multiple of F).
 """
 import math
 
@@ -18,15 +22,16 @@ from oracle import parareal
 
 
 def _tiny(flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0), n=12, kappa=0.05, N=6, T=0.6,
-          dt=0.01, tol=0.0, cap0=6, cap=8, ml=1, p=1, coarse_ratio=10):
+          dt=0.01, tol=0.0, cap0=6, cap=8, ml=1, p=1, coarse_ratio=10, mode=W.MODE_ADAPTIVE):
     prob = W.Problem(n=n, kappa=kappa, flow=flow, fp=fp)
     opts = W.PararealOpts(T=T, N=N, dt=dt, cap0=cap0, cap=cap, tol=tol, ml=ml, p=p,
-                          coarse_ratio=coarse_ratio)
+                          coarse_ratio=coarse_ratio, mode=mode)
     return prob, opts
 
 
-def test_finite_termination_and_prefix():
-    prob, opts = _tiny()
+@pytest.mark.parametrize("mode", [W.MODE_ADAPTIVE, W.MODE_FIXED_POD])
+def test_finite_termination_and_prefix(mode):
+    prob, opts = _tiny(mode=mode)
     u0 = W.blob_field(prob.n, 7)
     ref = parareal.reference(prob, opts, u0)
     r = parareal.solve(prob, opts, u0, U_ref=ref, keep_history=True)
@@ -94,3 +99,32 @@ def test_single_subinterval_is_plain_fine_solve():
     r = parareal.solve(prob, opts, u0)
     assert r.iters == 0 and len(r.U) == 2
     assert np.array_equal(r.U[1], ref[1].reshape(-1))
+
+
+def test_fixed_pod_shares_the_k0_step_and_builds_no_bases():
+    prob, opts = _tiny(N=5, T=0.5)
+    fixed = W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_FIXED_POD})
+    u0 = W.fourier_field(prob.n, 8, n_modes=6, kmax=3.0)
+    a = parareal.solve(prob, opts, u0, keep_history=True)
+    b = parareal.solve(prob, fixed, u0, keep_history=True)
+    assert a.m0 == b.m0
+    for x, y in zip(a.history[0], b.history[0]):
+        assert np.array_equal(x, y)
+    assert all(len(v) == 0 for v in b.ranks.values())
+    assert all(len(v) == 0 for v in b.ranks0.values())
+    # the two coarse propagators differ after k = 0
+    assert max(np.max(np.abs(x - y)) for x, y in zip(a.history[1], b.history[1])) > 1e-8
+
+
+def test_fixed_pod_invariant_subspace_converges_in_one_iteration():
+    n = 10
+    prob = W.Problem(n=n, kappa=0.05, flow=W.FLOW_UNIFORM, fp=(0.6, -0.9, 0.4))
+    opts = W.PararealOpts(T=0.4, N=4, dt=0.01, cap0=8, cap=8, tol=1e-10, coarse_ratio=1,
+                          gamma1=1.0, gamma2=1.0, gamma3=1.0, mode=W.MODE_FIXED_POD)
+    x = np.arange(n) * (2 * math.pi / n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    u0 = np.cos(X + 2 * Y - Z) + 0.5 * np.sin(3 * Y + Z + 0.4)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref)
+    assert r.m0 == 4 and r.errors[0] <= 1e-12
+    assert r.iters == 1 and r.jumps[0] <= 1e-12 and r.errors[1] <= 1e-12

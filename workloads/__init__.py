@@ -30,6 +30,9 @@ FLOW_KOLMOGOROV = 2
 PREC_F64 = 0
 PREC_MIXED = 1
 
+MODE_ADAPTIVE = 0    # Algorithm 2: local-in-time POD bases rebuilt every iteration
+MODE_FIXED_POD = 1   # "Parareal-I" of Sec. 4: the k = 0 POD basis for every iteration
+
 
 @dataclasses.dataclass(frozen=True)
 class Problem:
@@ -66,6 +69,7 @@ class PararealOpts:
     coarse_ratio: int = 10
     tol: float = 1e-8
     max_iter: int = 0        # 0: N - 1
+    mode: int = MODE_ADAPTIVE
 
 
 @dataclasses.dataclass(frozen=True)
