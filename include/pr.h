@@ -56,6 +56,7 @@ typedef enum {
 
 enum { PR_FLOW_UNIFORM = 0, PR_FLOW_ABC = 1, PR_FLOW_KOLMOGOROV = 2 };
 enum { PR_F64 = 0, PR_MIXED = 1 };
+enum { PR_MODE_ADAPTIVE = 0, PR_MODE_FIXED_POD = 1 };
 
 /* Problem of eq1 (Sec. 4) on the finite-difference grid.
  *   flow PR_FLOW_ABC:        v = (A sin z + C cos y, B sin x + A cos z,
@@ -229,6 +230,12 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *   U_out         device, (N + 1) x N_g doubles: U_out[j] = state at j DeltaT
  *   U_ref         NULL or device (N + 1) x N_g doubles (serial fine
  *                 solution): then err[k] = max_n ||U^k_n - U_ref||/||U_ref||
+ *   mode          PR_MODE_ADAPTIVE: Algorithm 2. PR_MODE_FIXED_POD: the
+ *                 comparison method "Parareal-I" of Sec. 4 -- plain parareal
+ *                 (formula4 without augmentation) whose coarse propagator is
+ *                 the k = 0 POD Galerkin propagator for every iteration; no
+ *                 snapshots or local bases are built after k = 0, and gamma2,
+ *                 gamma3, cap0, m_l and p are ignored
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
@@ -243,6 +250,7 @@ typedef struct {
   int coarse_ratio;
   double tol;
   int max_iter;
+  int mode;        /* PR_MODE_ADAPTIVE or PR_MODE_FIXED_POD */
   const double* U_ref;
 } pr_parareal_opts;
 

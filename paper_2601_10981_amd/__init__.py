@@ -16,6 +16,7 @@ from typing import List, Optional, Sequence
 
 from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
+from ._lib import PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD  # noqa: F401
 
 __all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
            "pr_coarse_propagate", "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin",
@@ -277,6 +278,7 @@ def opts_struct(o, U_ref=None) -> L.pr_parareal_opts:
     s.coarse_ratio = int(o.coarse_ratio)
     s.tol = float(o.tol)
     s.max_iter = int(getattr(o, "max_iter", 0))
+    s.mode = int(getattr(o, "mode", 0))
     s.U_ref = _ptr(U_ref)
     return s
 

@@ -13,6 +13,7 @@ STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "P
 
 PR_FLOW_UNIFORM, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV = 0, 1, 2
 PR_F64, PR_MIXED = 0, 1
+PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD = 0, 1
 
 
 class pr_grid_problem(Structure):
@@ -46,7 +47,7 @@ class pr_parareal_opts(Structure):
                 ("gamma1", c_double), ("gamma2", c_double), ("gamma3", c_double),
                 ("cap0", c_int), ("cap", c_int), ("ml", c_int), ("p", c_int),
                 ("coarse_ratio", c_int), ("tol", c_double), ("max_iter", c_int),
-                ("U_ref", c_void_p)]
+                ("mode", c_int), ("U_ref", c_void_p)]
 
 
 class pr_report(Structure):

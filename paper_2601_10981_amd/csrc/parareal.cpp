@@ -39,6 +39,7 @@ struct Plan {
   long long ng;
   bool f32;
   size_t sf;
+  bool fixed;      // PR_MODE_FIXED_POD: the k = 0 basis for every iteration
   int waveF, waveS;
   size_t fixed_bytes, perF, perS;
 };
@@ -58,9 +59,13 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
            "gamma must be in (0, 1]");
   PR_CHECK(o->cap0 >= 1 && o->cap0 <= kMaxCap && o->cap >= 1 && o->cap <= kMaxCap,
            "caps must be in [1, 31]");
-  PR_CHECK(o->ml >= 0 && o->p >= 0 && o->p <= 1, "need m_l >= 0 and p in {0, 1}");
-  PR_CHECK((o->ml + 1 + o->p) * o->cap0 <= kMaxPodCols,
-           "(m_l + 1 + p) * cap0 must be <= 64 (local POD input)");
+  PR_CHECK(o->mode == PR_MODE_ADAPTIVE || o->mode == PR_MODE_FIXED_POD, "unknown mode");
+  P.fixed = o->mode == PR_MODE_FIXED_POD;
+  if (!P.fixed) {
+    PR_CHECK(o->ml >= 0 && o->p >= 0 && o->p <= 1, "need m_l >= 0 and p in {0, 1}");
+    PR_CHECK((o->ml + 1 + o->p) * o->cap0 <= kMaxPodCols,
+             "(m_l + 1 + p) * cap0 must be <= 64 (local POD input)");
+  }
   PR_CHECK(o->coarse_ratio >= 1, "coarse_ratio must be >= 1");
   PR_CHECK(std::isfinite(o->tol) && o->tol >= 0, "tol must be >= 0");
   P.N = o->N;
@@ -84,11 +89,14 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
   const size_t Np1 = (size_t)std::max(P.Np, 1);
   // solve-owned memory apart from the waves: two state sets, F_n, two slots
-  // of stage-1 bases, u0, small matrices
-  P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 + 2 * Np1 * o->cap0 * fs + f8 +
-                  ((size_t)4 << 20);
-  P.perF = (size_t)P.n_s * fs;       // snapshots of one subinterval
-  P.perS = 2 * (size_t)o->cap * fs;  // stage-2 basis and L applied to it
+  // of stage-1 bases, u0, small matrices. The fixed-POD mode keeps only the
+  // k = 0 snapshots and basis (one wave slot each) and no stage-1 bases.
+  P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 +
+                  (P.fixed ? (size_t)P.n_s * fs + 2 * (size_t)o->cap * fs
+                           : 2 * Np1 * o->cap0 * fs) +
+                  f8 + ((size_t)4 << 20);
+  P.perF = P.fixed ? 0 : (size_t)P.n_s * fs;        // snapshots of one subinterval
+  P.perS = P.fixed ? 0 : 2 * (size_t)o->cap * fs;   // stage-2 basis and L applied to it
   return P;
 }
 
@@ -139,10 +147,11 @@ static void choose_waves(Plan& P, size_t avail) {
     return P.fixed_bytes + (size_t)wf * P.perF + (size_t)ws * P.perS + shared_scratch_bytes(Q);
   };
   if (need(1, 1) > avail) fail(PR_ENOMEM, "parareal solve does not fit the HBM budget");
-  int wf = Np, ws = Np;
+  int wf = Np, ws = P.fixed ? 1 : Np;
   while (need(wf, ws) > avail && (wf > 1 || ws > 1)) {
     // halve the larger of the two wave buffers first
-    if (((size_t)wf * P.perF >= (size_t)ws * P.perS && wf > 1) || ws == 1) wf = (wf + 1) / 2;
+    if (((size_t)wf * P.perF >= (size_t)ws * P.perS && wf > 1) || ws == 1 || P.fixed)
+      wf = (wf + 1) / 2;
     else ws = (ws + 1) / 2;
   }
   P.waveF = wf;
@@ -242,8 +251,8 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     }
     S->U[1] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
     S->Fn = (double*)owned_alloc(c, S, Np1 * f8);
-    S->R0 = (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
-    S->snaps = (char*)owned_alloc(c, S, (size_t)P.waveF * P.n_s * fs);
+    S->R0 = P.fixed ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
+    S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * fs);
     S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
     S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
     const int maxk = P.max_iter;
@@ -412,6 +421,16 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       const size_t fs = (size_t)P.ng * P.sf;
       const double* Uprev = S->U[S->prev];
       for (int n = n0; n < n1; ++n) {
+        if (P.fixed) {
+          // plain fine solves: no snapshots, no stage-1 basis (an empty POD
+          // item is skipped below)
+          fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
+                                S->Fn + (size_t)n * P.ng, 0, nullptr});
+          PodWork none;
+          none.prob = &S->P.prob;
+          pw.push_back(none);
+          continue;
+        }
         void* sn = S->snaps + (size_t)(n - n0) * P.n_s * fs;
         fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
                               S->Fn + (size_t)n * P.ng, P.dM, sn});
@@ -445,11 +464,11 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       while (i0 < f2.size()) {
         size_t i1 = i0 + 1, fb = 0, pb = 0;
         fb += fine_scratch_item(ngrid(*f2[i0].prob), prec == PR_MIXED);
-        pb += pod_scratch_item(ngrid(*f2[i0].prob));
+        pb += p2[i0].cols.empty() ? 0 : pod_scratch_item(ngrid(*f2[i0].prob));
         for (; i1 < f2.size(); ++i1) {
           const long long ng1 = ngrid(*f2[i1].prob);
           const size_t fb1 = fb + fine_scratch_item(ng1, prec == PR_MIXED);
-          const size_t pb1 = pb + pod_scratch_item(ng1);
+          const size_t pb1 = pb + (p2[i1].cols.empty() ? 0 : pod_scratch_item(ng1));
           if (!helpers_fit(c, fb1, pb1)) break;
           fb = fb1;
           pb = pb1;
@@ -491,8 +510,33 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
     enqueue_correct(c, ng, {}, nullptr, S->Fn + (size_t)(k - 1) * ng, 0, Ucur + (size_t)k * ng,
                     Uprev + (size_t)k * ng, Uref ? Uref + (size_t)(k + 1) * ng : nullptr,
                     S->norms + 4 * k, h3, s, "sol");
+    // (iv) for the fixed-POD mode: the k = 0 basis (wave slot 0 of the stage-2
+    // buffers, never overwritten in this mode) without augmentation
+    if (P.fixed) {
+      ph.begin(4);
+      for (int n = k; n < Np; ++n) {
+        CoarseWork w{};
+        w.prob = &S->P.prob;
+        w.R = S->Psi;
+        w.LR = S->LPsi;
+        w.cap = cap;
+        w.m = S->mS;
+        w.u_aug = nullptr;
+        w.n_in = 2;
+        w.u_in[0] = Ucur + (size_t)n * ng;
+        w.u_in[1] = Uprev + (size_t)n * ng;
+        w.dT = P.dTs;
+        w.n_c = P.n_c;
+        w.corr_out = Ucur + (size_t)(n + 1) * ng;
+        w.fine = S->Fn + (size_t)n * ng;
+        w.prev = Uprev + (size_t)(n + 1) * ng;
+        w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+        w.norms4 = S->norms + 4 * (n + 1);
+        enqueue_coarse(c, w, s, &ph);
+      }
+    }
     // (ii) + (iv)
-    for (int n0 = k; n0 < Np; n0 += P.waveS) {
+    for (int n0 = k; n0 < Np && !P.fixed; n0 += P.waveS) {
       const int n1 = std::min(Np, n0 + P.waveS);
       std::vector<PodWork> pw;
       std::vector<ApplyLWork> aw;
@@ -633,7 +677,8 @@ static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* 
 
 static size_t footprint(const pr_grid_problem* p, const pr_parareal_opts* o) {
   Plan P = make_plan(p, o);
-  P.waveF = P.waveS = std::max(P.Np, 1);
+  P.waveF = std::max(P.Np, 1);
+  P.waveS = P.fixed ? 1 : std::max(P.Np, 1);
   return P.fixed_bytes + P.perF * P.waveF + P.perS * P.waveS + shared_scratch_bytes(P);
 }
 

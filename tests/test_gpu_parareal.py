@@ -193,3 +193,38 @@ def test_parareal_errors(ctx):
     one = W.PararealOpts(**{**opts.__dict__, "max_iter": 1, "tol": 0.0})
     U, rep = pr.pr_parareal_solve(ctx, p, one, u0)
     assert rep.status == -5 and rep.iters == 1
+
+
+def test_fixed_pod_mode_matches_oracle(ctx):
+    """The fixed-POD comparison method ("Parareal-I", Sec. 4): iterates
+    against the oracle within its round-off envelope, finite termination
+    bitwise against the GPU serial solve, and the same k = 0 step as the
+    adaptive mode."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    opts = W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_FIXED_POD})
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    ores = parareal.solve(prob, opts, u0, keep_history=True)
+    env = _roundoff_envelope(prob, opts, u0, ores, 3)
+    for k in range(1, 4):
+        say(f"fixed-POD iterate k={k}")
+        o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
+        U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+        assert rep.iters == k and rep.m0 == ores.m0
+        Un = to_np(U)
+        for j in range(0, k + 2):
+            assert np.array_equal(Un[j], to_np(ref[j])), (k, j)
+        worst = max(rel_l2(Un[j + 1], h) for j, h in enumerate(ores.history[k]))
+        say(f"  k={k} worst rel L2 vs oracle {worst:.3e} (envelope {env[k]:.3e})")
+        assert worst <= 10.0 * env[k] + 1e-12
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.iters == opts.N - 1 and rep.converged
+    assert np.array_equal(to_np(U), to_np(ref))
+    # k = 0 is the adaptive method's
+    a0 = W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_ADAPTIVE, "max_iter": 1})
+    f0 = W.PararealOpts(**{**opts.__dict__, "max_iter": 1})
+    _, ra = pr.pr_parareal_solve(ctx, p, a0, to_dev(u0), U_ref=ref)
+    _, rf = pr.pr_parareal_solve(ctx, p, f0, to_dev(u0), U_ref=ref)
+    assert ra.err[0] == rf.err[0] and ra.m0 == rf.m0

@@ -12,9 +12,11 @@ from gpu_helpers import say, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 
-def _case(n, N, prec, flow, fp, kappa, seed, tol=0.0, max_iter=0, cap0=6, cap=8):
+def _case(n, N, prec, flow, fp, kappa, seed, tol=0.0, max_iter=0, cap0=6, cap=8,
+          mode=W.MODE_ADAPTIVE):
     prob = W.Problem(n=n, kappa=kappa, flow=flow, fp=fp, precision=prec)
-    opts = W.PararealOpts(T=0.1 * N, N=N, dt=0.01, cap0=cap0, cap=cap, tol=tol, max_iter=max_iter)
+    opts = W.PararealOpts(T=0.1 * N, N=N, dt=0.01, cap0=cap0, cap=cap, tol=tol, max_iter=max_iter,
+                          mode=mode)
     return prob, opts, W.fourier_field(n, seed, n_modes=6, kmax=3.0)
 
 
@@ -23,6 +25,8 @@ CASES = [
     _case(16, 6, W.PREC_MIXED, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.1, 5, tol=1e-6),
     _case(20, 10, W.PREC_F64, W.FLOW_ABC, (1.0, 0.7, 0.4), 0.05, 3, tol=1e-7, cap0=8, cap=10),
     _case(12, 5, W.PREC_F64, W.FLOW_UNIFORM, (1.0, 0.5, 0.25), 0.2, 11, max_iter=2),
+    _case(16, 7, W.PREC_F64, W.FLOW_KOLMOGOROV, (1.0, 1.0, 0.0), 0.2, 13, tol=1e-8,
+          mode=W.MODE_FIXED_POD),
 ]
 
 
@@ -106,6 +110,8 @@ def test_finished_handle_untouched_and_budget_admission():
     prob, opts, u0 = CASES[3]
     p = pr.problem_of(prob)
     need = pr.pr_footprint(p, opts)
+    fixed_need = pr.pr_footprint(pr.problem_of(CASES[4][0]), CASES[4][1])
+    assert 0 < fixed_need
     with pr.Context(0) as c:
         h = pr.pr_solve_begin(c, p, opts, to_dev(u0))
         while not h.done:
