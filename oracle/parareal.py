@@ -28,6 +28,11 @@ mode = 1 is the comparison method "Parareal-I" of Sec. 4: plain parareal
 propagator G_0 of the k = 0 step, kept for every iteration; steps (i) and
 (ii) build no bases. Its POD window is the same warm-up subinterval
 [0, T_0], T_0 = DeltaT.
+
+mode = 2 is "Parareal-II" of Sec. 4: plain parareal whose coarse propagator
+solves the same equation on the coarse n/2 grid (gridcoarse.py); no POD at
+all. The warm-up subinterval and the numbering are kept, so all three modes
+share U^0_0 = F(u0).
 """
 from __future__ import annotations
 
@@ -40,6 +45,7 @@ import numpy as np
 
 from . import coarse as C
 from . import fd
+from . import gridcoarse as GC
 from . import pod as P
 
 
@@ -99,6 +105,10 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     F0, W = fd.fine_propagate(op, u0v.reshape(n, n, n), dt, n_f, dM)
     t_phase["F"] += time.perf_counter() - t0
     U0hat = F0.reshape(-1)
+    mode = getattr(opts, "mode", 0)
+    if mode == 2:
+        return _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter,
+                                  err_of, keep_history, t_phase, h3)
     t0 = time.perf_counter()
     R0, m0, _ = P.pod_mode(W, opts.gamma1, h3, opts.cap, tau_r)
     t_phase["C"] += time.perf_counter() - t0
@@ -215,6 +225,67 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
                   ranks=ranks, ranks0=ranks0, m0=m0, n_f=n_f, dt=dt, dM=dM,
                   n_c=n_c, history=history, t_phase=t_phase)
+
+
+def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, err_of,
+                       keep_history, t_phase, h3) -> Result:
+    """Parareal-II: U^0_{n+1} = G(U^0_n) and, for k >= 1,
+    U^k_{n+1} = G(U^k_n) + F(U^{k-1}_n) - G(U^{k-1}_n), G the coarse-grid
+    propagator (formula4 with the coarse spatial discretisation)."""
+    n = prob.n
+    N = opts.N
+    Np = N - 1
+    dT_sub = opts.T / N
+    prob_c = GC.coarse_problem(prob)
+    op_c = fd.Operator.of(prob_c)
+    n_g = GC.grid_steps(prob_c, dT_sub, n_f, opts.coarse_ratio)
+
+    def G(u):
+        t0 = time.perf_counter()
+        v = GC.coarse_grid_propagate(op_c, u, dT_sub, n_g)
+        t_phase["G"] += time.perf_counter() - t0
+        return v
+
+    U_prev = [U0hat]
+    for _ in range(Np):
+        U_prev.append(G(U_prev[-1]))
+    errors = []
+    e0 = err_of(U_prev)
+    if e0 is not None:
+        errors.append(e0)
+    history = [list(U_prev)] if keep_history else []
+    jumps: List[float] = []
+    converged = Np == 0
+    k = 0
+    while not converged and k < max_iter:
+        k += 1
+        Fk = {}
+        for nn in range(k - 1, Np):
+            t0 = time.perf_counter()
+            Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f)
+            t_phase["F"] += time.perf_counter() - t0
+            Fk[nn] = Fn.reshape(-1)
+        U_cur = [U_prev[j] for j in range(k)]
+        U_cur.append(Fk[k - 1])
+        for nn in range(k, Np):
+            U_cur.append(G(U_cur[nn]) + Fk[nn] - G(U_prev[nn]))
+        e = 0.0
+        for j in range(1, Np + 1):
+            nrm = _norm_m(U_cur[j], h3)
+            dj = _norm_m(U_cur[j] - U_prev[j], h3)
+            e = max(e, dj / nrm if nrm > 0 else (0.0 if dj == 0 else math.inf))
+        jumps.append(e)
+        ek = err_of(U_cur)
+        if ek is not None:
+            errors.append(ek)
+        if keep_history:
+            history.append(list(U_cur))
+        U_prev = U_cur
+        converged = (e <= opts.tol) or (k == Np)
+    U_out = [u0v.copy()] + [u.copy() for u in U_prev]
+    return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
+                  ranks={}, ranks0={}, m0=0, n_f=n_f, dt=dt, dM=dM, n_c=n_g,
+                  history=history, t_phase=t_phase)
 
 
 def reference(prob, opts, u0: np.ndarray) -> List[np.ndarray]:

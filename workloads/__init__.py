@@ -32,6 +32,7 @@ PREC_MIXED = 1
 
 MODE_ADAPTIVE = 0    # Algorithm 2: local-in-time POD bases rebuilt every iteration
 MODE_FIXED_POD = 1   # "Parareal-I" of Sec. 4: the k = 0 POD basis for every iteration
+MODE_COARSE_GRID = 2  # "Parareal-II" of Sec. 4: the equation on the n/2 grid as coarse propagator
 
 
 @dataclasses.dataclass(frozen=True)
