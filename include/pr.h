@@ -56,7 +56,7 @@ typedef enum {
 
 enum { PR_FLOW_UNIFORM = 0, PR_FLOW_ABC = 1, PR_FLOW_KOLMOGOROV = 2 };
 enum { PR_F64 = 0, PR_MIXED = 1 };
-enum { PR_MODE_ADAPTIVE = 0, PR_MODE_FIXED_POD = 1 };
+enum { PR_MODE_ADAPTIVE = 0, PR_MODE_FIXED_POD = 1, PR_MODE_COARSE_GRID = 2 };
 
 /* Problem of eq1 (Sec. 4) on the finite-difference grid.
  *   flow PR_FLOW_ABC:        v = (A sin z + C cos y, B sin x + A cos z,
@@ -235,7 +235,13 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *                 (formula4 without augmentation) whose coarse propagator is
  *                 the k = 0 POD Galerkin propagator for every iteration; no
  *                 snapshots or local bases are built after k = 0, and gamma2,
- *                 gamma3, cap0, m_l and p are ignored
+ *                 gamma3, cap0, m_l and p are ignored. PR_MODE_COARSE_GRID:
+ *                 "Parareal-II" of Sec. 4 -- plain parareal whose coarse
+ *                 propagator solves the same equation on the n/2 grid (n even,
+ *                 n >= 8): full-weighting restriction, RK4 with
+ *                 n_g = n_c steps doubled while DeltaT / n_g * rho_c > 2.5
+ *                 (rho_c the bound above on the coarse grid), linear
+ *                 interpolation back; no POD
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
@@ -250,7 +256,7 @@ typedef struct {
   int coarse_ratio;
   double tol;
   int max_iter;
-  int mode;        /* PR_MODE_ADAPTIVE or PR_MODE_FIXED_POD */
+  int mode;        /* PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD or PR_MODE_COARSE_GRID */
   const double* U_ref;
 } pr_parareal_opts;
 

@@ -16,7 +16,7 @@ from typing import List, Optional, Sequence
 
 from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
-from ._lib import PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD  # noqa: F401
+from ._lib import PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD, PR_MODE_COARSE_GRID  # noqa: F401
 
 __all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
            "pr_coarse_propagate", "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin",

@@ -13,7 +13,7 @@ STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "P
 
 PR_FLOW_UNIFORM, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV = 0, 1, 2
 PR_F64, PR_MIXED = 0, 1
-PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD = 0, 1
+PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD, PR_MODE_COARSE_GRID = 0, 1, 2
 
 
 class pr_grid_problem(Structure):

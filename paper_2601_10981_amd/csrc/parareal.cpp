@@ -40,6 +40,10 @@ struct Plan {
   bool f32;
   size_t sf;
   bool fixed;      // PR_MODE_FIXED_POD: the k = 0 basis for every iteration
+  bool grid;       // PR_MODE_COARSE_GRID: the n/2 grid as coarse propagator
+  pr_grid_problem pc;   // the coarse-grid problem (grid mode)
+  int n_g;              // coarse-grid RK4 steps per subinterval (grid mode)
+  double dt_c;
   int waveF, waveS;
   size_t fixed_bytes, perF, perS;
 };
@@ -59,9 +63,13 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
            "gamma must be in (0, 1]");
   PR_CHECK(o->cap0 >= 1 && o->cap0 <= kMaxCap && o->cap >= 1 && o->cap <= kMaxCap,
            "caps must be in [1, 31]");
-  PR_CHECK(o->mode == PR_MODE_ADAPTIVE || o->mode == PR_MODE_FIXED_POD, "unknown mode");
+  PR_CHECK(o->mode == PR_MODE_ADAPTIVE || o->mode == PR_MODE_FIXED_POD ||
+               o->mode == PR_MODE_COARSE_GRID,
+           "unknown mode");
   P.fixed = o->mode == PR_MODE_FIXED_POD;
-  if (!P.fixed) {
+  P.grid = o->mode == PR_MODE_COARSE_GRID;
+  if (P.grid) PR_CHECK(p->n % 2 == 0 && p->n / 2 >= 4, "the coarse grid needs an even n >= 8");
+  if (o->mode == PR_MODE_ADAPTIVE) {
     PR_CHECK(o->ml >= 0 && o->p >= 0 && o->p <= 1, "need m_l >= 0 and p in {0, 1}");
     PR_CHECK((o->ml + 1 + o->p) * o->cap0 <= kMaxPodCols,
              "(m_l + 1 + p) * cap0 must be <= 64 (local POD input)");
@@ -86,17 +94,29 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   P.sf = P.f32 ? 4 : 8;
   if (P.dt * spectral_bound(*p) > kStabRK4)
     fail(PR_EUNSTABLE, "fine step exceeds the RK4 stability bound 2.6 / rho(L)");
+  if (P.grid) {
+    // the same problem on the n/2 grid; the coarse step rule, doubled while
+    // the explicit coarse step would leave RK4's stability region
+    P.pc = *p;
+    P.pc.n = p->n / 2;
+    const double rho_c = spectral_bound(P.pc);
+    P.n_g = P.n_c;
+    while (P.dTs / P.n_g * rho_c > kGuard) P.n_g *= 2;
+    P.dt_c = P.dTs / P.n_g;
+  }
   const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
   const size_t Np1 = (size_t)std::max(P.Np, 1);
   // solve-owned memory apart from the waves: two state sets, F_n, two slots
   // of stage-1 bases, u0, small matrices. The fixed-POD mode keeps only the
   // k = 0 snapshots and basis (one wave slot each) and no stage-1 bases.
+  const bool plain = P.fixed || P.grid;   // no local bases after k = 0
   P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 +
-                  (P.fixed ? (size_t)P.n_s * fs + 2 * (size_t)o->cap * fs
-                           : 2 * Np1 * o->cap0 * fs) +
+                  (P.grid ? 0
+                          : (P.fixed ? (size_t)P.n_s * fs + 2 * (size_t)o->cap * fs
+                                     : 2 * Np1 * o->cap0 * fs)) +
                   f8 + ((size_t)4 << 20);
-  P.perF = P.fixed ? 0 : (size_t)P.n_s * fs;        // snapshots of one subinterval
-  P.perS = P.fixed ? 0 : 2 * (size_t)o->cap * fs;   // stage-2 basis and L applied to it
+  P.perF = plain ? 0 : (size_t)P.n_s * fs;        // snapshots of one subinterval
+  P.perS = plain ? 0 : 2 * (size_t)o->cap * fs;   // stage-2 basis and L applied to it
   return P;
 }
 
@@ -133,9 +153,11 @@ static size_t shared_scratch_bytes(const Plan& P) {
   const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
   const long long ch = gram_chunk_rows(P.ng);
   const size_t nch = (size_t)((P.ng + ch - 1) / ch);
+  // coarse-grid mode: two coarse fields, the coarse fine-step work fields
+  const size_t grid = P.grid ? (size_t)P.pc.n * P.pc.n * P.pc.n * (16 + (P.f32 ? 12 : 8)) : 0;
   return fine_scratch_item(P.ng, P.f32) * (size_t)std::max(P.waveF, 1) +
          pod_scratch_item(P.ng) * (size_t)std::max({P.waveF, P.waveS, 1}) + 2 * fs + f8 +
-         (size_t)P.o.cap * fs + nch * 10 * 256 * 8 + ((size_t)16 << 20);
+         (size_t)P.o.cap * fs + nch * 10 * 256 * 8 + grid + ((size_t)16 << 20);
 }
 
 static void choose_waves(Plan& P, size_t avail) {
@@ -147,10 +169,10 @@ static void choose_waves(Plan& P, size_t avail) {
     return P.fixed_bytes + (size_t)wf * P.perF + (size_t)ws * P.perS + shared_scratch_bytes(Q);
   };
   if (need(1, 1) > avail) fail(PR_ENOMEM, "parareal solve does not fit the HBM budget");
-  int wf = Np, ws = P.fixed ? 1 : Np;
+  int wf = Np, ws = (P.fixed || P.grid) ? 1 : Np;
   while (need(wf, ws) > avail && (wf > 1 || ws > 1)) {
     // halve the larger of the two wave buffers first
-    if (((size_t)wf * P.perF >= (size_t)ws * P.perS && wf > 1) || ws == 1 || P.fixed)
+    if (((size_t)wf * P.perF >= (size_t)ws * P.perS && wf > 1) || ws == 1 || P.fixed || P.grid)
       wf = (wf + 1) / 2;
     else ws = (ws + 1) / 2;
   }
@@ -218,6 +240,33 @@ static double since(const pr_solve* S) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
 }
 
+// One coarse-grid coarse step: out = P(F_c(R(a - b))) + fine (b, fine
+// nullable), with the jump / error partials of out into norms4 (the
+// comparison method with a coarser spatial discretisation, Sec. 4).
+static void enqueue_grid_step(pr_ctx* c, pr_solve* S, const double* a, const double* b,
+                              const double* fine, double* out, const double* prev,
+                              const double* ref, double* norms4, hipStream_t s) {
+  const Plan& P = S->P;
+  const int m = P.pc.n;
+  const long long mc = (long long)m * m * m;
+  double* cb = (double*)scratch(c, "co_grid", (size_t)mc * 2 * 8);
+  const int nwg = (int)std::min<long long>(4096, std::max<long long>(1, (P.ng + 2047) / 2048));
+  double* part = (double*)scratch(c, "co_gpart", (size_t)nwg * 4 * 8);
+  RestrictDesc rd{m, a, b, cb};
+  RestrictDesc* rdd = stage_push1(c, rd);
+  stage_flush(c, s);
+  launch_restrict(rdd, mc, s);
+  enqueue_fine(c, {FineWork{&S->P.pc, P.dt_c, P.n_g, cb, cb + mc, 0, nullptr}}, s, "co_fine");
+  const double h = spacing(P.prob);
+  ProlongDesc pd{m, cb + mc, fine, out, prev, ref, part, nwg};
+  ProlongDesc* pdd = stage_push1(c, pd);
+  NormReduceDesc nr{part, nwg, h * h * h, norms4};
+  NormReduceDesc* nrd = stage_push1(c, nr);
+  stage_flush(c, s);
+  launch_prolong_add(pdd, nwg, s);
+  launch_norm_reduce(nrd, 1, s);
+}
+
 // Allocate the solve, enqueue k = 0 (Alg. 2 lines 3-5) and synchronise.
 static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
                              const double* u0, double* U_out, hipStream_t s) {
@@ -251,10 +300,12 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     }
     S->U[1] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
     S->Fn = (double*)owned_alloc(c, S, Np1 * f8);
-    S->R0 = P.fixed ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
-    S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * fs);
-    S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
-    S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+    S->R0 = (P.fixed || P.grid) ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
+    if (!P.grid) {
+      S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * fs);
+      S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+      S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+    }
     const int maxk = P.max_iter;
     const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 80, n_dscal = 8;
     const size_t n_dbl = n_norms + n_betas + n_S0 + n_dscal;
@@ -288,9 +339,18 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     ph.s = s;
     stage_begin(c, s);
     ph.begin(0);
-    enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.dM, S->snaps}}, s, "sol_fine");
+    enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.grid ? 0 : P.dM,
+                              P.grid ? nullptr : S->snaps}},
+                 s, "sol_fine");
     S->fine_updates += (double)P.n_f * ng;
-    if (Np > 0) {
+    if (Np > 0 && P.grid) {
+      // U^0_{n+1} = G(U^0_n) with the coarse-grid propagator
+      ph.begin(4);
+      for (int n = 0; n < Np; ++n)
+        enqueue_grid_step(c, S, Ua + (size_t)n * ng, nullptr, nullptr, Ua + (size_t)(n + 1) * ng,
+                          nullptr, S->U_ref ? S->U_ref + (size_t)(n + 2) * ng : nullptr,
+                          S->norms + 4 * (n + 1), s);
+    } else if (Np > 0) {
       ph.begin(1);
       PodWork pw;
       pw.prob = &S->P.prob;
@@ -421,7 +481,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       const size_t fs = (size_t)P.ng * P.sf;
       const double* Uprev = S->U[S->prev];
       for (int n = n0; n < n1; ++n) {
-        if (P.fixed) {
+        if (P.fixed || P.grid) {
           // plain fine solves: no snapshots, no stage-1 basis (an empty POD
           // item is skipped below)
           fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
@@ -510,6 +570,16 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
     enqueue_correct(c, ng, {}, nullptr, S->Fn + (size_t)(k - 1) * ng, 0, Ucur + (size_t)k * ng,
                     Uprev + (size_t)k * ng, Uref ? Uref + (size_t)(k + 1) * ng : nullptr,
                     S->norms + 4 * k, h3, s, "sol");
+    // (iv) for the coarse-grid mode: G(U^k_n) - G(U^{k-1}_n) = G(U^k_n -
+    // U^{k-1}_n) by linearity, plus F_n
+    if (P.grid) {
+      ph.begin(4);
+      for (int n = k; n < Np; ++n)
+        enqueue_grid_step(c, S, Ucur + (size_t)n * ng, Uprev + (size_t)n * ng,
+                          S->Fn + (size_t)n * ng, Ucur + (size_t)(n + 1) * ng,
+                          Uprev + (size_t)(n + 1) * ng,
+                          Uref ? Uref + (size_t)(n + 2) * ng : nullptr, S->norms + 4 * (n + 1), s);
+    }
     // (iv) for the fixed-POD mode: the k = 0 basis (wave slot 0 of the stage-2
     // buffers, never overwritten in this mode) without augmentation
     if (P.fixed) {
@@ -536,7 +606,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       }
     }
     // (ii) + (iv)
-    for (int n0 = k; n0 < Np && !P.fixed; n0 += P.waveS) {
+    for (int n0 = k; n0 < Np && !P.fixed && !P.grid; n0 += P.waveS) {
       const int n1 = std::min(Np, n0 + P.waveS);
       std::vector<PodWork> pw;
       std::vector<ApplyLWork> aw;
@@ -678,7 +748,7 @@ static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* 
 static size_t footprint(const pr_grid_problem* p, const pr_parareal_opts* o) {
   Plan P = make_plan(p, o);
   P.waveF = std::max(P.Np, 1);
-  P.waveS = P.fixed ? 1 : std::max(P.Np, 1);
+  P.waveS = (P.fixed || P.grid) ? 1 : std::max(P.Np, 1);
   return P.fixed_bytes + P.perF * P.waveF + P.perS * P.waveS + shared_scratch_bytes(P);
 }
 

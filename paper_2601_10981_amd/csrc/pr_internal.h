@@ -277,6 +277,26 @@ void launch_aug_decide(const AugDesc* d, int nitems, hipStream_t s);
 
 // Partial-sum reduction of jump norms: per item sums partial (nwg x 4) in
 // fixed order into out (4 doubles, times h^3).
+// ---- grid transfers of the coarse-grid coarse propagator ---------------------
+struct RestrictDesc {
+  int m;               // coarse points per axis (fine n = 2 m)
+  const double* a;     // fine field
+  const double* b;     // fine field subtracted first (nullable)
+  double* out;         // m^3 coarse values
+};
+struct ProlongDesc {
+  int m;               // coarse points per axis
+  const double* c;     // m^3 coarse values
+  const double* fine;  // added after interpolation (nullable)
+  double* out;         // (2 m)^3 fine values
+  const double* prev;  // nullable: jump partials against it
+  const double* ref;   // nullable: error partials against it
+  double* partial;     // nwg x 4 (layout of CorrectDesc::partial)
+  int nwg;
+};
+void launch_restrict(const RestrictDesc* d, long long coarse_points, hipStream_t s);
+void launch_prolong_add(const ProlongDesc* d, int nwg, hipStream_t s);
+
 struct NormReduceDesc {
   const double* partial;
   int nwg;

@@ -228,3 +228,39 @@ def test_fixed_pod_mode_matches_oracle(ctx):
     _, ra = pr.pr_parareal_solve(ctx, p, a0, to_dev(u0), U_ref=ref)
     _, rf = pr.pr_parareal_solve(ctx, p, f0, to_dev(u0), U_ref=ref)
     assert ra.err[0] == rf.err[0] and ra.m0 == rf.m0
+
+
+@pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
+def test_coarse_grid_mode_matches_oracle(ctx, prec):
+    """The coarse-grid comparison method ("Parareal-II", Sec. 4): no POD, so
+    FP64 iterates match the oracle to 1e-12 at every k (mixed precision: the
+    FP32 stencil's 1e-5); finite termination bitwise against the GPU serial
+    solve (FP64)."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=16, N=7, T=0.7, kappa=0.1, flow=W.FLOW_ABC, fp=(1.0, 0.8, 0.6), prec=prec)
+    opts = W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_COARSE_GRID})
+    u0 = W.fourier_field(prob.n, 12, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    p64 = pr.problem_of(W.Problem(n=16, kappa=0.1, flow=W.FLOW_ABC, fp=(1.0, 0.8, 0.6)))
+    ref = gpu_serial(ctx, p64, opts, u0)
+    prob64 = W.Problem(n=16, kappa=0.1, flow=W.FLOW_ABC, fp=(1.0, 0.8, 0.6))
+    ores = parareal.solve(prob64, opts, u0, keep_history=True)
+    tol = 1e-12 if prec == W.PREC_F64 else 1e-5
+    for k in (1, 3):
+        say(f"coarse-grid iterate k={k} prec={prec}")
+        o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
+        U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+        assert rep.iters == k and rep.m0 == 0
+        Un = to_np(U)
+        worst = max(rel_l2(Un[j + 1], h) for j, h in enumerate(ores.history[k]))
+        say(f"  worst rel L2 vs oracle {worst:.3e}")
+        assert worst <= tol
+    if prec == W.PREC_F64:
+        U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+        assert rep.iters == opts.N - 1 and rep.converged
+        assert np.array_equal(to_np(U), to_np(ref))
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_parareal_solve(ctx, pr.problem_of(W.Problem(n=6, kappa=0.1, flow=W.FLOW_ABC,
+                                                          fp=(1.0, 1.0, 1.0))),
+                             opts, to_dev(W.blob_field(6, 1)))
+    assert e.value.name == "PR_EINVAL"

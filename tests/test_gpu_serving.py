@@ -27,6 +27,8 @@ CASES = [
     _case(12, 5, W.PREC_F64, W.FLOW_UNIFORM, (1.0, 0.5, 0.25), 0.2, 11, max_iter=2),
     _case(16, 7, W.PREC_F64, W.FLOW_KOLMOGOROV, (1.0, 1.0, 0.0), 0.2, 13, tol=1e-8,
           mode=W.MODE_FIXED_POD),
+    _case(16, 6, W.PREC_MIXED, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.15, 14, tol=1e-7,
+          mode=W.MODE_COARSE_GRID),
 ]
 
 
