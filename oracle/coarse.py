@@ -22,6 +22,14 @@ Readings where the paper is silent or differs from this discretisation:
   * Degenerate augmentation (U in span R): skipped when
     ||d~||_M <= tau_aug ||U||_M, tau_aug = 1e-12.
   * M_r is kept explicitly (eq13 keeps Psi^T M Psi).
+  * Forced, time-dependent flows (Sec. 4): the reduced system is
+    M_r beta' = L_r(t) beta + f_r(t) with L_r(t) = Psi^T M L(t) Psi and
+    f_r(t) = Psi^T M f(t), integrated by classical RK4 from the start time of
+    the subinterval with stages at t, t + dT/2, t + dT/2, t + dT. The guard
+    uses sum_j ||M_r^{-1} L_r,j||_F over the time-space pieces of the flow
+    (fd.pieces: L(t) = L_0 + sum_{j>=1} theta_j(t) L_j with |theta_j| <= 1),
+    which bounds ||M_r^{-1} L_r(t)||_F at every t and is the single Frobenius
+    norm above for a steady flow.
 """
 from __future__ import annotations
 
@@ -96,15 +104,98 @@ def reduced_rk4(Lr: np.ndarray, Mr: np.ndarray, beta: np.ndarray,
     return b
 
 
-def coarse_propagate(op, Psi: np.ndarray, states, dT_total: float, n_c: int, h3: float):
+class ReducedSystem:
+    """The Galerkin system of one basis Psi: M_r beta' = L_r beta for a steady
+    flow, M_r beta' = L_r(t) beta + f_r(t) for a forced time-dependent one
+    (L_r(t) and f_r(t) formed from their definitions at every stage time)."""
+
+    def __init__(self, op, Psi: np.ndarray, h3: float):
+        self.op = op
+        self.Psi = Psi
+        self.h3 = h3
+        self.q = Psi.shape[1]
+        self.forced = getattr(op, "forced", False)
+        if self.forced:
+            self.Mr = h3 * (Psi.T @ Psi)
+            self.Lr = None
+        else:
+            self.Lr, self.Mr = reduced_matrices(op, Psi, h3)
+        self._memo = {}
+
+    def at(self, t: float):
+        """K(t) = M_r^{-1} L_r(t) and g(t) = M_r^{-1} f_r(t)."""
+        if t not in self._memo:
+            n = self.op.n
+            LPsi = np.empty_like(self.Psi)
+            for j in range(self.q):
+                LPsi[:, j] = self.op.apply(self.Psi[:, j].reshape(n, n, n), t).reshape(-1)
+            Lr = self.h3 * (self.Psi.T @ LPsi)
+            fr = self.h3 * (self.Psi.T @ self.op.forcing(t).reshape(-1))
+            self._memo[t] = (np.linalg.solve(self.Mr, Lr), np.linalg.solve(self.Mr, fr))
+        return self._memo[t]
+
+    def piece_norm(self) -> float:
+        """sum_j ||M_r^{-1} Psi^T M L_j Psi||_F over the flow's pieces."""
+        from . import fd
+        op = self.op
+        n = op.n
+        total = 0.0
+        for j, (_, vel, _) in enumerate(fd.pieces(n, op.flow, op.fp, op.L)):
+            LPsi = np.empty_like(self.Psi)
+            for c in range(self.q):
+                LPsi[:, c] = fd.apply_with(self.Psi[:, c].reshape(n, n, n), op.h,
+                                           op.kappa if j == 0 else 0.0, vel).reshape(-1)
+            K = np.linalg.solve(self.Mr, self.h3 * (self.Psi.T @ LPsi))
+            total += float(np.linalg.norm(K, "fro"))
+        return total
+
+    def guarded_steps(self, dT_total: float, n_c: int) -> int:
+        if not self.forced:
+            return guarded_steps(self.Lr, self.Mr, dT_total, n_c)
+        if self.q == 0:
+            return n_c
+        nrm = self.piece_norm()
+        while (dT_total / n_c) * nrm > GUARD:
+            n_c *= 2
+        return n_c
+
+    def rk4(self, beta: np.ndarray, t0: float, dT_total: float, n_c: int) -> np.ndarray:
+        """n_c classical RK4 steps over [t0, t0 + dT_total]."""
+        if not self.forced:
+            return reduced_rk4(self.Lr, self.Mr, beta, dT_total, n_c)
+        if beta.size == 0:
+            return beta
+        dT = dT_total / n_c
+        b = beta.copy()
+        for i in range(n_c):
+            t = t0 + i * dT
+            K1, g1 = self.at(t)
+            K2, g2 = self.at(t + 0.5 * dT)
+            k1 = K1 @ b + g1
+            k2 = K2 @ (b + 0.5 * dT * k1) + g2
+            k3 = K2 @ (b + 0.5 * dT * k2) + g2
+            K4, g4 = self.at(t + dT)
+            k4 = K4 @ (b + dT * k3) + g4
+            b = b + (dT / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+        return b
+
+    def project(self, U: np.ndarray) -> np.ndarray:
+        return project(self.Psi, self.Mr, U, self.h3)
+
+    def lift(self, beta: np.ndarray) -> np.ndarray:
+        return self.Psi @ beta if self.q else np.zeros(self.Psi.shape[0])
+
+
+def coarse_propagate(op, Psi: np.ndarray, states, dT_total: float, n_c: int, h3: float,
+                     t0: float = 0.0):
     """G(P U) for each U in ``states``: project onto span Psi, integrate the
-    reduced system over dT_total, lift. Returns (lifted list, beta list, n_c
-    after the guard)."""
-    Lr, Mr = reduced_matrices(op, Psi, h3)
-    n_c = guarded_steps(Lr, Mr, dT_total, n_c)
+    reduced system over [t0, t0 + dT_total], lift. Returns (lifted list, beta
+    list, n_c after the guard)."""
+    sysr = ReducedSystem(op, Psi, h3)
+    n_c = sysr.guarded_steps(dT_total, n_c)
     lifted, betas = [], []
     for U in states:
-        b = reduced_rk4(Lr, Mr, project(Psi, Mr, U, h3), dT_total, n_c)
+        b = sysr.rk4(sysr.project(U), t0, dT_total, n_c)
         betas.append(b)
         lifted.append(Psi @ b if Psi.shape[1] else np.zeros(Psi.shape[0]))
     return lifted, betas, n_c

@@ -77,9 +77,10 @@ def grid_steps(prob_c, dT: float, n_f: int, coarse_ratio: int) -> int:
     return n_g
 
 
-def coarse_grid_propagate(op_c, u: np.ndarray, dT: float, n_g: int) -> np.ndarray:
-    """G(u) = P(F_c(R u)) for a fine field u (any shape with n^3 values)."""
+def coarse_grid_propagate(op_c, u: np.ndarray, dT: float, n_g: int, t0: float = 0.0) -> np.ndarray:
+    """G(u) = P(F_c(R u)) for a fine field u (any shape with n^3 values), the
+    coarse solve running over [t0, t0 + dT] (forced flows: with the forcing)."""
     m = op_c.n
     uc = restrict(np.asarray(u, dtype=np.float64).reshape(2 * m, 2 * m, 2 * m))
-    vc, _ = fd.fine_propagate(op_c, uc, dT / n_g, n_g)
+    vc, _ = fd.fine_propagate(op_c, uc, dT / n_g, n_g, t0=t0)
     return prolong(vc).reshape(-1)

@@ -33,6 +33,11 @@ mode = 2 is "Parareal-II" of Sec. 4: plain parareal whose coarse propagator
 solves the same equation on the coarse n/2 grid (gridcoarse.py); no POD at
 all. The warm-up subinterval and the numbering are kept, so all three modes
 share U^0_0 = F(u0).
+
+Time: subinterval i of [0, T] starts at i DeltaT, so the warm-up solve starts
+at t = 0 and the fine and coarse solves from U_n (n = 0..N'-1) start at
+t_hat_n = (n + 1) DeltaT; fine step j of a solve from t starts at t + j dt.
+Only the forced time-dependent flows read the time.
 """
 from __future__ import annotations
 
@@ -91,6 +96,9 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     t_phase = {"F": 0.0, "C": 0.0, "U": 0.0, "A": 0.0, "G": 0.0}
     u0v = np.asarray(u0, dtype=np.float64).reshape(-1)
 
+    def t_hat(j):
+        return (j + 1) * dT_sub
+
     def err_of(states):
         if U_ref is None:
             return None
@@ -102,7 +110,7 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
 
     # ---- k = 0: Case I ----------------------------------------------------
     t0 = time.perf_counter()
-    F0, W = fd.fine_propagate(op, u0v.reshape(n, n, n), dt, n_f, dM)
+    F0, W = fd.fine_propagate(op, u0v.reshape(n, n, n), dt, n_f, dM, t0=0.0)
     t_phase["F"] += time.perf_counter() - t0
     U0hat = F0.reshape(-1)
     mode = getattr(opts, "mode", 0)
@@ -114,14 +122,13 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     t_phase["C"] += time.perf_counter() - t0
     del W
     t0 = time.perf_counter()
-    Lr0, Mr0 = C.reduced_matrices(op, R0, h3)
-    n_c = C.guarded_steps(Lr0, Mr0, dT_sub, n_c0)
+    sys0 = C.ReducedSystem(op, R0, h3)
+    n_c = sys0.guarded_steps(dT_sub, n_c0)
     t_phase["U"] += time.perf_counter() - t0
     U_prev = [U0hat]
     t0 = time.perf_counter()
-    for _ in range(Np):
-        beta = C.project(R0, Mr0, U_prev[-1], h3)
-        beta = C.reduced_rk4(Lr0, Mr0, beta, dT_sub, n_c)
+    for j in range(Np):
+        beta = sys0.rk4(sys0.project(U_prev[-1]), t_hat(j), dT_sub, n_c)
         U_prev.append(R0 @ beta if m0 > 0 else np.zeros_like(U0hat))
     t_phase["G"] += time.perf_counter() - t0
 
@@ -147,9 +154,11 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
         for nn in range(k - 1, Np):
             t0 = time.perf_counter()
             if fixed:
-                Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f)
+                Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f,
+                                          t0=t_hat(nn))
             else:
-                Fn, Wn = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f, dM)
+                Fn, Wn = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f, dM,
+                                           t0=t_hat(nn))
             t_phase["F"] += time.perf_counter() - t0
             Fk[nn] = Fn.reshape(-1)
             if fixed:
@@ -172,8 +181,8 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
             if fixed:
                 # U^k_{n+1} = G_0(P U^k_n) + F(U^{k-1}_n) - G_0(P U^{k-1}_n)
                 t0 = time.perf_counter()
-                b_new = C.reduced_rk4(Lr0, Mr0, C.project(R0, Mr0, U_cur[nn], h3), dT_sub, n_c)
-                b_old = C.reduced_rk4(Lr0, Mr0, C.project(R0, Mr0, U_prev[nn], h3), dT_sub, n_c)
+                b_new = sys0.rk4(sys0.project(U_cur[nn]), t_hat(nn), dT_sub, n_c)
+                b_old = sys0.rk4(sys0.project(U_prev[nn]), t_hat(nn), dT_sub, n_c)
                 g_new = R0 @ b_new if m0 > 0 else 0.0
                 g_old = R0 @ b_old if m0 > 0 else 0.0
                 U_cur.append(g_new + Fk[nn] - g_old)
@@ -190,12 +199,12 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
             Psi, _ = C.augment(Rkn, U_cur[nn], h3)
             t_phase["A"] += time.perf_counter() - t0
             t0 = time.perf_counter()
-            Lr, Mr = C.reduced_matrices(op, Psi, h3)
-            nc = C.guarded_steps(Lr, Mr, dT_sub, n_c0)
+            sysr = C.ReducedSystem(op, Psi, h3)
+            nc = sysr.guarded_steps(dT_sub, n_c0)
             t_phase["U"] += time.perf_counter() - t0
             t0 = time.perf_counter()
-            b_new = C.reduced_rk4(Lr, Mr, C.project(Psi, Mr, U_cur[nn], h3), dT_sub, nc)
-            b_old = C.reduced_rk4(Lr, Mr, C.project(Psi, Mr, U_prev[nn], h3), dT_sub, nc)
+            b_new = sysr.rk4(sysr.project(U_cur[nn]), t_hat(nn), dT_sub, nc)
+            b_old = sysr.rk4(sysr.project(U_prev[nn]), t_hat(nn), dT_sub, nc)
             g_new = Psi @ b_new if Psi.shape[1] else 0.0
             g_old = Psi @ b_old if Psi.shape[1] else 0.0
             U_cur.append(g_new + Fk[nn] - g_old)
@@ -240,15 +249,15 @@ def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, 
     op_c = fd.Operator.of(prob_c)
     n_g = GC.grid_steps(prob_c, dT_sub, n_f, opts.coarse_ratio)
 
-    def G(u):
+    def G(u, j):
         t0 = time.perf_counter()
-        v = GC.coarse_grid_propagate(op_c, u, dT_sub, n_g)
+        v = GC.coarse_grid_propagate(op_c, u, dT_sub, n_g, t0=(j + 1) * dT_sub)
         t_phase["G"] += time.perf_counter() - t0
         return v
 
     U_prev = [U0hat]
-    for _ in range(Np):
-        U_prev.append(G(U_prev[-1]))
+    for j in range(Np):
+        U_prev.append(G(U_prev[-1], j))
     errors = []
     e0 = err_of(U_prev)
     if e0 is not None:
@@ -262,13 +271,14 @@ def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, 
         Fk = {}
         for nn in range(k - 1, Np):
             t0 = time.perf_counter()
-            Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f)
+            Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f,
+                                      t0=(nn + 1) * dT_sub)
             t_phase["F"] += time.perf_counter() - t0
             Fk[nn] = Fn.reshape(-1)
         U_cur = [U_prev[j] for j in range(k)]
         U_cur.append(Fk[k - 1])
         for nn in range(k, Np):
-            U_cur.append(G(U_cur[nn]) + Fk[nn] - G(U_prev[nn]))
+            U_cur.append(G(U_cur[nn], nn) + Fk[nn] - G(U_prev[nn], nn))
         e = 0.0
         for j in range(1, Np + 1):
             nrm = _norm_m(U_cur[j], h3)

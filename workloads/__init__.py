@@ -26,6 +26,8 @@ TWO_PI = 2.0 * math.pi
 FLOW_UNIFORM = 0
 FLOW_ABC = 1
 FLOW_KOLMOGOROV = 2
+FLOW_KOLMOGOROV_T = 3   # the Kolmogorov flow of Sec. 4: B(t) and forcing f(t)
+FLOW_ABC_T = 4          # the ABC flow of Sec. 4 with phase sin(w t), forced
 
 PREC_F64 = 0
 PREC_MIXED = 1
@@ -43,6 +45,8 @@ class Problem:
       ABC:        (A, B, C)
       KOLMOGOROV: (amplitude, k_f, unused)
       UNIFORM:    (c_x, c_y, c_z)
+      KOLMOGOROV_T, ABC_T: (a_v, a_f, w) -- velocity and forcing scales and
+                  the frequency of the time dependence (Sec. 4: 1, 1, 1)
     """
     n: int
     kappa: float
