@@ -3,8 +3,9 @@
  *
  * Method: arXiv 2601.10981, "A model order reduction based adaptive parareal
  * method for time-dependent PDEs". The library implements, for the periodic
- * 3-D advection-diffusion equation u_t = kappa Lap u - v . grad u (eq1 of
- * Sec. 4 with c = 0, f = 0 and a steady velocity v), the fine propagator F,
+ * 3-D advection-diffusion equation u_t = kappa Lap u - v . grad u + f (eq1 of
+ * Sec. 4 with c = 0; a steady velocity with f = 0, or the time-dependent
+ * velocity and forcing of the two flows of Sec. 4), the fine propagator F,
  * POD_Mode (Algorithm 1), the POD-Galerkin coarse propagator G with
  * augmentation by the interface state (eqaug, eq12, eq13) and the whole
  * adaptive parareal iteration (formula4, Algorithm 2).
@@ -15,7 +16,9 @@
  *             (x_i, y_j, z_k): z fastest
  *   operator  (L u)_p = kappa sum_d (u_{p+e_d} - 2 u_p + u_{p-e_d}) / h^2
  *                       - sum_d v_d(p) (u_{p+e_d} - u_{p-e_d}) / (2 h)
- *   fine step classical RK4 (one step = P4(dt L) for this linear operator)
+ *   fine step classical RK4 (one step = P4(dt L) for a steady flow; for the
+ *             forced flows stages at t, t + dt/2, t + dt/2, t + dt of
+ *             du/dt = L(t) u + f(t), L(t) the same stencil with v(., t))
  *   mass      M = h^3 I (discrete L2 inner product)
  *
  * Conventions for every entry point:
@@ -54,7 +57,13 @@ typedef enum {
   PR_EBUSY = -7       /* context in use                                      */
 } pr_status;
 
-enum { PR_FLOW_UNIFORM = 0, PR_FLOW_ABC = 1, PR_FLOW_KOLMOGOROV = 2 };
+enum {
+  PR_FLOW_UNIFORM = 0,
+  PR_FLOW_ABC = 1,
+  PR_FLOW_KOLMOGOROV = 2,
+  PR_FLOW_KOLMOGOROV_T = 3, /* the Kolmogorov flow of Sec. 4 (eq. koleq), forced */
+  PR_FLOW_ABC_T = 4         /* the ABC flow of Sec. 4 with phase sin(w t), forced */
+};
 enum { PR_F64 = 0, PR_MIXED = 1 };
 enum { PR_MODE_ADAPTIVE = 0, PR_MODE_FIXED_POD = 1, PR_MODE_COARSE_GRID = 2 };
 
@@ -63,6 +72,16 @@ enum { PR_MODE_ADAPTIVE = 0, PR_MODE_FIXED_POD = 1, PR_MODE_COARSE_GRID = 2 };
  *                                 C sin y + B cos x),  fp = {A, B, C}
  *   flow PR_FLOW_KOLMOGOROV: v = (a sin(k_f y), 0, 0),  fp = {a, k_f, -}
  *   flow PR_FLOW_UNIFORM:    v = (c_x, c_y, c_z),        fp = {c_x, c_y, c_z}
+ *   flow PR_FLOW_KOLMOGOROV_T, fp = {a_v, a_f, w} (the paper: {1, 1, 1}):
+ *     v(t) = a_v [(cos y, cos z, cos x) + (sin z, sin x, sin y) cos(w t)],
+ *     f(t) = a_f [-cos y - sin z cos(w t)]
+ *   flow PR_FLOW_ABC_T, fp = {a_v, a_f, w}, s = sin(w t):
+ *     v(t) = a_v (sin(z+s) + cos(y+s), sin(x+s) + cos(z+s), sin(y+s) + cos(x+s)),
+ *     f(t) = a_f [-sin(z+s) - cos(y+s)]
+ *   For these two, sum_d max|v_d| = 6 |a_v| at every t in the stability
+ *   bound below, and the reduced systems use the flows' separation
+ *   v = sum_j theta_j(t) v_j, f = sum_j theta_j(t) f_j (Sec. 4: B and f are
+ *   separable in time and space).
  * n >= 4; L > 0; kappa >= 0. */
 typedef struct {
   int n;
@@ -109,20 +128,23 @@ typedef struct {
   double* u_out;
   int snap_every;
   void* snaps;
+  double t0;      /* start time (read by the forced flows only)             */
 } pr_fine_item;
 pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, void* stream);
 /* Tiling of the fused RK4 stencil. Every tiling gives bitwise the same
  * values; the context picks one per (precision, largest n of the batch,
- * floor(log2(batch))) by timing one step of the first such batch in each
- * candidate tiling and x-chunk length (that first call synchronises
- * `stream`). The environment
- * variables PR_FUSED_CFG=<index> and PR_FUSED_CHUNK=<policy> force one.
- * pr_fine_tuned reports, for a key, the workgroup's output tile (tile_y x
- * tile_z points of the (y, z) plane), its thread count and the x planes it
- * marches through (for `batch` fields of n^3); every output pointer may be
- * NULL. PR_EINVAL if no batch of that key ran yet. */
-pr_status pr_fine_tuned(const pr_ctx* ctx, int precision, int n, int batch, int* tile_y,
-                        int* tile_z, int* threads, int* planes);
+ * floor(log2(batch)), steady or forced flows -- a batch mixing the two runs
+ * as two launches per step) by timing one step of the first such batch in
+ * each candidate tiling and x-chunk length (that first call synchronises
+ * `stream`). The environment variables PR_FUSED_CFG=<index> (steady flows),
+ * PR_FORCED_CFG=<index> (forced flows) and PR_FUSED_CHUNK=<policy> force one.
+ * pr_fine_tuned reports, for a key (forced = 1: the forced-flow stencil), the
+ * workgroup's output tile (tile_y x tile_z points of the (y, z) plane), its
+ * thread count and the x planes it marches through (for `batch` fields of
+ * n^3); every output pointer may be NULL. PR_EINVAL if no batch of that key
+ * ran yet. */
+pr_status pr_fine_tuned(const pr_ctx* ctx, int precision, int forced, int n, int batch,
+                        int* tile_y, int* tile_z, int* threads, int* planes);
 
 /* ---------------------------------------------------------------------------
  * POD_Mode (Algorithm 1; Sec. 3.2 Case I and Case II, eq. W^k_n): modes of
@@ -175,7 +197,12 @@ pr_status pr_gram(pr_ctx* ctx, const pr_grid_problem* prob, const void* W, int n
 /* ---------------------------------------------------------------------------
  * Coarse propagator G_{k,n} (eq. 8 / eq00; with augmentation eqaug, eq12,
  * eq13; formula4): Galerkin projection of each input state onto span(Psi),
- * n_c RK4 steps of M_r beta' = L_r beta over dT_total, optional lift.
+ * n_c RK4 steps of M_r beta' = L_r beta over dT_total, optional lift. For the
+ * forced flows the system is M_r beta' = sum_j theta_j(t) (L_r,j beta +
+ * f_r,j) over [t0, t0 + dT_total] (L_r,j = Psi^T M L_j Psi and f_r,j =
+ * Psi^T M f_j of the flow's time-space pieces, theta_0 = 1), with stages at
+ * t, t + h/2, t + h/2, t + h, and the guard below uses
+ * sum_j ||M_r^{-1} L_r,j||_F in place of ||M_r^{-1} L_r||_F.
  *   R            device, N_g x cap, field precision, M-orthonormal columns
  *   m            device int: valid columns of R (<= cap <= 32)
  *   u_aug        NULL, or device N_g doubles: Psi = [R, d] with
@@ -204,6 +231,7 @@ typedef struct {
   double* u_out[2];
   double* beta_out;
   int* n_c_out;
+  double t0;      /* start time (read by the forced flows only)             */
 } pr_coarse_item;
 pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* items, void* stream);
 
@@ -211,7 +239,8 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  * The adaptive parareal solve (formula4, Algorithm 2).
  * [0, T] is split into N subintervals of DeltaT = T / N; subinterval 0 is the
  * warm-up window [0, T_0] (T_0 = DeltaT) whose fine solve gives G_0 (Case I);
- * the parareal partition of [T_0, T] has N - 1 subintervals.
+ * the parareal partition of [T_0, T] has N - 1 subintervals. Subinterval i
+ * of [0, T] starts at t = i DeltaT (the time the forced flows read).
  *   fine steps    n_f = ceil(DeltaT / dt - 1e-9), delta_t = DeltaT / n_f;
  *                 dt <= 0 requests min(2e-3, 1.3 / rho) with the bound
  *                 rho = 12 kappa / h^2 + sum_d max|v_d| / h (max|v_d| from

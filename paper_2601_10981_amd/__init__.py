@@ -16,6 +16,7 @@ from typing import List, Optional, Sequence
 
 from . import _lib as L
 from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNIFORM  # noqa: F401
+from ._lib import PR_FLOW_ABC_T, PR_FLOW_KOLMOGOROV_T  # noqa: F401
 from ._lib import PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD, PR_MODE_COARSE_GRID  # noqa: F401
 
 __all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
@@ -124,7 +125,7 @@ def _fdtype(prob: L.pr_grid_problem):
 
 def pr_fine_propagate(ctx: Context, items: Sequence[dict], stream=None):
     """items: dicts with prob, dt, n_steps, u_in, u_out and optional
-    snap_every, snaps (see pr.h)."""
+    snap_every, snaps, t0 (see pr.h)."""
     torch = _torch()
     arr = (L.pr_fine_item * len(items))()
     keep = []
@@ -145,15 +146,18 @@ def pr_fine_propagate(ctx: Context, items: Sequence[dict], stream=None):
         if snaps is not None:
             _check_dev(snaps, _fdtype(prob), ng * (int(it["n_steps"]) // se + 1), "snaps")
         arr[i].snaps = _ptr(snaps)
+        arr[i].t0 = float(it.get("t0", 0.0))
     ctx.check(ctx.lib.pr_fine_propagate(ctx.h, len(items), arr, _stream(stream)))
 
 
-def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int, planes: bool = False):
+def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int, planes: bool = False,
+                  forced: bool = False):
     """(tile_y, tile_z, threads[, x planes per workgroup]) of the fused
-    stencil launch shape chosen for a batch key, or None if no such batch
-    ran yet."""
+    stencil launch shape chosen for a batch key (forced: the forced-flow
+    stencil), or None if no such batch ran yet."""
     ty, tz, nt, xp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-    st = ctx.lib.pr_fine_tuned(ctx.h, int(precision), int(n), int(batch), ctypes.byref(ty),
+    st = ctx.lib.pr_fine_tuned(ctx.h, int(precision), 1 if forced else 0, int(n), int(batch),
+                               ctypes.byref(ty),
                                ctypes.byref(tz), ctypes.byref(nt), ctypes.byref(xp))
     if st != L.PR_OK:
         return None
@@ -219,7 +223,7 @@ def pr_pod_build(ctx: Context, items: Sequence[dict], stream=None):
 def pr_coarse_propagate(ctx: Context, items: Sequence[dict], stream=None):
     """items: dicts with prob, R ((cap, N_g) tensor), cap, m (int32 device
     scalar), u_in (list of 1 or 2 float64 fields), dT_total, and optional
-    u_aug, n_c, dt_hint, u_out (list), beta_out, n_c_out."""
+    u_aug, n_c, dt_hint, u_out (list), beta_out, n_c_out, t0."""
     torch = _torch()
     arr = (L.pr_coarse_item * len(items))()
     keep = []
@@ -246,6 +250,7 @@ def pr_coarse_propagate(ctx: Context, items: Sequence[dict], stream=None):
         arr[i].dT_total = float(it["dT_total"])
         arr[i].n_c = int(it.get("n_c", 0))
         arr[i].dt_hint = float(it.get("dt_hint", 0.0))
+        arr[i].t0 = float(it.get("t0", 0.0))
         outs = list(it.get("u_out") or [])
         for j, u in enumerate(outs):
             if u is not None:

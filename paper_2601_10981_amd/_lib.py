@@ -12,6 +12,7 @@ STATUS = {0: "PR_OK", -1: "PR_EINVAL", -2: "PR_ENOMEM", -3: "PR_EDEVICE", -4: "P
           -5: "PR_ENOTCONV", -6: "PR_ENUMERIC", -7: "PR_EBUSY"}
 
 PR_FLOW_UNIFORM, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV = 0, 1, 2
+PR_FLOW_KOLMOGOROV_T, PR_FLOW_ABC_T = 3, 4
 PR_F64, PR_MIXED = 0, 1
 PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD, PR_MODE_COARSE_GRID = 0, 1, 2
 
@@ -24,7 +25,7 @@ class pr_grid_problem(Structure):
 class pr_fine_item(Structure):
     _fields_ = [("prob", POINTER(pr_grid_problem)), ("dt", c_double), ("n_steps", c_int),
                 ("u_in", c_void_p), ("u_out", c_void_p), ("snap_every", c_int),
-                ("snaps", c_void_p)]
+                ("snaps", c_void_p), ("t0", c_double)]
 
 
 class pr_pod_item(Structure):
@@ -39,7 +40,8 @@ class pr_coarse_item(Structure):
     _fields_ = [("prob", POINTER(pr_grid_problem)), ("R", c_void_p), ("cap", c_int),
                 ("m", c_void_p), ("u_aug", c_void_p), ("n_in", c_int), ("u_in", c_void_p * 2),
                 ("dT_total", c_double), ("n_c", c_int), ("dt_hint", c_double),
-                ("u_out", c_void_p * 2), ("beta_out", c_void_p), ("n_c_out", c_void_p)]
+                ("u_out", c_void_p * 2), ("beta_out", c_void_p), ("n_c_out", c_void_p),
+                ("t0", c_double)]
 
 
 class pr_parareal_opts(Structure):
@@ -98,7 +100,7 @@ def load(path: str = LIB_PATH):
     lib.pr_ctx_scratch_bytes.restype = c_size_t
     lib.pr_fine_propagate.argtypes = [c_void_p, c_int, POINTER(pr_fine_item), c_void_p]
     lib.pr_fine_propagate.restype = c_int
-    lib.pr_fine_tuned.argtypes = [c_void_p, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int),
+    lib.pr_fine_tuned.argtypes = [c_void_p, c_int, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int),
                                   POINTER(c_int), POINTER(c_int)]
     lib.pr_fine_tuned.restype = c_int
     lib.pr_gram.argtypes = [c_void_p, POINTER(pr_grid_problem), c_void_p, c_int, c_void_p,

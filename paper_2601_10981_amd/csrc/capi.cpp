@@ -173,7 +173,8 @@ void check_problem(const pr_grid_problem* p) {
   PR_CHECK(p->n >= 4 && p->n <= 2048, "grid size n must be in [4, 2048]");
   PR_CHECK(std::isfinite(p->L) && p->L > 0, "domain length L must be positive");
   PR_CHECK(std::isfinite(p->kappa) && p->kappa >= 0, "kappa must be >= 0");
-  PR_CHECK(p->flow == PR_FLOW_UNIFORM || p->flow == PR_FLOW_ABC || p->flow == PR_FLOW_KOLMOGOROV,
+  PR_CHECK(p->flow == PR_FLOW_UNIFORM || p->flow == PR_FLOW_ABC || p->flow == PR_FLOW_KOLMOGOROV ||
+               p->flow == PR_FLOW_KOLMOGOROV_T || p->flow == PR_FLOW_ABC_T,
            "unknown flow");
   PR_CHECK(p->precision == PR_F64 || p->precision == PR_MIXED, "unknown precision");
   for (int i = 0; i < 3; ++i) PR_CHECK(std::isfinite(p->fp[i]), "flow parameters must be finite");
@@ -188,10 +189,69 @@ double spectral_bound(const pr_grid_problem& p) {
     vs = (A + C) + (B + A) + (C + B);
   } else if (p.flow == PR_FLOW_KOLMOGOROV) {
     vs = fabs(p.fp[0]);
+  } else if (forced_flow(p)) {
+    vs = 6.0 * fabs(p.fp[0]);   // each component: two terms of magnitude <= |a_v|
   } else {
     vs = fabs(p.fp[0]) + fabs(p.fp[1]) + fabs(p.fp[2]);
   }
   return 12.0 * p.kappa / (h * h) + vs / h;
+}
+
+bool forced_flow(const pr_grid_problem& p) {
+  return p.flow == PR_FLOW_KOLMOGOROV_T || p.flow == PR_FLOW_ABC_T;
+}
+int flow_pieces(const pr_grid_problem& p) {
+  return p.flow == PR_FLOW_ABC_T ? 3 : (p.flow == PR_FLOW_KOLMOGOROV_T ? 2 : 1);
+}
+
+// Tables of the forced flows' pieces (layout in pr_internal.h), velocities
+// pre-multiplied by s = 1 / (2 h):
+//   Kolmogorov (a_v, a_f, w), theta = (1, cos(w t)):
+//     piece 0: v = a_v (cos y, cos z, cos x), f = -a_f cos y
+//     piece 1: v = a_v (sin z, sin x, sin y), f = -a_f sin z
+//   ABC with phase s(t) = sin(w t), theta = (1, cos s, sin s):
+//     piece 0: v = 0, f = 0
+//     piece 1: v = a_v (sin z + cos y, sin x + cos z, sin y + cos x),
+//              f = -a_f (sin z + cos y)
+//     piece 2: v = a_v (cos z - sin y, cos x - sin z, cos y - sin x),
+//              f = -a_f (cos z - sin y)
+static std::vector<double> forced_tables(const pr_grid_problem& p) {
+  const int n = p.n, np = flow_pieces(p);
+  const double h = spacing(p), s = 1.0 / (2.0 * h);
+  const double av = p.fp[0] * s, af = p.fp[1];
+  std::vector<double> t((size_t)np * 9 * n, 0.0);
+  auto T = [&](int j, int tab, int i) -> double& { return t[((size_t)j * 9 + tab) * n + i]; };
+  for (int i = 0; i < n; ++i) {
+    const double x = i * h, sx = sin(x), cx = cos(x);
+    if (p.flow == PR_FLOW_KOLMOGOROV_T) {
+      T(0, 0, i) = av * cx;    // v_x: cos y
+      T(0, 3, i) = av * cx;    // v_y: cos z
+      T(0, 4, i) = av * cx;    // v_z: cos x
+      T(0, 7, i) = -af * cx;   // f: -cos y
+      T(1, 1, i) = av * sx;    // v_x: sin z
+      T(1, 2, i) = av * sx;    // v_y: sin x
+      T(1, 5, i) = av * sx;    // v_z: sin y
+      T(1, 8, i) = -af * sx;   // f: -sin z
+    } else {
+      T(1, 0, i) = av * cx;    // v_x: cos y + sin z
+      T(1, 1, i) = av * sx;
+      T(1, 2, i) = av * sx;    // v_y: sin x + cos z
+      T(1, 3, i) = av * cx;
+      T(1, 4, i) = av * cx;    // v_z: cos x + sin y
+      T(1, 5, i) = av * sx;
+      T(1, 7, i) = -af * cx;   // f: -(cos y + sin z)
+      T(1, 8, i) = -af * sx;
+      T(2, 0, i) = -av * sx;   // v_x: -sin y + cos z
+      T(2, 1, i) = av * cx;
+      T(2, 2, i) = av * cx;    // v_y: cos x - sin z
+      T(2, 3, i) = -av * sx;
+      T(2, 4, i) = -av * sx;   // v_z: -sin x + cos y
+      T(2, 5, i) = av * cx;
+      T(2, 7, i) = af * sx;    // f: -(cos z - sin y)
+      T(2, 8, i) = -af * cx;
+    }
+  }
+  return t;
 }
 
 Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
@@ -203,7 +263,8 @@ Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
   if (it == c->tables.end()) {
     const double h = spacing(p), s = 1.0 / (2.0 * h);
     std::vector<double> t(6 * (size_t)n, 0.0);
-    for (int i = 0; i < n; ++i) {
+    if (forced_flow(p)) t = forced_tables(p);
+    for (int i = 0; i < n && !forced_flow(p); ++i) {
       const double x = i * h;
       if (p.flow == PR_FLOW_ABC) {
         const double A = p.fp[0], B = p.fp[1], C = p.fp[2];
@@ -237,9 +298,32 @@ Geom geom_of(pr_ctx* c, const pr_grid_problem& p) {
   g.xonly = (p.flow == PR_FLOW_KOLMOGOROV) ||
             (p.flow == PR_FLOW_UNIFORM && p.fp[1] == 0.0 && p.fp[2] == 0.0);
   g.c_lap = p.kappa / (h * h);
+  const size_t nt = forced_flow(p) ? (size_t)flow_pieces(p) * 9 * n : 6 * (size_t)n;
   g.tab64 = (const double*)dev;
-  g.tab32 = (const float*)((char*)dev + 6 * (size_t)n * 8);
+  g.tab32 = (const float*)((char*)dev + nt * 8);
+  g.forced = p.flow == PR_FLOW_KOLMOGOROV_T ? kForcedKolmogorov
+                                            : (p.flow == PR_FLOW_ABC_T ? kForcedABC : kForcedNone);
+  g.npieces = flow_pieces(p);
+  g.w = forced_flow(p) ? p.fp[2] : 0.0;
+  g.ptab64 = g.forced ? g.tab64 : nullptr;
+  g.ptab32 = g.forced ? g.tab32 : nullptr;
+  if (g.forced) g.xonly = 0;
   return g;
+}
+
+// Piece j of a forced flow's operator as a steady operator: kappa Lap -
+// v_0 . grad for j = 0, -v_j . grad for j > 0 (tables of piece j).
+Geom geom_piece(const Geom& g, int j) {
+  Geom q = g;
+  if (!g.forced) return q;
+  q.tab64 = g.ptab64 + (size_t)9 * g.n * j;
+  q.tab32 = g.ptab32 + (size_t)9 * g.n * j;
+  if (j > 0) q.c_lap = 0.0;
+  q.forced = kForcedNone;
+  q.npieces = 1;
+  q.ptab64 = nullptr;
+  q.ptab32 = nullptr;
+  return q;
 }
 
 // Rows per Gram chunk: a function of the row count only (about 512 chunks,
@@ -272,14 +356,26 @@ static int forced_cfg() {
   const int pol = (p && *p) ? atoi(p) : 0;
   return v + kNumFusedCfgs * ((pol >= 0 && pol < kChunkPolicies) ? pol : 0);
 }
+// The same for the forced-flow stencil: PR_FORCED_CFG=<index into
+// kForcedCfgs> (with PR_FUSED_CHUNK).
+static int forced_cfg_forced() {
+  const char* e = getenv("PR_FORCED_CFG");
+  if (!e || !*e) return -1;
+  const int v = atoi(e);
+  if (v < 0 || v >= kNumForcedCfgs) return -1;
+  const char* p = getenv("PR_FUSED_CHUNK");
+  const int pol = (p && *p) ? atoi(p) : 0;
+  return kForcedCfgs[v] + kNumFusedCfgs * ((pol >= 0 && pol < kChunkPolicies) ? pol : 0);
+}
 
 // x-chunk length of the fused stencil: chunks of up to kMaxChunk planes,
 // halved while the batch would give fewer than min_wgs workgroups (small
 // batches, e.g. the serial fine solve of one field, still fill the chip).
 // Longer chunks re-read fewer warm-up planes (6 per chunk); shorter ones give
 // more workgroups. The tuner tries both policies.
-static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min_wgs) {
-  int xc = kMaxChunk;
+static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min_wgs,
+                      bool forced) {
+  int xc = forced ? kForcedChunk : kMaxChunk;
   auto total = [&](int x) {
     long long t = 0;
     for (auto& w : items) {
@@ -299,9 +395,9 @@ static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min
 // code / kNumFusedCfgs.
 template <typename T>
 static long long shape_descs(const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
-                             int code) {
+                             int code, bool forced) {
   const int cfg = code % kNumFusedCfgs;
-  const int xc = fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs]);
+  const int xc = fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs], forced);
   long long tiles = 0;
   for (size_t i = 0; i < items.size(); ++i) {
     const int n = items[i].prob->n;
@@ -317,7 +413,14 @@ static long long shape_descs(const std::vector<FineWork>& items, std::vector<Fin
 
 template <typename T>
 static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step, int cfg,
-                        hipStream_t s) {
+                        bool forced, hipStream_t s) {
+  if (forced) {
+    if (std::is_same<T, float>::value)
+      launch_forced_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, s);
+    else
+      launch_forced_step_f64((const FineDesc<double>*)d, nd, tiles, step, cfg, s);
+    return;
+  }
   if (std::is_same<T, float>::value)
     launch_fine_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, s);
   else
@@ -326,13 +429,31 @@ static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step,
 
 constexpr int kTuneReps = 3;
 
-// Tuning key: value size, largest grid, batch size class floor(log2(batch)).
-static std::string tune_key(int value_bytes, int nmax, int batch) {
+// Tuning key: value size, largest grid, batch size class floor(log2(batch)),
+// and F for the forced-flow stencil.
+static std::string tune_key(int value_bytes, int nmax, int batch, bool forced) {
   int cls = 0;
   while ((1LL << (cls + 1)) <= batch) ++cls;
   char key[64];
-  snprintf(key, sizeof key, "%d|%d|%d", value_bytes, nmax, cls);
+  snprintf(key, sizeof key, "%d|%d|%d%s", value_bytes, nmax, cls, forced ? "|F" : "");
   return key;
+}
+
+// Launch shapes the tuner tries: every tiling (the forced stencil: those of
+// kForcedCfgs; in FP64 not the 1024-thread one, whose four waves per SIMD
+// leave too few registers) under every chunk policy.
+static std::vector<int> shape_codes(bool forced, int value_bytes) {
+  std::vector<int> v;
+  for (int pol = 0; pol < kChunkPolicies; ++pol) {
+    if (forced) {
+      for (int i = 0; i < kNumForcedCfgs; ++i)
+        if (!(value_bytes == 8 && kFusedCfgs[kForcedCfgs[i]].nt > 512))
+          v.push_back(kForcedCfgs[i] + kNumFusedCfgs * pol);
+    } else {
+      for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg) v.push_back(cfg + kNumFusedCfgs * pol);
+    }
+  }
+  return v;
 }
 
 // Autotuner: time step 0 of the actual batch in every configuration (one
@@ -343,28 +464,31 @@ static std::string tune_key(int value_bytes, int nmax, int batch) {
 // values. Synchronises `s` once, at the first batch of a key.
 template <typename T>
 static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
-                     hipStream_t s) {
+                     bool forced, hipStream_t s) {
   int nmax = 0;
   for (auto& w : items) nmax = std::max(nmax, w.prob->n);
-  const std::string key = tune_key((int)sizeof(T), nmax, (int)items.size());
+  const std::string key = tune_key((int)sizeof(T), nmax, (int)items.size(), forced);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
   hipEvent_t e0 = event_get(c), e1 = event_get(c);
   float best_ms = 0;
-  int best = 1;
-  for (int code = 0; code < kNumFusedCfgs * kChunkPolicies; ++code) {
+  const std::vector<int> codes = shape_codes(forced, (int)sizeof(T));
+  int best = codes[0];
+  for (size_t ic = 0; ic < codes.size(); ++ic) {
+    const int code = codes[ic];
     const int cfg = code % kNumFusedCfgs;
-    const long long tiles = shape_descs<T>(items, d, code);
+    const long long tiles = shape_descs<T>(items, d, code, forced);
     FineDesc<T>* dd = stage_push(c, d);
     stage_flush(c, s);
-    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
+    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
     PR_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < kTuneReps; ++r) launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, s);
+    for (int r = 0; r < kTuneReps; ++r)
+      launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
     PR_HIP(hipEventRecord(e1, s));
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0;
     PR_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (code == 0 || ms < best_ms) {
+    if (ic == 0 || ms < best_ms) {
       best_ms = ms;
       best = code;
     }
@@ -376,13 +500,13 @@ static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<
 }
 
 template <typename T>
-static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
+static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, bool forced, hipStream_t s,
                        const std::string& tag) {
   const bool f32 = std::is_same<T, float>::value;
   const int nwork = f32 ? 3 : 1;
   size_t total = 0;
   for (auto& w : items) total += (size_t)ngrid(*w.prob) * nwork * sizeof(T);
-  char* base = (char*)scratch(c, tag + "_w", total);
+  char* base = (char*)scratch(c, tag + (forced ? "_fw" : "_w"), total);
   std::vector<FineDesc<T>> descs;
   int max_steps = 0;
   size_t off = 0;
@@ -417,20 +541,26 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, hipStream_
       PR_HIP(hipMemcpyAsync(w.snaps, d.first_src, ng * sizeof(T), hipMemcpyDeviceToDevice, s));
     d.n_steps = w.n_steps;
     d.dt = w.dt;
+    d.t0 = w.t0;
+    d.with_forcing = w.unforced ? 0 : 1;
     max_steps = std::max(max_steps, w.n_steps);
     descs.push_back(d);
   }
   if (max_steps > 0) {
-    int code = forced_cfg();
-    if (code < 0) code = tune_fine<T>(c, items, descs, s);
+    int code = forced ? forced_cfg_forced() : forced_cfg();
+    if (code < 0) code = tune_fine<T>(c, items, descs, forced, s);
     const int cfg = code % kNumFusedCfgs;
-    const long long tiles = shape_descs<T>(items, descs, code);
+    const long long tiles = shape_descs<T>(items, descs, code, forced);
     FineDesc<T>* dd = stage_push(c, descs);
     stage_flush(c, s);
-    if (f32)
+    if (forced) {
+      for (int step = 0; step < max_steps; ++step)
+        launch_step<T>(dd, (int)descs.size(), tiles, step, cfg, true, s);
+    } else if (f32) {
       launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
-    else
+    } else {
       launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+    }
   }
   if (f32)
     for (size_t i = 0; i < items.size(); ++i)
@@ -454,8 +584,14 @@ void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
     if (w.dt * spectral_bound(*w.prob) > kStabRK4)
       fail(PR_EUNSTABLE, "dt exceeds the RK4 stability bound 2.6 / rho(L)");
   }
-  if (prec == PR_MIXED) fine_typed<float>(c, items, s, tag);
-  else fine_typed<double>(c, items, s, tag);
+  std::vector<FineWork> steady, forced;
+  for (auto& w : items) (forced_flow(*w.prob) ? forced : steady).push_back(w);
+  for (int g = 0; g < 2; ++g) {
+    const std::vector<FineWork>& v = g ? forced : steady;
+    if (v.empty()) continue;
+    if (prec == PR_MIXED) fine_typed<float>(c, v, g == 1, s, tag);
+    else fine_typed<double>(c, v, g == 1, s, tag);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -505,7 +641,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
     std::vector<ApplyLDesc<float>> d;
     for (auto& w : items) {
       ApplyLDesc<float> a{};
-      a.g = geom_of(c, *w.prob);
+      a.g = geom_piece(geom_of(c, *w.prob), w.piece);
       a.in = (const float*)w.in;
       a.out = (float*)w.out;
       a.ncols = w.ncols;
@@ -523,7 +659,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
     std::vector<ApplyLDesc<double>> d;
     for (auto& w : items) {
       ApplyLDesc<double> a{};
-      a.g = geom_of(c, *w.prob);
+      a.g = geom_piece(geom_of(c, *w.prob), w.piece);
       a.in = (const double*)w.in;
       a.out = (double*)w.out;
       a.ncols = w.ncols;
@@ -543,6 +679,28 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
 void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out, int ncols,
                     const int* mptr, hipStream_t s) {
   enqueue_applyL_batch(c, {ApplyLWork{&p, in, out, ncols, mptr}}, s);
+}
+
+// L_j applied to ncols columns for every piece j of the problem's flow: piece
+// j's columns at out + j * ncols * N_g (one piece, L itself, for a steady
+// flow).
+void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
+                           int ncols, const int* mptr, hipStream_t s) {
+  const size_t col = (size_t)ngrid(p) * (p.precision == PR_MIXED ? 4 : 8);
+  std::vector<ApplyLWork> v;
+  for (int j = 0; j < flow_pieces(p); ++j)
+    v.push_back(ApplyLWork{&p, in, (char*)out + (size_t)j * ncols * col, ncols, mptr, j});
+  enqueue_applyL_batch(c, v, s);
+}
+
+// The forcing fields f_j of a forced flow's pieces (field precision), one
+// after another in out.
+void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s) {
+  const Geom g = geom_of(c, p);
+  const bool f32 = p.precision == PR_MIXED;
+  const size_t col = (size_t)ngrid(p) * (f32 ? 4 : 8);
+  for (int j = 0; j < g.npieces; ++j)
+    launch_forcing_field(g, j, (char*)out + (size_t)j * col, f32 ? 1 : 0, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,6 +895,8 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   PR_CHECK(cap >= 1 && cap <= kMaxCap, "cap must be in [1, 31]");
   PR_CHECK(w.n_in == 1 || w.n_in == 2, "n_in must be 1 or 2");
 
+  const int np = flow_pieces(p);
+  const bool forced = forced_flow(p);
   char* sm = (char*)scratch(c, "co_small", 64 * 1024);
   double* S1 = (double*)(sm);              // 32 x 16
   double* S2 = (double*)(sm + 4096);       // 32 x 16
@@ -747,25 +907,34 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   double* coef = (double*)(sm + 16384);    // cap + 1
   double* betas = (double*)(sm + 16384 + 512);  // 2 x (cap + 1)
   double* nrm = (double*)(sm + 16384 + 1024);   // scratch norms
-  double* Sbig = (double*)(sm + 20480);    // 32 x 80
+  double* Sbig = (double*)(sm + 20480);    // 32 x (16 (2 + 2 np + 1)), <= 32 x 144
 
   PhaseEvents dummy;
   PhaseEvents& P = ph ? *ph : dummy;
 
   const void* LR = w.LR;
-  char* ld = (char*)scratch(c, "co_fields", (size_t)ng * sf * 2 + (size_t)ng * 8);
+  char* ld = (char*)scratch(c, "co_fields", (size_t)ng * sf * (1 + np) + (size_t)ng * 8);
   void* dcol = ld;                          // augmented column d (field precision)
-  void* Ld = ld + (size_t)ng * sf;          // L d
-  double* dtil = (double*)(ld + (size_t)ng * sf * 2);
+  void* Ld = ld + (size_t)ng * sf;          // L_j d, j < np
+  double* dtil = (double*)(ld + (size_t)ng * sf * (1 + np));
   if (!LR) {
     P.begin(2);
-    void* lr = scratch(c, "co_LR", (size_t)ng * sf * cap);
-    enqueue_applyL(c, p, w.R, lr, cap, w.m, s);
+    void* lr = scratch(c, "co_LR", (size_t)ng * sf * cap * np);
+    enqueue_applyL_pieces(c, p, w.R, lr, cap, w.m, s);
     LR = lr;
+  }
+  const void* forcing = w.forcing;
+  if (forced && !forcing) {
+    void* fb = scratch(c, "co_force", (size_t)ng * sf * np);
+    enqueue_forcing_fields(c, p, fb, s);
+    forcing = fb;
   }
 
   auto Rcol = [&](int j) { return col_of(w.R, j, ng, f32, w.m); };
-  auto LRcol = [&](int j) { return col_of(LR, j, ng, f32, w.m); };
+  // piece jp of L applied to column j
+  auto LRcol = [&](int jp, int j) {
+    return col_of((const char*)LR + (size_t)jp * cap * ng * sf, j, ng, f32, w.m);
+  };
   auto f64col = [&](const double* x) { return ColDesc{x, nullptr, 0, 0}; };
   const int* aug = nullptr;
   if (w.u_aug) {
@@ -829,7 +998,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     launch_scale_into(dtil, dcol, f32, ng, dscale, s);
     aug = flag;
     P.begin(2);
-    enqueue_applyL(c, p, dcol, Ld, 1, flag, s);
+    enqueue_applyL_pieces(c, p, dcol, Ld, 1, flag, s);
   }
   P.begin(2);
   // Galerkin products of Psi against [Psi, L Psi, u_in]
@@ -844,33 +1013,45 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   }
   gb.cols = psi;                                   // A tiles
   gb.cols.insert(gb.cols.end(), psi.begin(), psi.end());  // B: Psi
-  for (int j = 0; j < 32; ++j) {                   // B: L Psi
+  for (int jp = 0; jp < np; ++jp)                  // B: L_j Psi per piece
+    for (int j = 0; j < 32; ++j) {
+      ColDesc cd = col_null();
+      if (j < cap) cd = LRcol(jp, j);
+      else if (j == cap && aug) cd = ColDesc{(const char*)Ld + (size_t)jp * ng * sf, aug, 0, f32 ? 1 : 0};
+      gb.cols.push_back(cd);
+    }
+  for (int j = 0; j < 16; ++j) {                   // B: states, then forcing fields
     ColDesc cd = col_null();
-    if (j < cap) cd = LRcol(j);
-    else if (j == cap && aug) cd = ColDesc{Ld, aug, 0, f32 ? 1 : 0};
+    if (j < w.n_in) cd = f64col(w.u_in[j]);
+    else if (forced && j >= 2 && j < 2 + np)
+      cd = col_of(forcing, j - 2, ng, f32, nullptr);
     gb.cols.push_back(cd);
   }
-  for (int j = 0; j < 16; ++j)                     // B: states
-    gb.cols.push_back(j < w.n_in ? f64col(w.u_in[j]) : col_null());
+  const int nb = 2 + 2 * np + 1;
   gb.out = Sbig;
-  gb.ld = 80;
+  gb.ld = 16 * nb;
   gb.scale = h3;
-  enqueue_gram(c, {gb}, 2, 5, false, s, "co_g");
+  enqueue_gram(c, {gb}, 2, nb, false, s, "co_g");
 
   P.begin(4);
   double* beta = w.beta_out ? w.beta_out : betas;
   ReducedDesc rd{};
   rd.S = Sbig;
-  rd.ld = 80;
+  rd.ld = 16 * nb;
   rd.cap = cap;
   rd.m = w.m;
   rd.aug = aug;
   rd.off_M = 0;
   rd.off_L = 32;
-  rd.off_U = 64;
+  rd.off_U = 32 + 32 * np;
   rd.n_in = w.n_in;
   rd.dT = w.dT;
   rd.n_c = w.n_c;
+  rd.forced = forced ? geom_of(c, p).forced : 0;
+  rd.npieces = np;
+  rd.off_F = rd.off_U + 2;
+  rd.w = forced ? p.fp[2] : 0.0;
+  rd.t0 = w.t0;
   rd.beta = beta;
   rd.coef = coef;
   rd.n_c_out = w.n_c_out;
@@ -962,12 +1143,12 @@ void pr_ctx_destroy(pr_ctx* c) {
   delete c;
 }
 
-pr_status pr_fine_tuned(const pr_ctx* c, int precision, int n, int batch, int* tile_y,
-                        int* tile_z, int* threads, int* planes) {
+pr_status pr_fine_tuned(const pr_ctx* c, int precision, int forced, int n, int batch,
+                        int* tile_y, int* tile_z, int* threads, int* planes) {
   if (!c || batch < 1 || (precision != PR_F64 && precision != PR_MIXED)) return PR_EINVAL;
-  int code = forced_cfg();
+  int code = forced ? forced_cfg_forced() : forced_cfg();
   if (code < 0) {
-    auto it = c->tuned.find(tune_key(precision == PR_MIXED ? 4 : 8, n, batch));
+    auto it = c->tuned.find(tune_key(precision == PR_MIXED ? 4 : 8, n, batch, forced != 0));
     if (it == c->tuned.end()) return PR_EINVAL;
     code = it->second;
   }
@@ -980,7 +1161,7 @@ pr_status pr_fine_tuned(const pr_ctx* c, int precision, int n, int batch, int* t
     pr_grid_problem p{};
     p.n = n;
     const std::vector<FineWork> items(batch, FineWork{&p, 0.0, 0, nullptr, nullptr, 0, nullptr});
-    *planes = std::min(n, fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs]));
+    *planes = std::min(n, fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs], forced != 0));
   }
   return PR_OK;
 }
@@ -998,7 +1179,8 @@ pr_status pr_fine_propagate(pr_ctx* c, int batch, const pr_fine_item* items, voi
   std::vector<FineWork> w;
   for (int i = 0; i < batch; ++i) {
     const pr_fine_item& it = items[i];
-    w.push_back(FineWork{it.prob, it.dt, it.n_steps, it.u_in, it.u_out, it.snap_every, it.snaps});
+    w.push_back(FineWork{it.prob, it.dt, it.n_steps, it.u_in, it.u_out, it.snap_every, it.snaps,
+                         it.t0, 0});
   }
   stage_begin(c, s);
   enqueue_fine(c, w, s, "api_fine");
@@ -1110,6 +1292,8 @@ pr_status pr_coarse_propagate(pr_ctx* c, int batch, const pr_coarse_item* items,
     w.u_in[1] = it.n_in > 1 ? it.u_in[1] : nullptr;
     w.dT = it.dT_total;
     w.n_c = n_c;
+    w.t0 = it.t0;
+    w.forcing = nullptr;
     w.lift[0] = it.u_out[0];
     w.lift[1] = it.n_in > 1 ? it.u_out[1] : nullptr;
     w.beta_out = it.beta_out;

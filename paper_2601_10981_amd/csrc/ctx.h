@@ -73,6 +73,9 @@ void stage_end(pr_ctx* c, hipStream_t s);
 
 // Problem geometry with device velocity tables.
 Geom geom_of(pr_ctx* c, const pr_grid_problem& p);
+Geom geom_piece(const Geom& g, int j);
+bool forced_flow(const pr_grid_problem& p);
+int flow_pieces(const pr_grid_problem& p);
 double spacing(const pr_grid_problem& p);
 double spectral_bound(const pr_grid_problem& p);
 void check_problem(const pr_grid_problem* p);
@@ -98,6 +101,8 @@ struct FineWork {
   double* u_out;
   int snap_every;
   void* snaps;
+  double t0 = 0.0;      // forced flows: start time
+  int unforced = 0;     // forced flows: 1 = homogeneous propagator (no f)
 };
 void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
                   const std::string& tag);
@@ -135,8 +140,12 @@ struct ApplyLWork {
   void* out;
   int ncols;
   const int* mptr;
+  int piece = 0;          // forced flows: apply piece `piece` of L(t)
 };
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
+void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
+                           int ncols, const int* mptr, hipStream_t s);
+void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s);
 
 // The coarse step of the sweep (eqaug, eq12, eq13, formula4): augment span(R)
 // with u_aug, form the Galerkin matrices of Psi = [R, d] against [Psi, L Psi,
@@ -146,7 +155,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
 struct CoarseWork {
   const pr_grid_problem* prob;
   const void* R;          // N_g x cap (field precision)
-  const void* LR;         // L R (N_g x cap), may be nullptr (then computed)
+  const void* LR;         // L_j R (N_g x cap per piece j), may be nullptr (then computed)
   int cap;
   const int* m;
   const double* u_aug;    // nullable
@@ -154,6 +163,8 @@ struct CoarseWork {
   const double* u_in[2];
   double dT;
   int n_c;
+  double t0;              // start time (forced flows)
+  const void* forcing;    // forced flows: the pieces' f_j (field precision), nullable
   // outputs
   double* lift[2];        // nullable
   double* beta_out;       // nullable, n_in x (cap + 1)

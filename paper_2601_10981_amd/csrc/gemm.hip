@@ -259,7 +259,7 @@ static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
 }
 
 #define PR_GEMM_SHAPES(X) \
-  X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 1) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(1, 2) X(1, 4)
+  X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 1) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 7) X(2, 9) X(1, 2) X(1, 4)
 
 void launch_gemm_tn(const GemmDesc* d, int nd, long long total_wg, int na, int nb, bool f32,
                     hipStream_t s) {

@@ -46,7 +46,13 @@ struct Plan {
   double dt_c;
   int waveF, waveS;
   size_t fixed_bytes, perF, perS;
+  int np;          // time-space pieces of the flow (1: steady)
+  bool forced;     // forced, time-dependent flow
 };
+
+// Start time of parareal subinterval n (state U_n at t_hat_n = (n + 1) DeltaT;
+// subinterval 0 of [0, T] is the warm-up window).
+static double t_hat(const Plan& P, int n) { return (double)(n + 1) * P.dTs; }
 
 static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   check_problem(p);
@@ -110,13 +116,18 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   // of stage-1 bases, u0, small matrices. The fixed-POD mode keeps only the
   // k = 0 snapshots and basis (one wave slot each) and no stage-1 bases.
   const bool plain = P.fixed || P.grid;   // no local bases after k = 0
+  // A forced flow's operator has np time-space pieces: L_j is applied to
+  // every basis separately, and the np forcing fields stay resident.
+  P.np = flow_pieces(*p);
+  P.forced = forced_flow(*p);
   P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 +
                   (P.grid ? 0
-                          : (P.fixed ? (size_t)P.n_s * fs + 2 * (size_t)o->cap * fs
+                          : (P.fixed ? (size_t)P.n_s * fs + (1 + (size_t)P.np) * o->cap * fs
                                      : 2 * Np1 * o->cap0 * fs)) +
-                  f8 + ((size_t)4 << 20);
+                  (P.forced && !P.grid ? (size_t)P.np * fs : 0) + f8 + ((size_t)4 << 20);
   P.perF = plain ? 0 : (size_t)P.n_s * fs;        // snapshots of one subinterval
-  P.perS = plain ? 0 : 2 * (size_t)o->cap * fs;   // stage-2 basis and L applied to it
+  // stage-2 basis and the pieces of L applied to it
+  P.perS = plain ? 0 : (1 + (size_t)P.np) * o->cap * fs;
   return P;
 }
 
@@ -155,9 +166,13 @@ static size_t shared_scratch_bytes(const Plan& P) {
   const size_t nch = (size_t)((P.ng + ch - 1) / ch);
   // coarse-grid mode: two coarse fields, the coarse fine-step work fields
   const size_t grid = P.grid ? (size_t)P.pc.n * P.pc.n * P.pc.n * (16 + (P.f32 ? 12 : 8)) : 0;
+  // coarse step: augmentation fields d, L_j d (co_fields) and Gram partials
+  // of the widest Galerkin product (2 x (2 + 2 np + 1) tile pairs)
+  const size_t gal = (size_t)2 * (2 + 2 * P.np + 1);
   return fine_scratch_item(P.ng, P.f32) * (size_t)std::max(P.waveF, 1) +
-         pod_scratch_item(P.ng) * (size_t)std::max({P.waveF, P.waveS, 1}) + 2 * fs + f8 +
-         (size_t)P.o.cap * fs + nch * 10 * 256 * 8 + grid + ((size_t)16 << 20);
+         pod_scratch_item(P.ng) * (size_t)std::max({P.waveF, P.waveS, 1}) +
+         (1 + (size_t)P.np) * fs + f8 + (size_t)P.o.cap * fs +
+         nch * std::max<size_t>(10, gal) * 256 * 8 + grid + ((size_t)16 << 20);
 }
 
 static void choose_waves(Plan& P, size_t avail) {
@@ -198,7 +213,8 @@ struct pr_solve {
   char* R0 = nullptr;
   char* snaps = nullptr;
   char* Psi = nullptr;
-  char* LPsi = nullptr;
+  char* LPsi = nullptr;     // per wave slot: np blocks of cap columns (L_j Psi)
+  char* forcing = nullptr;  // forced flows: f_j fields of the np pieces
   double *norms = nullptr, *betas0 = nullptr, *S0 = nullptr, *dscal = nullptr;
   int *m0slot = nullptr, *mS = nullptr, *misc = nullptr, *ranks = nullptr;
   double* host = nullptr;  // pinned: e_k, err_k
@@ -240,12 +256,14 @@ static double since(const pr_solve* S) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
 }
 
-// One coarse-grid coarse step: out = P(F_c(R(a - b))) + fine (b, fine
-// nullable), with the jump / error partials of out into norms4 (the
-// comparison method with a coarser spatial discretisation, Sec. 4).
+// One coarse-grid coarse step over [t0, t0 + DeltaT]: out = P(F_c(R(a - b)))
+// + fine (b, fine nullable), with the jump / error partials of out into
+// norms4 (the comparison method with a coarser spatial discretisation,
+// Sec. 4). For a forced flow F_c is affine; with b given the forcing cancels
+// in F_c(R a) - F_c(R b), so the homogeneous propagator runs on R(a - b).
 static void enqueue_grid_step(pr_ctx* c, pr_solve* S, const double* a, const double* b,
                               const double* fine, double* out, const double* prev,
-                              const double* ref, double* norms4, hipStream_t s) {
+                              const double* ref, double* norms4, double t0, hipStream_t s) {
   const Plan& P = S->P;
   const int m = P.pc.n;
   const long long mc = (long long)m * m * m;
@@ -256,7 +274,8 @@ static void enqueue_grid_step(pr_ctx* c, pr_solve* S, const double* a, const dou
   RestrictDesc* rdd = stage_push1(c, rd);
   stage_flush(c, s);
   launch_restrict(rdd, mc, s);
-  enqueue_fine(c, {FineWork{&S->P.pc, P.dt_c, P.n_g, cb, cb + mc, 0, nullptr}}, s, "co_fine");
+  enqueue_fine(c, {FineWork{&S->P.pc, P.dt_c, P.n_g, cb, cb + mc, 0, nullptr, t0, b ? 1 : 0}}, s,
+               "co_fine");
   const double h = spacing(P.prob);
   ProlongDesc pd{m, cb + mc, fine, out, prev, ref, part, nwg};
   ProlongDesc* pdd = stage_push1(c, pd);
@@ -304,10 +323,11 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     if (!P.grid) {
       S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * fs);
       S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
-      S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
+      S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * fs);
+      if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * fs);
     }
     const int maxk = P.max_iter;
-    const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 80, n_dscal = 8;
+    const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 144, n_dscal = 8;
     const size_t n_dbl = n_norms + n_betas + n_S0 + n_dscal;
     const size_t n_int = 2 * Np1 + (size_t)P.waveS + 64 + (size_t)(maxk + 1) * Np1;
     char* small = (char*)owned_alloc(c, S, n_dbl * 8 + n_int * 4);
@@ -340,7 +360,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     stage_begin(c, s);
     ph.begin(0);
     enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.grid ? 0 : P.dM,
-                              P.grid ? nullptr : S->snaps}},
+                              P.grid ? nullptr : S->snaps, 0.0, 0}},
                  s, "sol_fine");
     S->fine_updates += (double)P.n_f * ng;
     if (Np > 0 && P.grid) {
@@ -349,7 +369,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       for (int n = 0; n < Np; ++n)
         enqueue_grid_step(c, S, Ua + (size_t)n * ng, nullptr, nullptr, Ua + (size_t)(n + 1) * ng,
                           nullptr, S->U_ref ? S->U_ref + (size_t)(n + 2) * ng : nullptr,
-                          S->norms + 4 * (n + 1), s);
+                          S->norms + 4 * (n + 1), t_hat(P, n), s);
     } else if (Np > 0) {
       ph.begin(1);
       PodWork pw;
@@ -363,30 +383,43 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       pw.lambda_out = nullptr;
       enqueue_pod(c, {pw}, s, "sol_pod");
       ph.begin(2);
-      enqueue_applyL(c, p, S->Psi, S->LPsi, cap, S->mS, s);
+      // the Galerkin products of the k = 0 basis: Psi^T M [Psi, L_j Psi, U_0,
+      // f_j] (one L block per time-space piece of a forced flow)
+      const int np = P.np, nb = 2 + 2 * np + 1;
+      enqueue_applyL_pieces(c, p, S->Psi, S->LPsi, cap, S->mS, s);
+      if (P.forced) enqueue_forcing_fields(c, p, S->forcing, s);
       GramWork g;
       g.nrows = ng;
       std::vector<ColDesc> a;
       for (int j = 0; j < 32; ++j) a.push_back(j < cap ? colp(S->Psi, j, ng, P.f32, S->mS) : colnull());
       g.cols = a;
       g.cols.insert(g.cols.end(), a.begin(), a.end());
-      for (int j = 0; j < 32; ++j)
-        g.cols.push_back(j < cap ? colp(S->LPsi, j, ng, P.f32, S->mS) : colnull());
+      for (int jp = 0; jp < np; ++jp)
+        for (int j = 0; j < 32; ++j)
+          g.cols.push_back(j < cap ? colp(S->LPsi + (size_t)jp * cap * fs, j, ng, P.f32, S->mS)
+                                   : colnull());
       g.cols.push_back(ColDesc{Ua, nullptr, 0, 0});
-      g.cols.resize((2 + 5) * 16, colnull());
+      g.cols.push_back(colnull());
+      for (int jp = 0; jp < np && P.forced; ++jp)
+        g.cols.push_back(colp(S->forcing, jp, ng, P.f32, nullptr));
+      g.cols.resize((2 + nb) * 16, colnull());
       g.out = S->S0;
-      g.ld = 80;
+      g.ld = 16 * nb;
       g.scale = h3;
-      enqueue_gram(c, {g}, 2, 5, false, s, "co_g");
+      enqueue_gram(c, {g}, 2, nb, false, s, "co_g");
       ph.begin(4);
       Reduced0Desc d{};
       d.S = S->S0;
-      d.ld = 80;
+      d.ld = 16 * nb;
       d.cap = cap;
       d.m = S->mS;
       d.off_M = 0;
       d.off_L = 32;
-      d.off_U = 64;
+      d.off_U = 32 + 32 * np;
+      d.forced = P.forced ? geom_of(c, p).forced : 0;
+      d.npieces = np;
+      d.off_F = d.off_U + 2;
+      d.w = P.forced ? p.fp[2] : 0.0;
       d.dT = P.dTs;
       d.n_c = P.n_c;
       d.count = Np;
@@ -485,7 +518,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           // plain fine solves: no snapshots, no stage-1 basis (an empty POD
           // item is skipped below)
           fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
-                                S->Fn + (size_t)n * P.ng, 0, nullptr});
+                                S->Fn + (size_t)n * P.ng, 0, nullptr, t_hat(P, n), 0});
           PodWork none;
           none.prob = &S->P.prob;
           pw.push_back(none);
@@ -493,7 +526,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         }
         void* sn = S->snaps + (size_t)(n - n0) * P.n_s * fs;
         fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
-                              S->Fn + (size_t)n * P.ng, P.dM, sn});
+                              S->Fn + (size_t)n * P.ng, P.dM, sn, t_hat(P, n), 0});
         PodWork w;
         w.prob = &S->P.prob;
         for (int j = 0; j < P.n_s; ++j) w.cols.push_back(colp(sn, j, P.ng, P.f32, nullptr));
@@ -578,7 +611,8 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         enqueue_grid_step(c, S, Ucur + (size_t)n * ng, Uprev + (size_t)n * ng,
                           S->Fn + (size_t)n * ng, Ucur + (size_t)(n + 1) * ng,
                           Uprev + (size_t)(n + 1) * ng,
-                          Uref ? Uref + (size_t)(n + 2) * ng : nullptr, S->norms + 4 * (n + 1), s);
+                          Uref ? Uref + (size_t)(n + 2) * ng : nullptr, S->norms + 4 * (n + 1),
+                          t_hat(P, n), s);
     }
     // (iv) for the fixed-POD mode: the k = 0 basis (wave slot 0 of the stage-2
     // buffers, never overwritten in this mode) without augmentation
@@ -597,6 +631,8 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.u_in[1] = Uprev + (size_t)n * ng;
         w.dT = P.dTs;
         w.n_c = P.n_c;
+        w.t0 = t_hat(P, n);
+        w.forcing = S->forcing;
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
         w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;
@@ -632,8 +668,10 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.m_out = S->mS + (n - n0);
         w.lambda_out = nullptr;
         pw.push_back(w);
-        aw.push_back(ApplyLWork{&S->P.prob, w.R_out, S->LPsi + (size_t)(n - n0) * cap * fs, cap,
-                                w.m_out});
+        for (int jp = 0; jp < P.np; ++jp)
+          aw.push_back(ApplyLWork{&S->P.prob, w.R_out,
+                                  S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * fs, cap,
+                                  w.m_out, jp});
       }
       ph.begin(1);
       for (int na = 1; na <= 4; ++na) {
@@ -650,7 +688,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         CoarseWork w{};
         w.prob = &S->P.prob;
         w.R = S->Psi + (size_t)(n - n0) * cap * fs;
-        w.LR = S->LPsi + (size_t)(n - n0) * cap * fs;
+        w.LR = S->LPsi + (size_t)(n - n0) * P.np * cap * fs;
         w.cap = cap;
         w.m = S->mS + (n - n0);
         w.u_aug = Ucur + (size_t)n * ng;
@@ -659,6 +697,8 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.u_in[1] = Uprev + (size_t)n * ng;
         w.dT = P.dTs;
         w.n_c = P.n_c;
+        w.t0 = t_hat(P, n);
+        w.forcing = S->forcing;
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
         w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;

@@ -66,13 +66,36 @@ __device__ __forceinline__ PR_GLOBAL T* gptr(T* p) {
 //   v_x(y, z) = t[0][y] + t[1][z],  v_y(x, z) = t[2][x] + t[3][z],
 //   v_z(x, y) = t[4][x] + t[5][y].
 // tab64 holds them in double, tab32 in float (for the FP32 stencil).
+//
+// The forced flows of Sec. 4 separate in time and space:
+// v(x, t) = sum_j theta_j(t) v_j(x) and f(x, t) = sum_j theta_j(t) f_j(x),
+// theta_0 = 1 (Kolmogorov flow: theta_1 = cos(w t); ABC flow with phase
+// s = sin(w t): theta_1 = cos s, theta_2 = sin s). Piece j has nine tables of
+// n values at ptab + 9 n j: the six velocity tables above and
+// f_j(x, y, z) = t[6][x] + t[7][y] + t[8][z]. tab64/tab32 then point at
+// piece 0, so the steady kernels apply piece 0's operator.
+enum { kForcedNone = 0, kForcedKolmogorov = 1, kForcedABC = 2 };
+constexpr int kMaxPieces = 3;
 struct Geom {
   int n;
   int xonly;             // velocity has only an x component (v_y = v_z = 0)
   double c_lap;          // kappa / h^2
   const double* tab64;   // 6 n doubles
   const float* tab32;    // 6 n floats
+  int forced;            // kForced*: which theta functions
+  int npieces;           // pieces of the forced flow (1 for steady flows)
+  double w;              // frequency of the time dependence
+  const double* ptab64;  // npieces x 9 n doubles (forced flows)
+  const float* ptab32;
 };
+
+// theta_j(t) of a forced flow's piece j.
+__host__ __device__ inline double theta_of(int kind, double w, int j, double t) {
+  if (j == 0) return 1.0;
+  if (kind == kForcedKolmogorov) return cos(w * t);
+  const double s = sin(w * t);
+  return j == 1 ? cos(s) : sin(s);
+}
 
 // Column of a tall-skinny operand: N_g values at ptr (float if f32), valid iff
 // mptr == nullptr || idx < *mptr (invalid columns read as zero).
@@ -99,9 +122,14 @@ struct FineDesc {
   double dt;
   int tiles_y, tiles_z, chunks_x, xc;  // (y, z) tiles of the launch's shape, x chunks
   long long tile_begin;
+  // forced flows: step j runs from t0 + j dt; with_forcing = 0 drops f (the
+  // homogeneous propagator, used for differences of two solutions)
+  double t0;
+  int with_forcing;
 };
 constexpr int kFusedHalo = 4;      // one halo layer per RK4 stage
 constexpr int kMaxChunk = 256;     // x planes per fused-stencil workgroup (at most)
+constexpr int kForcedChunk = 128;  // the same for the forced-flow stencil
 // Tile configurations of the fused stencil: output tile TY x TZ of the
 // (y, z) plane per workgroup of NT threads. Every configuration computes
 // bitwise the same values (each point's arithmetic does not depend on the
@@ -115,6 +143,10 @@ constexpr FusedCfg kFusedCfgs[kNumFusedCfgs] = {
     {8, 32, 256},  {16, 64, 512}, {8, 64, 512}};
 inline int fused_ty(int cfg) { return kFusedCfgs[cfg].ty; }
 inline int fused_tz(int cfg) { return kFusedCfgs[cfg].tz; }
+// Tilings of the forced-flow stencil (at most three columns per thread: it
+// keeps per-stage coefficients and an accumulator in registers).
+constexpr int kNumForcedCfgs = 4;
+constexpr int kForcedCfgs[kNumForcedCfgs] = {2, 3, 4, 6};
 
 // ---- L applied to basis columns -------------------------------------------
 template <typename T>
@@ -186,6 +218,14 @@ void launch_fine_step_f64(const FineDesc<double>* d_descs, int nfields, long lon
                           int step, int cfg, hipStream_t s);
 void launch_fine_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
                           int step, int cfg, hipStream_t s);
+// The same for the forced flows (classical RK4 with stage times and forcing);
+// cfg must be one of kForcedCfgs.
+void launch_forced_step_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
+                            int step, int cfg, hipStream_t s);
+void launch_forced_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
+                            int step, int cfg, hipStream_t s);
+// f_j of piece j of a forced flow written as an N_g field (double or float).
+void launch_forcing_field(const Geom& g, int piece, void* out, int out_f32, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, long long n, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, long long n, hipStream_t s);
 void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, hipStream_t s);
@@ -229,6 +269,9 @@ void launch_cholqr_coef(const CholDesc* d, int nitems, hipStream_t s);
 // read from the Gram output: S (q x ld) with Psi^T M Psi in columns
 // [0, q) and Psi^T M L Psi in columns [q_off_L, q_off_L + q) and the
 // projections Psi^T M u_i in column q_off_U + i.
+// Forced flows: S holds Psi^T M L_j Psi in columns [off_L + 32 j, ...) for
+// piece j < npieces and Psi^T M f_j in column off_F + j; the system is
+// M_r beta' = sum_j theta_j(t) (L_r,j beta + f_r,j) from t0.
 struct ReducedDesc {
   const double* S;
   int ld;            // leading dimension of S (row = basis index)
@@ -239,6 +282,8 @@ struct ReducedDesc {
   int n_in;
   double dT;
   int n_c;
+  int forced, npieces, off_F;
+  double w, t0;
   double* beta;      // n_in x (cap + 1): beta_i(dT)
   double* coef;      // nullable: (cap+1): beta_0 - beta_1 (correction coefficients)
   int* n_c_out;      // nullable
@@ -255,6 +300,8 @@ struct Reduced0Desc {
   int off_M, off_L, off_U;
   double dT;
   int n_c;
+  int forced, npieces, off_F;
+  double w;          // subinterval n starts at (n + 1) dT
   int count;
   double* betas;     // count x ld_out
   int ld_out;

@@ -230,6 +230,11 @@ struct RedShared {
   double T[kMaxQ + 1][kMaxQ + 2];
   double beta[2][kMaxQ + 1];
   double tmp[2][kMaxQ + 1];
+  // forced flows: g_j = M_r^{-1} f_r,j and the RK4 stage vectors
+  double g[kMaxPieces][kMaxQ + 1];
+  double y[2][kMaxQ + 1];
+  double kv[2][kMaxQ + 1];
+  double acc[2][kMaxQ + 1];
   int idx[kMaxQ + 1];
   double red[256];
   int q, n_c, bad;
@@ -314,6 +319,79 @@ __device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0) {
   }
 }
 
+// Forced flows: the pieces K_j = M_r^{-1} L_r,j sit in sh.K, sh.B, sh.T (j =
+// 0, 1, 2) and g_j = M_r^{-1} f_r,j in sh.g[j], given sh.M (Cholesky factor)
+// and the unsolved L_r,j / f_r,j in the same places. Solves in place and sets
+// sh.n_c by the guard on sum_j ||K_j||_F (|theta_j| <= 1 bounds
+// ||K(t)||_F by it at every t).
+__device__ void red_forced_setup(RedShared& sh, int q, int np, double dT, int n_c0) {
+  const int tid = threadIdx.x;
+  double (*P[kMaxPieces])[kMaxQ + 2] = {sh.K, sh.B, sh.T};
+  for (int e = tid; e < np * q; e += 256) red_solve(sh, q, &P[e / q][0][e % q], kMaxQ + 2);
+  if (tid < np) red_solve(sh, q, sh.g[tid], 1);
+  __syncthreads();
+  double nrm = 0.0;
+  for (int j = 0; j < np; ++j) {
+    double s = 0.0;
+    for (int e = tid; e < q * q; e += 256) {
+      const double v = P[j][e / q][e % q];
+      s += v * v;
+    }
+    sh.red[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = 0.0;
+      for (int i = 0; i < 256; ++i) t += sh.red[i];
+      sh.tmp[0][0] = sqrt(t);
+    }
+    __syncthreads();
+    nrm += sh.tmp[0][0];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int n_c = max(1, n_c0);
+    while ((dT / n_c) * nrm > kGuard && n_c < (1 << 16)) n_c *= 2;
+    sh.n_c = n_c;
+  }
+  __syncthreads();
+}
+
+// Forced flows: n_c classical RK4 steps of beta' = sum_j theta_j(t)
+// (K_j beta + g_j) over [t0, t0 + dT] for beta[v], v < nv; stages at t,
+// t + h/2, t + h/2, t + h.
+__device__ void red_advance_forced(RedShared& sh, int q, int nv, int np, int kind, double w,
+                                   double t0, double dT) {
+  const int tid = threadIdx.x;
+  double (*P[kMaxPieces])[kMaxQ + 2] = {sh.K, sh.B, sh.T};
+  const double h = dT / sh.n_c;
+  const bool act = tid < nv * q;
+  const int v = act ? tid / q : 0, i = act ? tid % q : 0;
+  const double cst[4] = {0.0, 0.5, 0.5, 1.0};     // stage time offsets
+  const double cin[4] = {0.0, 0.5, 0.5, 1.0};     // stage input weights (of h)
+  const double cacc[4] = {1.0, 2.0, 2.0, 1.0};
+  for (int it = 0; it < sh.n_c; ++it) {
+    const double t = t0 + it * h;
+    for (int st = 0; st < 4; ++st) {
+      if (act) sh.y[v][i] = st == 0 ? sh.beta[v][i] : fma(cin[st] * h, sh.kv[v][i], sh.beta[v][i]);
+      __syncthreads();
+      if (act) {
+        const double ta = t + cst[st] * h;
+        double k = 0.0;
+        for (int j = 0; j < np; ++j) {
+          double r = sh.g[j][i];
+          for (int l = 0; l < q; ++l) r = fma(P[j][i][l], sh.y[v][l], r);
+          k = fma(theta_of(kind, w, j, ta), r, k);
+        }
+        sh.kv[v][i] = k;
+        sh.acc[v][i] = st == 0 ? k : fma(cacc[st], k, sh.acc[v][i]);
+      }
+      __syncthreads();
+    }
+    if (act) sh.beta[v][i] = fma(h / 6.0, sh.acc[v][i], sh.beta[v][i]);
+    __syncthreads();
+  }
+}
+
 // beta[v] <- B^{n_c} beta[v] for v < nv.
 __device__ void red_advance(RedShared& sh, int q, int nv) {
   const int tid = threadIdx.x;
@@ -345,22 +423,34 @@ __global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__
   }
   __syncthreads();
   const int q = sh.q;
+  const int np = d.forced ? d.npieces : 1;
   for (int e = tid; e < q * q; e += 256) {
     const int a = e / q, b = e % q;
     const double* row = d.S + (long long)sh.idx[a] * d.ld;
     sh.M[a][b] = row[d.off_M + sh.idx[b]];
     sh.K[a][b] = row[d.off_L + sh.idx[b]];
+    if (np > 1) sh.B[a][b] = row[d.off_L + 32 + sh.idx[b]];
+    if (np > 2) sh.T[a][b] = row[d.off_L + 64 + sh.idx[b]];
   }
   if (tid < d.n_in * q) {
     const int v = tid / q, a = tid % q;
     sh.beta[v][a] = d.S[(long long)sh.idx[a] * d.ld + d.off_U + v];
   }
+  if (d.forced && tid < np * q) {
+    const int j = tid / q, a = tid % q;
+    sh.g[j][a] = d.S[(long long)sh.idx[a] * d.ld + d.off_F + j];
+  }
   __syncthreads();
   red_cholesky(sh, q);
   if (tid < d.n_in) red_solve(sh, q, sh.beta[tid], 1);
   __syncthreads();
-  red_propagator(sh, q, d.dT, d.n_c);
-  red_advance(sh, q, d.n_in);
+  if (d.forced) {
+    red_forced_setup(sh, q, np, d.dT, d.n_c);
+    red_advance_forced(sh, q, d.n_in, np, d.forced, d.w, d.t0, d.dT);
+  } else {
+    red_propagator(sh, q, d.dT, d.n_c);
+    red_advance(sh, q, d.n_in);
+  }
   const int w = d.cap + 1;
   for (int e = tid; e < d.n_in * w; e += 256) d.beta[e] = 0.0;
   if (d.coef)
@@ -398,20 +488,27 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   }
   __syncthreads();
   const int q = sh.q;
+  const int np = d.forced ? d.npieces : 1;
   for (int e = tid; e < q * q; e += 256) {
     const int a = e / q, b = e % q;
     const double* row = d.S + (long long)a * d.ld;
     sh.M[a][b] = row[d.off_M + b];
     sh.K[a][b] = row[d.off_L + b];
+    if (np > 1) sh.B[a][b] = row[d.off_L + 32 + b];
+    if (np > 2) sh.T[a][b] = row[d.off_L + 64 + b];
   }
   if (tid < q) sh.beta[0][tid] = d.S[(long long)tid * d.ld + d.off_U];
+  if (d.forced && tid < np * q) sh.g[tid / q][tid % q] = d.S[(long long)(tid % q) * d.ld + d.off_F + tid / q];
   __syncthreads();
   red_cholesky(sh, q);
   if (tid == 0) red_solve(sh, q, sh.beta[0], 1);
   __syncthreads();
-  red_propagator(sh, q, d.dT, d.n_c);
+  if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c);
+  else red_propagator(sh, q, d.dT, d.n_c);
   for (int n = 0; n < d.count; ++n) {
-    red_advance(sh, q, 1);
+    // subinterval n runs over [(n + 1) dT, (n + 2) dT]
+    if (d.forced) red_advance_forced(sh, q, 1, np, d.forced, d.w, (double)(n + 1) * d.dT, d.dT);
+    else red_advance(sh, q, 1);
     for (int e = tid; e < d.ld_out; e += 256)
       d.betas[(long long)n * d.ld_out + e] = (e < q) ? sh.beta[0][e] : 0.0;
   }

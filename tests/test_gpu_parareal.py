@@ -16,7 +16,7 @@ import pytest
 
 import workloads as W
 from oracle import fd, parareal
-from gpu_helpers import rel_l2, say, to_dev, to_np
+from gpu_helpers import rel_l2, roundoff_envelope as _roundoff_envelope, say, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -64,32 +64,6 @@ def test_parareal_finite_termination(ctx):
     for j in range(opts.N + 1):
         assert rel_l2(to_np(U[j]), oref[j]) <= 1e-12
     assert rep.err[-1] == 0.0
-
-
-def _roundoff_envelope(prob, opts, u0, base, kmax, seeds=(0, 1)):
-    """How far the oracle's own iterates move when every snapshot matrix is
-    perturbed by one unit in the last place (relative 2.2e-16, seeded): the
-    POD modes near the rank cut (lambda ~ 1e-13 lambda_1) are fixed by the
-    data only to about eps lambda_1 / gap, so intermediate iterates of any
-    FP64 implementation agree only to this envelope. Returns env[k]."""
-    from oracle import pod
-    orig = pod.gram
-    env = [0.0] * (kmax + 1)
-    try:
-        for sd in seeds:
-            rng = np.random.Generator(np.random.PCG64(1000 + sd))
-
-            def g(Wm, h3):
-                return orig(Wm * (1.0 + 2.2e-16 * rng.uniform(-1.0, 1.0, Wm.shape)), h3)
-            pod.gram = g
-            alt = parareal.solve(prob, opts, u0, keep_history=True)
-            pod.gram = orig
-            for k in range(1, kmax + 1):
-                e = max(rel_l2(a, b) for a, b in zip(alt.history[k], base.history[k]))
-                env[k] = max(env[k], e)
-    finally:
-        pod.gram = orig
-    return env
 
 
 @pytest.mark.parametrize("ml,p", [(1, 1), (0, 0), (1, 0), (0, 1)])
