@@ -53,6 +53,11 @@ def parse():
                     help="iterations of the --mixed256 run")
     ap.add_argument("--study", action="store_true",
                     help="report run of the (m_l, p) x kappa grid on 32^3 ABC (own JSON line)")
+    ap.add_argument("--paper-flow", action="store_true",
+                    help="report run of the forced flows of Sec. 4 on 128^3 (own JSON line): "
+                         "forced-stencil roofline and error per iteration of the three modes")
+    ap.add_argument("--paper-N", type=int, default=41,
+                    help="subintervals of the --paper-flow runs (DeltaT = 5)")
     return ap.parse_args()
 
 
@@ -60,19 +65,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-STENCIL_SRC = os.path.join(ROOT, "paper_2601_10981_amd", "csrc", "stencil.hip")
+CSRC = os.path.join(ROOT, "paper_2601_10981_amd", "csrc")
+STENCIL_SRC = os.path.join(CSRC, "stencil.hip")
 STENCIL_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_fused_f64_kolmogorov128_batch63.md")
+FORCED_SRC = os.path.join(CSRC, "forced.hip")
+FORCED_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_forced_f64_paperkolmogorov128_batch40.md")
 
 
-def profiled_traffic(kernel):
-    """HBM bytes per launch of the stencil kernel from the committed PMC
-    summary, or None when the kernel source or tiling changed since it was
-    taken."""
+def _sources_sha(paths):
     import hashlib
+    h = hashlib.sha256()
+    for q in paths:
+        h.update(open(q, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, src=None, profile=STENCIL_PROFILE):
+    """HBM bytes per launch of a stencil kernel from its committed PMC
+    summary, or None when the kernel's sources (its .hip file and the shared
+    stencil_dev.h) or its tiling changed since it was taken."""
     try:
-        sha = hashlib.sha256(open(STENCIL_SRC, "rb").read()).hexdigest()[:16]
+        sha = _sources_sha([src or STENCIL_SRC, os.path.join(CSRC, "stencil_dev.h")])
         fields = {}
-        for line in open(STENCIL_PROFILE):
+        for line in open(profile):
             if ":" in line and not line.startswith(("|", "#", " ")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
@@ -306,6 +321,134 @@ def study_run(args):
     print(json.dumps({"mode": "study", "n": n, "N": N, "T": 2.0, "flow": "ABC", "rows": rows}))
 
 
+def paper_flow_run(args):
+    """The forced flows of Sec. 4 (the Kolmogorov flow of eq. koleq and the
+    ABC flow with phase sin(t)) at the paper's 2,097,152 unknowns (128^3) and
+    its time parameters: delta t = 1e-2, DeltaT = 5 (n_f = 500), coarse step
+    dT = 0.5 (coarse_ratio 50), the paper's gamma_1..3, initial value h = 0.
+    delta_M = 10 (the paper's 5 would give 101 snapshots per subinterval, above
+    the 64-column POD input), epsilon = 0.01 (one of the paper's AdapParareal
+    cases; its explicit RK4 step is stable at delta t = 1e-2), N = --paper-N
+    subintervals (the paper: 201), rank caps 21 / 31. For each flow: the
+    forced stencil's roofline on the batched fine launch of one iteration,
+    then the adaptive method ((m_l, p) = (1, 1)) and the two comparison
+    methods, error per iteration against the serial fine solution."""
+    import dataclasses
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    n, N, dt, dTs = 128, args.paper_N, 1e-2, 5.0
+    ng = n ** 3
+    base = W.PararealOpts(T=dTs * N, N=N, dt=dt, dM=10, gamma1=1.0 - 5.0e-6,
+                          gamma2=1.0 - 5.0e-6, gamma3=1.0 - 2.0e-8, cap0=21, cap=31, ml=1, p=1,
+                          coarse_ratio=50, tol=1e-6, max_iter=args.max_iter)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    free, _ = torch.cuda.mem_get_info()
+    ctx = pr.Context(0, budget_bytes=int(0.85 * free))
+    out = {"metric": "forced flows of Sec. 4: forced-stencil GPts/s + %HBM; error per iteration",
+           "n": n, "dofs": ng, "dt": dt, "DeltaT": dTs, "N": N, "T": dTs * N, "kappa": 0.01,
+           "dM": base.dM, "coarse_ratio": base.coarse_ratio, "cap0": base.cap0, "cap": base.cap,
+           "initial_value": "h = 0 (Sec. 4)", "flows": {}}
+    for name, flow in (("kolmogorov", W.FLOW_KOLMOGOROV_T), ("abc", W.FLOW_ABC_T)):
+        prob = pr.problem(n, 0.01, flow, (1.0, 1.0, 1.0))
+        plan = pr.pr_plan(prob, base)
+        n_f = plan["n_f"]
+        res = {"n_f": n_f, "n_c": plan["n_c"]}
+        # forced-stencil roofline: the batched fine launch of one iteration
+        B = N - 1
+        log(f"paper flow {name}: stencil timing {B} x {n}^3, {n_f} steps")
+        xin = torch.stack([W.fourier_field_device(n, 11 + i, "cuda").reshape(-1) for i in range(B)])
+        xout = torch.empty_like(xin)
+        items = [dict(prob=prob, dt=plan["dt"], n_steps=n_f, u_in=xin[i], u_out=xout[i],
+                      t0=(i + 1) * dTs) for i in range(B)]
+        pr.pr_fine_propagate(ctx, items)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        pr.pr_fine_propagate(ctx, items)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        avg = ms * 1e-3 / n_f
+        bpl = 16 * ng * B
+        tiling = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, planes=True, forced=True)
+        kname = ("k_rk4_forced<double,%d,%d,%d>/x%d" % tiling) if tiling else "k_rk4_forced<double>"
+        achieved = bpl / avg / 1e9
+        res["stencil_gpts"] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
+        res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": profiled_traffic(kname, FORCED_SRC, FORCED_PROFILE)
+                           if name == "kolmogorov" else None,
+                           "kernel": kname, "avg_launch_us": round(avg * 1e6, 2),
+                           "bytes_per_launch": bpl}
+        log(f"  {res['stencil_gpts']} GPts/s, {res['roofline']['frac']} of HBM peak")
+        if args.sweep:
+            sweep = {}
+            for pol in range(3):
+                os.environ["PR_FUSED_CHUNK"] = str(pol)
+                for cfg in range(5):
+                    os.environ["PR_FORCED_CFG"] = str(cfg)
+                    pr.pr_fine_propagate(ctx, items)
+                    e0.record(stream)
+                    pr.pr_fine_propagate(ctx, items)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, forced=True)
+                    key = "%dx%dx%d/chunks%d" % (t + (pol,))
+                    sweep[key] = round(B * ng * n_f / (e0.elapsed_time(e1) * 1e-3) / 1e9, 2)
+                    log(f"  tiling {key}: {sweep[key]} GPts/s")
+            del os.environ["PR_FORCED_CFG"]
+            del os.environ["PR_FUSED_CHUNK"]
+            res["roofline"]["sweep_gpts"] = sweep
+        del xin, xout
+        if args.stencil_only:
+            out["flows"][name] = res
+            break
+        # serial fine reference from h = 0
+        U_ref = torch.zeros((N + 1, ng), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(N):
+            pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=plan["dt"], n_steps=n_f, u_in=U_ref[j],
+                                            u_out=U_ref[j + 1], t0=j * dTs)])
+        torch.cuda.synchronize()
+        res["serial_fine_s"] = round(time.perf_counter() - t0, 3)
+        u0 = torch.zeros(ng, dtype=torch.float64, device="cuda")
+        for mname, mode in (("adaptive_ml1_p1", W.MODE_ADAPTIVE), ("parareal_I_fixed_pod",
+                                                                   W.MODE_FIXED_POD),
+                            ("parareal_II_coarse_grid", W.MODE_COARSE_GRID)):
+            opts = dataclasses.replace(base, mode=mode)
+            log(f"  {mname}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                _, rep = pr.pr_parareal_solve(ctx, prob, opts, u0, U_ref=U_ref)
+            except pr.PrError as e:
+                res[mname] = {"error": e.name}
+                continue
+            el = time.perf_counter() - t0
+            res[mname] = {"iters": rep.iters, "converged": rep.converged, "seconds": round(el, 3),
+                          "m0": rep.m0, "err_history": [float("%.3e" % e) for e in rep.err],
+                          "jump_history": [float("%.3e" % e) for e in rep.jump],
+                          "t_iter_s": [round(t, 3) for t in rep.t_iter],
+                          "t_phase_s": {k: round(v, 3) for k, v in rep.t_phase.items()},
+                          "ranks_k1": rep.ranks[0][:8] if rep.ranks else None}
+            log(f"    iters {rep.iters} err {res[mname]['err_history']}")
+        out["flows"][name] = res
+        del U_ref
+        torch.cuda.empty_cache()
+    if args.stencil_only:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = a.numel() * 8
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -317,6 +460,8 @@ def main():
         return ensemble_run(args)
     if args.study:
         return study_run(args)
+    if args.paper_flow:
+        return paper_flow_run(args)
     import numpy as np
     import torch
     import paper_2601_10981_amd as pr
@@ -393,7 +538,7 @@ def main():
         sweep = {}
         for pol in range(3):
             os.environ["PR_FUSED_CHUNK"] = str(pol)
-            for cfg in range(7):
+            for cfg in range(8):
                 os.environ["PR_FUSED_CFG"] = str(cfg)
                 pr.pr_fine_propagate(ctx, items)
                 e0.record(stream)

@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpr.so")
-SOURCES = ["stencil.hip", "gemm.hip", "small.hip", "grid.hip", "capi.cpp", "parareal.cpp"]
+SOURCES = ["stencil.hip", "forced.hip", "gemm.hip", "small.hip", "grid.hip", "capi.cpp",
+           "parareal.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

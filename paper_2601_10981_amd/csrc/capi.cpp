@@ -440,14 +440,16 @@ static std::string tune_key(int value_bytes, int nmax, int batch, bool forced) {
 }
 
 // Launch shapes the tuner tries: every tiling (the forced stencil: those of
-// kForcedCfgs; in FP64 not the 1024-thread one, whose four waves per SIMD
-// leave too few registers) under every chunk policy.
+// kForcedCfgs; in FP64 not a 1024-thread one with two columns per thread,
+// whose four waves per SIMD leave too few registers) under every chunk
+// policy.
 static std::vector<int> shape_codes(bool forced, int value_bytes) {
   std::vector<int> v;
   for (int pol = 0; pol < kChunkPolicies; ++pol) {
     if (forced) {
       for (int i = 0; i < kNumForcedCfgs; ++i)
-        if (!(value_bytes == 8 && kFusedCfgs[kForcedCfgs[i]].nt > 512))
+        if (!(value_bytes == 8 && kFusedCfgs[kForcedCfgs[i]].nt > 512 &&
+              fused_slots(kForcedCfgs[i]) > 1))
           v.push_back(kForcedCfgs[i] + kNumFusedCfgs * pol);
     } else {
       for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg) v.push_back(cfg + kNumFusedCfgs * pol);

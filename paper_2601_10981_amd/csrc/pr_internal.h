@@ -137,16 +137,22 @@ constexpr int kForcedChunk = 128;  // the same for the forced-flow stencil
 struct FusedCfg {
   int ty, tz, nt;
 };
-constexpr int kNumFusedCfgs = 7;
+constexpr int kNumFusedCfgs = 8;
 constexpr FusedCfg kFusedCfgs[kNumFusedCfgs] = {
     {32, 32, 512}, {16, 32, 256}, {16, 32, 512}, {32, 32, 1024},
-    {8, 32, 256},  {16, 64, 512}, {8, 64, 512}};
+    {8, 32, 256},  {16, 64, 512}, {8, 64, 512},  {16, 32, 1024}};
 inline int fused_ty(int cfg) { return kFusedCfgs[cfg].ty; }
 inline int fused_tz(int cfg) { return kFusedCfgs[cfg].tz; }
 // Tilings of the forced-flow stencil (at most three columns per thread: it
 // keeps per-stage coefficients and an accumulator in registers).
-constexpr int kNumForcedCfgs = 4;
-constexpr int kForcedCfgs[kNumForcedCfgs] = {2, 3, 4, 6};
+constexpr int kNumForcedCfgs = 5;
+constexpr int kForcedCfgs[kNumForcedCfgs] = {2, 3, 4, 6, 7};
+// Columns per thread of a tiling (the region with its 4-layer halo over the
+// thread count).
+inline int fused_slots(int cfg) {
+  const FusedCfg& f = kFusedCfgs[cfg];
+  return ((f.ty + 8) * (f.tz + 8) + f.nt - 1) / f.nt;
+}
 
 // ---- L applied to basis columns -------------------------------------------
 template <typename T>

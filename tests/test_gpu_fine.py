@@ -98,7 +98,7 @@ def test_fine_every_tile_configuration_is_bitwise_identical(ctx, prec, monkeypat
     ref_outs, ref_snaps = _run(ctx, cases, prec)          # autotuned
     for pol in range(3):
         monkeypatch.setenv("PR_FUSED_CHUNK", str(pol))
-        for cfg in range(7):
+        for cfg in range(8):
             monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
             outs, snaps = _run(ctx, cases, prec)
             for i in range(len(cases)):

@@ -100,7 +100,7 @@ def test_forced_every_tiling_is_bitwise_identical(ctx, prec, monkeypatch):
     ref_outs, ref_snaps = _run(ctx, CASES, prec)      # autotuned
     for pol in range(3):
         monkeypatch.setenv("PR_FUSED_CHUNK", str(pol))
-        for cfg in range(4):
+        for cfg in range(5):
             monkeypatch.setenv("PR_FORCED_CFG", str(cfg))
             outs, snaps = _run(ctx, CASES, prec)
             for i in range(len(CASES)):
@@ -256,3 +256,25 @@ def test_forced_mixed_precision_converges(ctx):
     assert rep.err[-1] <= 1e-5
     oref = parareal.reference(p64, opts, u0)
     assert rel_l2(to_np(U[-1]), oref[-1]) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", [W.MODE_ADAPTIVE, W.MODE_FIXED_POD], ids=["adaptive", "fixed"])
+def test_forced_zero_initial_value(ctx, mode):
+    """The paper's initial value h = 0 (Sec. 4): the warm-up snapshots start
+    with a zero column, and the forcing alone drives the solution."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _forced(KT, mode, n=12, N=6, T=0.6)
+    u0 = np.zeros(prob.n ** 3)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    ores = parareal.solve(prob, opts, u0, keep_history=True)
+    o = W.PararealOpts(**{**opts.__dict__, "max_iter": 2})
+    U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+    assert rep.iters == 2 and rep.m0 == ores.m0
+    Un = to_np(U)
+    env = roundoff_envelope(prob, opts, u0, ores, 2)
+    worst = max(rel_l2(Un[j + 1], h) for j, h in enumerate(ores.history[2]))
+    say(f"zero initial value mode={mode}: m0 {rep.m0}, worst rel L2 {worst:.3e} (envelope {env[2]:.3e})")
+    assert worst <= 10.0 * env[2] + 1e-12
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.iters == opts.N - 1 and np.array_equal(to_np(U), to_np(ref))
