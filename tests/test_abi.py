@@ -73,3 +73,21 @@ def test_plan_matches_the_oracle_reading(w):
     assert plan["n_s"] == n_f // dM + 1
     assert plan["n_c"] == coarse.coarse_steps(n_f, wl.opts.coarse_ratio)
     assert plan["n_sub"] == wl.opts.N - 1
+
+
+
+@pytest.mark.parametrize("flow,fp,kappa", [(3, (1.0, 1.0, 1.0), 0.01), (4, (0.7, 1.3, 2.0), 0.05),
+                                           (3, (2.5, 0.0, 1.0), 0.0)])
+def test_plan_forced_flows_automatic_step(flow, fp, kappa):
+    """For the forced flows the automatic step uses sum_d max|v_d| = 6 |a_v|
+    (host only, against the oracle's rule)."""
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    from oracle import fd, parareal
+    prob = W.Problem(n=64, kappa=kappa, flow=flow, fp=fp)
+    opts = W.PararealOpts(T=2.0, N=8, dt=0.0)
+    plan = pr.pr_plan(pr.problem_of(prob), opts)
+    n_f, dt = fd.steps_per_subinterval(opts.T / opts.N, parareal.requested_dt(prob, opts))
+    assert plan["n_f"] == n_f
+    assert plan["dt"] == pytest.approx(dt, rel=1e-15)
+    assert fd.velocity_bound(flow, fp) == 6.0 * abs(fp[0])
