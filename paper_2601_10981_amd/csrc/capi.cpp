@@ -545,6 +545,7 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, bool force
     d.dt = w.dt;
     d.t0 = w.t0;
     d.with_forcing = w.unforced ? 0 : 1;
+    d.snap_ld = w.snap_ld > 0 ? w.snap_ld : ng;
     max_steps = std::max(max_steps, w.n_steps);
     descs.push_back(d);
   }
@@ -646,6 +647,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.g = geom_piece(geom_of(c, *w.prob), w.piece);
       a.in = (const float*)w.in;
       a.out = (float*)w.out;
+      a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
       a.ncols = w.ncols;
       a.mptr = w.mptr;
       a.tiles_q = tiles_q(w.prob->n);
@@ -664,6 +666,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.g = geom_piece(geom_of(c, *w.prob), w.piece);
       a.in = (const double*)w.in;
       a.out = (double*)w.out;
+      a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
       a.ncols = w.ncols;
       a.mptr = w.mptr;
       a.tiles_q = tiles_q(w.prob->n);
@@ -683,33 +686,37 @@ void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* o
   enqueue_applyL_batch(c, {ApplyLWork{&p, in, out, ncols, mptr}}, s);
 }
 
-// L_j applied to ncols columns for every piece j of the problem's flow: piece
-// j's columns at out + j * ncols * N_g (one piece, L itself, for a steady
-// flow).
+// L_j applied to ncols columns (ld elements apart; 0: N_g) for every piece j
+// of the problem's flow: piece j's columns at out + j * ncols columns (one
+// piece, L itself, for a steady flow).
 void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
-                           int ncols, const int* mptr, hipStream_t s) {
-  const size_t col = (size_t)ngrid(p) * (p.precision == PR_MIXED ? 4 : 8);
+                           int ncols, const int* mptr, hipStream_t s, long long ld) {
+  if (ld <= 0) ld = ngrid(p);
+  const size_t col = (size_t)ld * (p.precision == PR_MIXED ? 4 : 8);
   std::vector<ApplyLWork> v;
   for (int j = 0; j < flow_pieces(p); ++j)
-    v.push_back(ApplyLWork{&p, in, (char*)out + (size_t)j * ncols * col, ncols, mptr, j});
+    v.push_back(ApplyLWork{&p, in, (char*)out + (size_t)j * ncols * col, ncols, mptr, j, ld});
   enqueue_applyL_batch(c, v, s);
 }
 
 // The forcing fields f_j of a forced flow's pieces (field precision), one
-// after another in out.
-void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s) {
+// column each, ld elements apart (0: N_g).
+void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s,
+                            long long ld) {
+  if (ld <= 0) ld = ngrid(p);
   const Geom g = geom_of(c, p);
   const bool f32 = p.precision == PR_MIXED;
-  const size_t col = (size_t)ngrid(p) * (f32 ? 4 : 8);
+  const size_t col = (size_t)ld * (f32 ? 4 : 8);
   for (int j = 0; j < g.npieces; ++j)
     launch_forcing_field(g, j, (char*)out + (size_t)j * col, f32 ? 1 : 0, s);
 }
 
 // ---------------------------------------------------------------------------
 // POD_Mode
-static ColDesc col_of(const void* base, int idx, long long ng, bool f32, const int* mptr) {
+// Column idx of a block whose columns are ld elements apart.
+static ColDesc col_of(const void* base, int idx, long long ld, bool f32, const int* mptr) {
   ColDesc d;
-  d.ptr = (const char*)base + (size_t)idx * ng * (f32 ? 4 : 8);
+  d.ptr = (const char*)base + (size_t)idx * ld * (f32 ? 4 : 8);
   d.mptr = mptr;
   d.idx = idx;
   d.f32 = f32 ? 1 : 0;
@@ -790,6 +797,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
     t.C = ed[i].coef;
     t.ldc = items[i].cap;
     t.out = items[i].R_out;
+    t.out_ld = items[i].R_ld > 0 ? items[i].R_ld : t.nrows;
     t.out_f32 = f32;
     t.nout = items[i].cap;
     t.out_mptr = items[i].m_out;
@@ -811,8 +819,9 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
     std::vector<std::vector<ColDesc>> rcols(nitems);
     for (int i = 0; i < nitems; ++i) {
       const long long ng = ngrid(*items[i].prob);
+      const long long rld = items[i].R_ld > 0 ? items[i].R_ld : ng;
       for (int j = 0; j < 32; ++j)
-        rcols[i].push_back(j < items[i].cap ? col_of(items[i].R_out, j, ng, f32, items[i].m_out)
+        rcols[i].push_back(j < items[i].cap ? col_of(items[i].R_out, j, rld, f32, items[i].m_out)
                                             : col_null());
       GramWork g;
       g.nrows = ng;
@@ -842,6 +851,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
       t.C = coef2 + (size_t)i * 32 * 32;
       t.ldc = items[i].cap;
       t.out = items[i].R_out;
+      t.out_ld = items[i].R_ld > 0 ? items[i].R_ld : t.nrows;
       t.out_f32 = f32;
       t.nout = items[i].cap;
       t.out_mptr = items[i].m_out;
@@ -915,27 +925,28 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   PhaseEvents& P = ph ? *ph : dummy;
 
   const void* LR = w.LR;
+  const long long cld = w.ld > 0 ? w.ld : ng;   // column stride of R, LR, forcing
   char* ld = (char*)scratch(c, "co_fields", (size_t)ng * sf * (1 + np) + (size_t)ng * 8);
   void* dcol = ld;                          // augmented column d (field precision)
   void* Ld = ld + (size_t)ng * sf;          // L_j d, j < np
   double* dtil = (double*)(ld + (size_t)ng * sf * (1 + np));
   if (!LR) {
     P.begin(2);
-    void* lr = scratch(c, "co_LR", (size_t)ng * sf * cap * np);
-    enqueue_applyL_pieces(c, p, w.R, lr, cap, w.m, s);
+    void* lr = scratch(c, "co_LR", (size_t)cld * sf * cap * np);
+    enqueue_applyL_pieces(c, p, w.R, lr, cap, w.m, s, cld);
     LR = lr;
   }
   const void* forcing = w.forcing;
   if (forced && !forcing) {
-    void* fb = scratch(c, "co_force", (size_t)ng * sf * np);
-    enqueue_forcing_fields(c, p, fb, s);
+    void* fb = scratch(c, "co_force", (size_t)cld * sf * np);
+    enqueue_forcing_fields(c, p, fb, s, cld);
     forcing = fb;
   }
 
-  auto Rcol = [&](int j) { return col_of(w.R, j, ng, f32, w.m); };
+  auto Rcol = [&](int j) { return col_of(w.R, j, cld, f32, w.m); };
   // piece jp of L applied to column j
   auto LRcol = [&](int jp, int j) {
-    return col_of((const char*)LR + (size_t)jp * cap * ng * sf, j, ng, f32, w.m);
+    return col_of((const char*)LR + (size_t)jp * cap * cld * sf, j, cld, f32, w.m);
   };
   auto f64col = [&](const double* x) { return ColDesc{x, nullptr, 0, 0}; };
   const int* aug = nullptr;
@@ -962,6 +973,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     t.C = S1;
     t.ldc = 16;
     t.out = dtil;
+    t.out_ld = ng;
     t.out_f32 = 0;
     t.nout = 1;
     t.add = w.u_aug;
@@ -1026,7 +1038,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     ColDesc cd = col_null();
     if (j < w.n_in) cd = f64col(w.u_in[j]);
     else if (forced && j >= 2 && j < 2 + np)
-      cd = col_of(forcing, j - 2, ng, f32, nullptr);
+      cd = col_of(forcing, j - 2, cld, f32, nullptr);
     gb.cols.push_back(cd);
   }
   const int nb = 2 + 2 * np + 1;

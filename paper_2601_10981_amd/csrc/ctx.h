@@ -103,6 +103,7 @@ struct FineWork {
   void* snaps;
   double t0 = 0.0;      // forced flows: start time
   int unforced = 0;     // forced flows: 1 = homogeneous propagator (no f)
+  long long snap_ld = 0;  // snapshot column stride in elements (0: N_g)
 };
 void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
                   const std::string& tag);
@@ -113,9 +114,10 @@ struct PodWork {
   double gamma;
   int cap;
   int force_m;
-  void* R_out;                 // N_g x cap (field precision)
+  void* R_out;                 // cap columns (field precision), R_ld apart
   int* m_out;
   double* lambda_out;          // nullable, >= cols.size()
+  long long R_ld = 0;          // column stride of R_out in elements (0: N_g)
 };
 void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
                  const std::string& tag);
@@ -141,11 +143,13 @@ struct ApplyLWork {
   int ncols;
   const int* mptr;
   int piece = 0;          // forced flows: apply piece `piece` of L(t)
+  long long ld = 0;       // column stride of in and out in elements (0: N_g)
 };
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
 void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
-                           int ncols, const int* mptr, hipStream_t s);
-void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s);
+                           int ncols, const int* mptr, hipStream_t s, long long ld = 0);
+void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s,
+                            long long ld = 0);
 
 // The coarse step of the sweep (eqaug, eq12, eq13, formula4): augment span(R)
 // with u_aug, form the Galerkin matrices of Psi = [R, d] against [Psi, L Psi,
@@ -165,6 +169,7 @@ struct CoarseWork {
   int n_c;
   double t0;              // start time (forced flows)
   const void* forcing;    // forced flows: the pieces' f_j (field precision), nullable
+  long long ld;           // column stride of R, LR and forcing in elements (0: N_g)
   // outputs
   double* lift[2];        // nullable
   double* beta_out;       // nullable, n_in x (cap + 1)

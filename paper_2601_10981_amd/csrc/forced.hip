@@ -54,7 +54,7 @@ __device__ __forceinline__ void rk4_tile_forced(
   PR_GLOBAL T* dst = gptr(d.buf[(nst - 1 - step) % 2]);
   PR_GLOBAL T* snap = nullptr;
   if (d.snaps != nullptr && (step + 1) % d.snap_every == 0)
-    snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * plane * n);
+    snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * d.snap_ld);
   const PR_GLOBAL T* pt = gptr(ptab_of<T>(d.g));
   const int np = d.g.npieces;
   const long long pstride = 9LL * n;

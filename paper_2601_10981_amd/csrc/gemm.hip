@@ -347,7 +347,6 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
       }
   }
   const int mo = s_mo;
-  const long long ng = d.nrows;
   const PR_GLOBAL double* add = d.add ? gptr(d.add) : nullptr;
   const double ad0 = add ? add[r0] : 0.0, ad1 = add ? add[q1] : 0.0;
 #pragma unroll
@@ -360,11 +359,11 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
         y1 += ad1;
       }
       if (d.out_f32) {
-        PR_GLOBAL float* o = gptr((float*)d.out) + (long long)j * ng;
+        PR_GLOBAL float* o = gptr((float*)d.out) + (long long)j * d.out_ld;
         o[r0] = (float)y0;
         if (v1) o[r1] = (float)y1;
       } else {
-        PR_GLOBAL double* o = gptr((double*)d.out) + (long long)j * ng;
+        PR_GLOBAL double* o = gptr((double*)d.out) + (long long)j * d.out_ld;
         o[r0] = y0;
         if (v1) o[r1] = y1;
       }

@@ -48,6 +48,9 @@ struct Plan {
   size_t fixed_bytes, perF, perS;
   int np;          // time-space pieces of the flow (1: steady)
   bool forced;     // forced, time-dependent flow
+  long long ld;    // column stride (elements) of the multi-column blocks:
+                   // snapshots, bases, L applied to bases, forcing fields
+  size_t cs;       // bytes per column of those blocks (ld x field size)
 };
 
 // Start time of parareal subinterval n (state U_n at t_hat_n = (n + 1) DeltaT;
@@ -110,7 +113,9 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
     while (P.dTs / P.n_g * rho_c > kGuard) P.n_g *= 2;
     P.dt_c = P.dTs / P.n_g;
   }
-  const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
+  P.ld = P.ng + kColPad;
+  P.cs = (size_t)P.ld * P.sf;
+  const size_t f8 = (size_t)P.ng * 8, cs = P.cs;
   const size_t Np1 = (size_t)std::max(P.Np, 1);
   // solve-owned memory apart from the waves: two state sets, F_n, two slots
   // of stage-1 bases, u0, small matrices. The fixed-POD mode keeps only the
@@ -122,12 +127,12 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   P.forced = forced_flow(*p);
   P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 +
                   (P.grid ? 0
-                          : (P.fixed ? (size_t)P.n_s * fs + (1 + (size_t)P.np) * o->cap * fs
-                                     : 2 * Np1 * o->cap0 * fs)) +
-                  (P.forced && !P.grid ? (size_t)P.np * fs : 0) + f8 + ((size_t)4 << 20);
-  P.perF = plain ? 0 : (size_t)P.n_s * fs;        // snapshots of one subinterval
+                          : (P.fixed ? (size_t)P.n_s * cs + (1 + (size_t)P.np) * o->cap * cs
+                                     : 2 * Np1 * o->cap0 * cs)) +
+                  (P.forced && !P.grid ? (size_t)P.np * cs : 0) + f8 + ((size_t)4 << 20);
+  P.perF = plain ? 0 : (size_t)P.n_s * cs;        // snapshots of one subinterval
   // stage-2 basis and the pieces of L applied to it
-  P.perS = plain ? 0 : (1 + (size_t)P.np) * o->cap * fs;
+  P.perS = plain ? 0 : (1 + (size_t)P.np) * o->cap * cs;
   return P;
 }
 
@@ -195,8 +200,9 @@ static void choose_waves(Plan& P, size_t avail) {
   P.waveS = ws;
 }
 
-static ColDesc colp(const void* base, int idx, long long ng, bool f32, const int* mptr) {
-  return ColDesc{(const char*)base + (size_t)idx * ng * (f32 ? 4 : 8), mptr, idx, f32 ? 1 : 0};
+// Column idx of a block whose columns are ld elements apart.
+static ColDesc colp(const void* base, int idx, long long ld, bool f32, const int* mptr) {
+  return ColDesc{(const char*)base + (size_t)idx * ld * (f32 ? 4 : 8), mptr, idx, f32 ? 1 : 0};
 }
 static ColDesc colnull() { return ColDesc{nullptr, nullptr, 0, 0}; }
 
@@ -319,12 +325,13 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     }
     S->U[1] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
     S->Fn = (double*)owned_alloc(c, S, Np1 * f8);
-    S->R0 = (P.fixed || P.grid) ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * fs);
+    const size_t cs = P.cs;
+    S->R0 = (P.fixed || P.grid) ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * cs);
     if (!P.grid) {
-      S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * fs);
-      S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * fs);
-      S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * fs);
-      if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * fs);
+      S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * cs);
+      S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * cs);
+      S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * cs);
+      if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * cs);
     }
     const int maxk = P.max_iter;
     const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 144, n_dscal = 8;
@@ -360,7 +367,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     stage_begin(c, s);
     ph.begin(0);
     enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.grid ? 0 : P.dM,
-                              P.grid ? nullptr : S->snaps, 0.0, 0}},
+                              P.grid ? nullptr : S->snaps, 0.0, 0, P.ld}},
                  s, "sol_fine");
     S->fine_updates += (double)P.n_f * ng;
     if (Np > 0 && P.grid) {
@@ -374,11 +381,12 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       ph.begin(1);
       PodWork pw;
       pw.prob = &S->P.prob;
-      for (int j = 0; j < P.n_s; ++j) pw.cols.push_back(colp(S->snaps, j, ng, P.f32, nullptr));
+      for (int j = 0; j < P.n_s; ++j) pw.cols.push_back(colp(S->snaps, j, P.ld, P.f32, nullptr));
       pw.gamma = P.o.gamma1;
       pw.cap = cap;
       pw.force_m = -1;
       pw.R_out = S->Psi;
+      pw.R_ld = P.ld;
       pw.m_out = S->mS;
       pw.lambda_out = nullptr;
       enqueue_pod(c, {pw}, s, "sol_pod");
@@ -386,22 +394,22 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       // the Galerkin products of the k = 0 basis: Psi^T M [Psi, L_j Psi, U_0,
       // f_j] (one L block per time-space piece of a forced flow)
       const int np = P.np, nb = 2 + 2 * np + 1;
-      enqueue_applyL_pieces(c, p, S->Psi, S->LPsi, cap, S->mS, s);
-      if (P.forced) enqueue_forcing_fields(c, p, S->forcing, s);
+      enqueue_applyL_pieces(c, p, S->Psi, S->LPsi, cap, S->mS, s, P.ld);
+      if (P.forced) enqueue_forcing_fields(c, p, S->forcing, s, P.ld);
       GramWork g;
       g.nrows = ng;
       std::vector<ColDesc> a;
-      for (int j = 0; j < 32; ++j) a.push_back(j < cap ? colp(S->Psi, j, ng, P.f32, S->mS) : colnull());
+      for (int j = 0; j < 32; ++j) a.push_back(j < cap ? colp(S->Psi, j, P.ld, P.f32, S->mS) : colnull());
       g.cols = a;
       g.cols.insert(g.cols.end(), a.begin(), a.end());
       for (int jp = 0; jp < np; ++jp)
         for (int j = 0; j < 32; ++j)
-          g.cols.push_back(j < cap ? colp(S->LPsi + (size_t)jp * cap * fs, j, ng, P.f32, S->mS)
+          g.cols.push_back(j < cap ? colp(S->LPsi + (size_t)jp * cap * P.cs, j, P.ld, P.f32, S->mS)
                                    : colnull());
       g.cols.push_back(ColDesc{Ua, nullptr, 0, 0});
       g.cols.push_back(colnull());
       for (int jp = 0; jp < np && P.forced; ++jp)
-        g.cols.push_back(colp(S->forcing, jp, ng, P.f32, nullptr));
+        g.cols.push_back(colp(S->forcing, jp, P.ld, P.f32, nullptr));
       g.cols.resize((2 + nb) * 16, colnull());
       g.out = S->S0;
       g.ld = 16 * nb;
@@ -430,7 +438,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       stage_flush(c, s);
       launch_reduced0(dd, s);
       std::vector<ColDesc> psi;
-      for (int j = 0; j < cap; ++j) psi.push_back(colp(S->Psi, j, ng, P.f32, S->mS));
+      for (int j = 0; j < cap; ++j) psi.push_back(colp(S->Psi, j, P.ld, P.f32, S->mS));
       for (int n = 0; n < Np; ++n)
         enqueue_correct(c, ng, psi, S->betas0 + (size_t)n * 32, nullptr, 0,
                         Ua + (size_t)(n + 1) * ng, nullptr,
@@ -511,7 +519,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       const int n0 = (k - 1) + round * P.waveF;
       if (n0 >= Np) continue;
       const int n1 = std::min(Np, n0 + P.waveF);
-      const size_t fs = (size_t)P.ng * P.sf;
+      const size_t cs = P.cs;
       const double* Uprev = S->U[S->prev];
       for (int n = n0; n < n1; ++n) {
         if (P.fixed || P.grid) {
@@ -524,17 +532,18 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           pw.push_back(none);
           continue;
         }
-        void* sn = S->snaps + (size_t)(n - n0) * P.n_s * fs;
+        void* sn = S->snaps + (size_t)(n - n0) * P.n_s * cs;
         fw.push_back(FineWork{&S->P.prob, P.dt, P.n_f, Uprev + (size_t)n * P.ng,
-                              S->Fn + (size_t)n * P.ng, P.dM, sn, t_hat(P, n), 0});
+                              S->Fn + (size_t)n * P.ng, P.dM, sn, t_hat(P, n), 0, P.ld});
         PodWork w;
         w.prob = &S->P.prob;
-        for (int j = 0; j < P.n_s; ++j) w.cols.push_back(colp(sn, j, P.ng, P.f32, nullptr));
+        for (int j = 0; j < P.n_s; ++j) w.cols.push_back(colp(sn, j, P.ld, P.f32, nullptr));
         w.gamma = P.o.gamma2;
         w.cap = P.o.cap0;
         w.force_m = -1;
         const int slot = k % 2;
-        w.R_out = S->R0 + ((size_t)slot * Np + n) * P.o.cap0 * fs;
+        w.R_out = S->R0 + ((size_t)slot * Np + n) * P.o.cap0 * cs;
+        w.R_ld = P.ld;
         w.m_out = S->m0slot + slot * Np + n;
         w.lambda_out = nullptr;
         pw.push_back(w);
@@ -623,6 +632,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.prob = &S->P.prob;
         w.R = S->Psi;
         w.LR = S->LPsi;
+        w.ld = P.ld;
         w.cap = cap;
         w.m = S->mS;
         w.u_aug = nullptr;
@@ -651,27 +661,28 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.prob = &S->P.prob;
         for (int j = std::max(0, n - P.o.ml); j <= n; ++j) {
           const int slot = std::min(k, j + 1) % 2;
-          const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * fs;
+          const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * P.cs;
           const int* mp = S->m0slot + slot * Np + j;
-          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, ng, P.f32, mp));
+          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
         }
         if (P.o.p >= 1 && k - 1 >= 1) {
           const int slot = (k - 1) % 2;
-          const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * fs;
+          const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * P.cs;
           const int* mp = S->m0slot + slot * Np + n;
-          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, ng, P.f32, mp));
+          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
         }
         w.gamma = P.o.gamma3;
         w.cap = cap;
         w.force_m = -1;
-        w.R_out = S->Psi + (size_t)(n - n0) * cap * fs;
+        w.R_out = S->Psi + (size_t)(n - n0) * cap * P.cs;
+        w.R_ld = P.ld;
         w.m_out = S->mS + (n - n0);
         w.lambda_out = nullptr;
         pw.push_back(w);
         for (int jp = 0; jp < P.np; ++jp)
           aw.push_back(ApplyLWork{&S->P.prob, w.R_out,
-                                  S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * fs, cap,
-                                  w.m_out, jp});
+                                  S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * P.cs, cap,
+                                  w.m_out, jp, P.ld});
       }
       ph.begin(1);
       for (int na = 1; na <= 4; ++na) {
@@ -687,8 +698,9 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       for (int n = n0; n < n1; ++n) {
         CoarseWork w{};
         w.prob = &S->P.prob;
-        w.R = S->Psi + (size_t)(n - n0) * cap * fs;
-        w.LR = S->LPsi + (size_t)(n - n0) * P.np * cap * fs;
+        w.R = S->Psi + (size_t)(n - n0) * cap * P.cs;
+        w.LR = S->LPsi + (size_t)(n - n0) * P.np * cap * P.cs;
+        w.ld = P.ld;
         w.cap = cap;
         w.m = S->mS + (n - n0);
         w.u_aug = Ucur + (size_t)n * ng;

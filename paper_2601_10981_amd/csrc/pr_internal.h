@@ -43,6 +43,13 @@ constexpr double kDropPivot = 1e-8;
 constexpr int kCholQRPasses = 1;
 constexpr double kGuard = 2.5;
 constexpr double kStabRK4 = 2.6;
+// Column stride of the solver's own multi-column blocks (snapshots, bases, L
+// applied to bases): N_g + kColPad elements. With N_g a power of two (128^3,
+// 256^3) unpadded columns start 2^k bytes apart, and the tall-skinny MFMA
+// Grams -- which read 16 columns at one row per instruction -- then hit the
+// same HBM channels (measured: a 64-column 128^3 Gram 385 -> 290 us with the
+// pad). Caller buffers at the C ABI stay contiguous.
+constexpr long long kColPad = 32;
 
 // ----------------------------------------------------------------------------
 // Device pointers read from descriptors are generic; casting them to the
@@ -116,7 +123,8 @@ struct FineDesc {
   Geom g;
   const T* first_src;
   T* buf[2];
-  T* snaps;        // nullptr or N_g x n_s: column j = state after j * snap_every steps
+  T* snaps;        // nullptr or n_s columns: column j = state after j * snap_every steps
+  long long snap_ld;  // elements from one snapshot column to the next (>= N_g)
   int snap_every;
   int n_steps;
   double dt;
@@ -158,8 +166,9 @@ inline int fused_slots(int cfg) {
 template <typename T>
 struct ApplyLDesc {
   Geom g;
-  const T* in;     // ncols columns of N_g
+  const T* in;     // ncols columns of N_g values, ld apart
   T* out;
+  long long ld;    // column stride in elements (>= N_g)
   int ncols;
   const int* mptr;  // valid columns (nullptr = all)
   int tiles_q, tiles_x;
@@ -187,7 +196,8 @@ struct TsmmDesc {
   int nin;
   const double* C;       // nin x ldc, FP64, device
   int ldc;
-  void* out;             // nout columns of N_g
+  void* out;             // nout columns of N_g values, out_ld apart
+  long long out_ld;      // output column stride in elements (>= N_g)
   int out_f32;
   int nout;
   const int* out_mptr;   // columns >= *out_mptr written as zero (nullptr: none)

@@ -96,7 +96,7 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
   PR_GLOBAL T* dst = gptr(d.buf[(nst - 1 - step) % 2]);
   PR_GLOBAL T* snap = nullptr;
   if (d.snaps != nullptr && (step + 1) % d.snap_every == 0)
-    snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * plane * n);
+    snap = gptr(d.snaps + (long long)((step + 1) / d.snap_every) * d.snap_ld);
   const PR_GLOBAL T* tab = gptr(tab_of<T>(d.g));
   const T clap = (T)d.g.c_lap;
   const T e6 = (T)-6 * clap;
@@ -375,9 +375,8 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   if (q >= n * n) return;
   const int j = q / n, k = q - (q / n) * n;
   const int x0 = tx * kChunkX, x1 = min(n, x0 + kChunkX);
-  const long long ng = (long long)n * n * n;
-  const PR_GLOBAL T* in = gptr(d.in) + (long long)col * ng;
-  PR_GLOBAL T* out = gptr(d.out) + (long long)col * ng;
+  const PR_GLOBAL T* in = gptr(d.in) + (long long)col * d.ld;
+  PR_GLOBAL T* out = gptr(d.out) + (long long)col * d.ld;
   const bool valid = (d.mptr == nullptr) || (col < *d.mptr);
   if (!valid) {
     const long long plane = (long long)n * n;
