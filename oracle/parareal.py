@@ -34,6 +34,13 @@ solves the same equation on the coarse n/2 grid (gridcoarse.py); no POD at
 all. The warm-up subinterval and the numbering are kept, so all three modes
 share U^0_0 = F(u0).
 
+Coarse-gap diagnostics (Sec. 4, the dT = delta t experiments; opts.diag): at
+iteration k >= 1 the sweep step from U_n to U_{n+1} (n = k..N'-1) records
+  gap_fine = ||F(U^{k-1}_n) - G_k(P U^{k-1}_n)||_M / ||F(U^{k-1}_n)||_M,
+  gap_ref  = ||U_{n+1} - G_k(P U^k_n)||_M / ||U_{n+1}||_M  (U_{n+1} the serial
+             fine reference, when given),
+with G_k the coarse propagator of that step (adaptive and fixed-POD modes).
+
 Time: subinterval i of [0, T] starts at i DeltaT, so the warm-up solve starts
 at t = 0 and the fine and coarse solves from U_n (n = 0..N'-1) start at
 t_hat_n = (n + 1) DeltaT; fine step j of a solve from t starts at t + j dt.
@@ -70,6 +77,8 @@ class Result:
     n_c: int
     history: List[List[np.ndarray]]  # iterates per k (only with keep_history)
     t_phase: Dict[str, float]
+    gap_fine: Dict[int, List[float]] = dataclasses.field(default_factory=dict)  # k -> n = k..N'-1
+    gap_ref: Dict[int, List[float]] = dataclasses.field(default_factory=dict)
 
 
 def _norm_m(x: np.ndarray, h3: float) -> float:
@@ -145,8 +154,21 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     converged = Np == 0
     k = 0
     fixed = getattr(opts, "mode", 0) == 1
+    diag = bool(getattr(opts, "diag", 0))
+    gap_fine: Dict[int, List[float]] = {}
+    gap_ref: Dict[int, List[float]] = {}
+
+    def record_gaps(kk, nn, g_new, g_old):
+        F = Fk[nn]
+        gap_fine[kk].append(_norm_m(F - g_old, h3) / _norm_m(F, h3))
+        if U_ref is not None:
+            ref = np.asarray(U_ref[nn + 2]).reshape(-1)
+            gap_ref[kk].append(_norm_m(ref - g_new, h3) / _norm_m(ref, h3))
+
     while not converged and k < max_iter:
         k += 1
+        gap_fine[k] = []
+        gap_ref[k] = []
         # (i) fine propagation and stage-1 POD, parallel over n
         Fk: Dict[int, np.ndarray] = {}
         hist[k] = {}
@@ -183,10 +205,12 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
                 t0 = time.perf_counter()
                 b_new = sys0.rk4(sys0.project(U_cur[nn]), t_hat(nn), dT_sub, n_c)
                 b_old = sys0.rk4(sys0.project(U_prev[nn]), t_hat(nn), dT_sub, n_c)
-                g_new = R0 @ b_new if m0 > 0 else 0.0
-                g_old = R0 @ b_old if m0 > 0 else 0.0
+                g_new = R0 @ b_new if m0 > 0 else np.zeros_like(Fk[nn])
+                g_old = R0 @ b_old if m0 > 0 else np.zeros_like(Fk[nn])
                 U_cur.append(g_new + Fk[nn] - g_old)
                 t_phase["G"] += time.perf_counter() - t0
+                if diag:
+                    record_gaps(k, nn, g_new, g_old)
                 continue
             t0 = time.perf_counter()
             blocks = [latest(j) for j in range(nn - opts.ml, nn + 1) if j >= 0]
@@ -205,10 +229,12 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
             t0 = time.perf_counter()
             b_new = sysr.rk4(sysr.project(U_cur[nn]), t_hat(nn), dT_sub, nc)
             b_old = sysr.rk4(sysr.project(U_prev[nn]), t_hat(nn), dT_sub, nc)
-            g_new = Psi @ b_new if Psi.shape[1] else 0.0
-            g_old = Psi @ b_old if Psi.shape[1] else 0.0
+            g_new = Psi @ b_new if Psi.shape[1] else np.zeros_like(Fk[nn])
+            g_old = Psi @ b_old if Psi.shape[1] else np.zeros_like(Fk[nn])
             U_cur.append(g_new + Fk[nn] - g_old)
             t_phase["G"] += time.perf_counter() - t0
+            if diag:
+                record_gaps(k, nn, g_new, g_old)
         # (v) jump
         e = 0.0
         for j in range(1, Np + 1):
@@ -233,7 +259,8 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     U_out = [u0v.copy()] + [u.copy() for u in U_prev]
     return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
                   ranks=ranks, ranks0=ranks0, m0=m0, n_f=n_f, dt=dt, dM=dM,
-                  n_c=n_c, history=history, t_phase=t_phase)
+                  n_c=n_c, history=history, t_phase=t_phase,
+                  gap_fine=gap_fine if diag else {}, gap_ref=gap_ref if diag else {})
 
 
 def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, err_of,

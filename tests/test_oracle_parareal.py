@@ -128,3 +128,44 @@ def test_fixed_pod_invariant_subspace_converges_in_one_iteration():
     r = parareal.solve(prob, opts, u0, U_ref=ref)
     assert r.m0 == 4 and r.errors[0] <= 1e-12
     assert r.iters == 1 and r.jumps[0] <= 1e-12 and r.errors[1] <= 1e-12
+
+
+@pytest.mark.parametrize("ratio", [1, 5])
+def test_coarse_gap_diagnostics_closed_form(ratio):
+    """Coarse-gap diagnostics (Sec. 4, dT = delta t runs) on a single Fourier
+    mode under a uniform flow: span{cos, sin} is invariant under L, so the
+    Galerkin reduction is exact in space and the gap is the time
+    discretisation alone, |P4(dt lam)^n_f - P4(dT lam)^n_c| / |P4(dt lam)^n_f|
+    with lam the FD symbol of the mode; it vanishes for dT = delta t. The
+    reference gap at the first sweep step of iteration k starts from the
+    exact U_k (converged prefix), so it takes the same value."""
+    n, kappa, c = 10, 0.05, (0.6, -0.9, 0.4)
+    prob = W.Problem(n=n, kappa=kappa, flow=W.FLOW_UNIFORM, fp=c)
+    opts = W.PararealOpts(T=0.6, N=4, dt=0.01, cap0=4, cap=4, tol=0.0, coarse_ratio=ratio,
+                          gamma1=1.0, gamma2=1.0, gamma3=1.0, mode=W.MODE_FIXED_POD, diag=1)
+    h = 2 * math.pi / n
+    x = np.arange(n) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    kv = (1, 2, -1)
+    u0 = np.cos(kv[0] * X + kv[1] * Y + kv[2] * Z + 0.3)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref)
+    assert r.m0 == 2
+    lam = (-kappa * sum(4.0 / h ** 2 * math.sin(k * h / 2) ** 2 for k in kv)
+           - 1j * sum(cd * math.sin(k * h) / h for cd, k in zip(c, kv)))
+    p4 = lambda z: 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    dTs = opts.T / opts.N
+    zF = p4(r.dt * lam) ** r.n_f
+    zG = p4(dTs / r.n_c * lam) ** r.n_c
+    expect = abs(zF - zG) / abs(zF)
+    assert r.iters == opts.N - 1
+    for k in range(1, r.iters + 1):
+        assert len(r.gap_fine[k]) == opts.N - 1 - k
+        for g in r.gap_fine[k]:
+            assert abs(g - expect) <= 1e-9 * max(expect, 1e-6) + 1e-13
+        if r.gap_ref[k]:
+            assert abs(r.gap_ref[k][0] - expect) <= 1e-9 * max(expect, 1e-6) + 1e-13
+    if ratio == 1:
+        assert expect <= 1e-13
+    else:
+        assert expect > 1e-9

@@ -75,6 +75,7 @@ class PararealOpts:
     tol: float = 1e-8
     max_iter: int = 0        # 0: N - 1
     mode: int = MODE_ADAPTIVE
+    diag: int = 0            # 1: record the coarse-gap diagnostics (Sec. 4, dT = delta t runs)
 
 
 @dataclasses.dataclass(frozen=True)
