@@ -58,6 +58,9 @@ def parse():
                          "forced-stencil roofline and error per iteration of the three modes")
     ap.add_argument("--paper-N", type=int, default=41,
                     help="subintervals of the --paper-flow runs (DeltaT = 5)")
+    ap.add_argument("--gap", action="store_true",
+                    help="report run of the coarse-gap diagnostics (Sec. 4, dT = delta t) of the "
+                         "adaptive method on the forced flows at 128^3 (own JSON line)")
     return ap.parse_args()
 
 
@@ -449,6 +452,62 @@ def paper_flow_run(args):
     print(json.dumps(out))
 
 
+def gap_run(args):
+    """The paper's dT = delta t experiments (Sec. 4): the coarse step equals
+    the fine one, so the coarse propagator differs from the fine one only by
+    the POD reduction in space. For both forced flows at 128^3 and epsilon in
+    {0.05, 0.01, 0.005} the adaptive method ((m_l, p) = (1, 1)) records per
+    iteration k and subinterval n the gaps
+      ||F(U^{k-1}_n) - G_k(U^{k-1}_n)|| / ||F(U^{k-1}_n)|| and
+      ||U_{n+1} - G_k(U^k_n)|| / ||U_{n+1}||.
+    delta t = 1e-2 (epsilon = 0.05: 5e-3, the explicit RK4 bound), DeltaT = 5,
+    delta_M = 10, h = 0, caps 21 / 31, N = --paper-N // 2 subintervals."""
+    import dataclasses
+    import statistics
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    n, dTs = 128, 5.0
+    N = max(3, args.paper_N // 2)
+    ng = n ** 3
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    free, _ = torch.cuda.mem_get_info()
+    ctx = pr.Context(0, budget_bytes=int(0.85 * free))
+    out = {"metric": "coarse-gap diagnostics of the adaptive method, dT = delta t (Sec. 4)",
+           "n": n, "N": N, "DeltaT": dTs, "max_iter": args.max_iter, "runs": []}
+    for name, flow in (("kolmogorov", W.FLOW_KOLMOGOROV_T), ("abc", W.FLOW_ABC_T)):
+        for eps in (0.05, 0.01, 0.005):
+            dt = 1e-2 if eps < 0.05 else 5e-3
+            n_f = int(round(dTs / dt))
+            opts = W.PararealOpts(T=dTs * N, N=N, dt=dt, dM=n_f // 50, cap0=21, cap=31, ml=1, p=1,
+                                  coarse_ratio=1, tol=1e-10, max_iter=args.max_iter, diag=1)
+            prob = pr.problem(n, eps, flow, (1.0, 1.0, 1.0))
+            U_ref = torch.zeros((N + 1, ng), dtype=torch.float64, device="cuda")
+            for j in range(N):
+                pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=n_f, u_in=U_ref[j],
+                                                u_out=U_ref[j + 1], t0=j * dTs)])
+            u0 = torch.zeros(ng, dtype=torch.float64, device="cuda")
+            log(f"gap run {name} eps={eps}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = pr.pr_parareal_solve(ctx, prob, opts, u0, U_ref=U_ref)
+            el = time.perf_counter() - t0
+            row = {"flow": name, "eps": eps, "dt": dt, "iters": rep.iters, "seconds": round(el, 2),
+                   "err_history": [float("%.3e" % e) for e in rep.err], "gap_fine": {}, "gap_ref": {}}
+            for key, src in (("gap_fine", rep.gap_fine), ("gap_ref", rep.gap_ref)):
+                for k, vals in src.items():
+                    row[key][k] = {"max": float("%.3e" % max(vals)),
+                                   "median": float("%.3e" % statistics.median(vals))}
+            log(f"  iters {rep.iters}; max fine gap per k "
+                f"{[row['gap_fine'][k]['max'] for k in sorted(row['gap_fine'])]}")
+            out["runs"].append(row)
+            del U_ref
+            torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -462,6 +521,8 @@ def main():
         return study_run(args)
     if args.paper_flow:
         return paper_flow_run(args)
+    if args.gap:
+        return gap_run(args)
     import numpy as np
     import torch
     import paper_2601_10981_amd as pr

@@ -271,6 +271,14 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *                 n_g = n_c steps doubled while DeltaT / n_g * rho_c > 2.5
  *                 (rho_c the bound above on the coarse grid), linear
  *                 interpolation back; no POD
+ *   diag          1: record the coarse-gap diagnostics of Sec. 4 (its dT =
+ *                 delta t runs; set coarse_ratio = 1 for those): at iteration
+ *                 k >= 1 the sweep step from U_n to U_{n+1} records
+ *                 ||F(U^{k-1}_n) - G_k(P U^{k-1}_n)||_M / ||F(U^{k-1}_n)||_M
+ *                 and, with U_ref, ||U_{n+1} - G_k(P U^k_n)||_M /
+ *                 ||U_{n+1}||_M (report gap_fine / gap_ref). POD modes only
+ *                 (PR_EINVAL with PR_MODE_COARSE_GRID); costs two extra field
+ *                 passes per sweep step
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
@@ -286,6 +294,7 @@ typedef struct {
   double tol;
   int max_iter;
   int mode;        /* PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD or PR_MODE_COARSE_GRID */
+  int diag;        /* 1: coarse-gap diagnostics (see above)                   */
   const double* U_ref;
 } pr_parareal_opts;
 
@@ -302,6 +311,11 @@ typedef struct {
   double t_phase[5];  /* seconds in F, C (POD), U (reduced ops), A, G      */
   double fine_updates;/* grid-point RK4 updates performed                  */
   double seconds;     /* wall time of the solve                            */
+  double* gap_fine;   /* [(max_iter + 1) * n_sub]: row k, column n: the
+                         fine-vs-coarse gap of the step from U_n (opts.diag);
+                         -1 where no such step ran                          */
+  double* gap_ref;    /* the same layout: reference-vs-coarse gap (needs
+                         U_ref); -1 where not recorded                      */
 } pr_report;
 
 pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,

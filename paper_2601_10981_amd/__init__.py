@@ -284,6 +284,7 @@ def opts_struct(o, U_ref=None) -> L.pr_parareal_opts:
     s.tol = float(o.tol)
     s.max_iter = int(getattr(o, "max_iter", 0))
     s.mode = int(getattr(o, "mode", 0))
+    s.diag = int(getattr(o, "diag", 0))
     s.U_ref = _ptr(U_ref)
     return s
 
@@ -306,6 +307,9 @@ class Report:
     t_phase: dict
     fine_updates: float
     seconds: float
+    # coarse-gap diagnostics (opts.diag): k -> values for n = k..N-2
+    gap_fine: dict = dataclasses.field(default_factory=dict)
+    gap_ref: dict = dataclasses.field(default_factory=dict)
 
 
 class _ReportBuffers:
@@ -321,11 +325,15 @@ class _ReportBuffers:
         self.err = (ctypes.c_double * cap)()
         self.t_iter = (ctypes.c_double * cap)()
         self.ranks = (ctypes.c_int * (cap * self.n_sub))()
+        self.gap_fine = (ctypes.c_double * (cap * self.n_sub))()
+        self.gap_ref = (ctypes.c_double * (cap * self.n_sub))()
         self.rep = L.pr_report()
         self.rep.jump = self.jump
         self.rep.err = self.err
         self.rep.t_iter = self.t_iter
         self.rep.ranks = self.ranks
+        self.rep.gap_fine = self.gap_fine
+        self.rep.gap_ref = self.gap_ref
 
     def report(self, st: int, has_ref: bool) -> "Report":
         rep, k, n_sub, N = self.rep, self.rep.iters, self.n_sub, self.N
@@ -337,7 +345,16 @@ class _ReportBuffers:
                       ranks=[[self.ranks[kk * n_sub + n] for n in range(kk, N - 1)]
                              for kk in range(1, k + 1)],
                       t_phase=dict(zip("FCUAG", list(rep.t_phase))),
-                      fine_updates=rep.fine_updates, seconds=rep.seconds)
+                      fine_updates=rep.fine_updates, seconds=rep.seconds,
+                      gap_fine=self._gaps(self.gap_fine, k), gap_ref=self._gaps(self.gap_ref, k))
+
+    def _gaps(self, arr, k):
+        out = {}
+        for kk in range(1, k + 1):
+            row = [arr[kk * self.n_sub + n] for n in range(kk, self.N - 1)]
+            if row and all(v >= 0 for v in row):
+                out[kk] = row
+        return out
 
 
 def pr_parareal_solve(ctx: Context, prob: L.pr_grid_problem, opts, u0, U_out=None,

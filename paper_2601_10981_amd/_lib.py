@@ -49,7 +49,7 @@ class pr_parareal_opts(Structure):
                 ("gamma1", c_double), ("gamma2", c_double), ("gamma3", c_double),
                 ("cap0", c_int), ("cap", c_int), ("ml", c_int), ("p", c_int),
                 ("coarse_ratio", c_int), ("tol", c_double), ("max_iter", c_int),
-                ("mode", c_int), ("U_ref", c_void_p)]
+                ("mode", c_int), ("diag", c_int), ("U_ref", c_void_p)]
 
 
 class pr_report(Structure):
@@ -57,7 +57,8 @@ class pr_report(Structure):
                 ("n_s", c_int), ("n_c", c_int), ("n_sub", c_int), ("m0", c_int),
                 ("jump", POINTER(c_double)), ("err", POINTER(c_double)),
                 ("t_iter", POINTER(c_double)), ("ranks", POINTER(c_int)),
-                ("t_phase", c_double * 5), ("fine_updates", c_double), ("seconds", c_double)]
+                ("t_phase", c_double * 5), ("fine_updates", c_double), ("seconds", c_double),
+                ("gap_fine", POINTER(c_double)), ("gap_ref", POINTER(c_double))]
 
 
 class pr_plan_info(Structure):

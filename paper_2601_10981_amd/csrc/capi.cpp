@@ -1074,6 +1074,18 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   stage_flush(c, s);
   launch_reduced(rdd, 1, s);
   std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
+  if (w.diag_norms && w.n_in == 2 && w.fine) {
+    // coarse-gap diagnostics: F(U_old) - G(U_old) and U_ref - G(U_new) with
+    // their norms (Sec. 4, dT = delta t runs)
+    double* nbeta = (double*)(sm + 57344);   // 2 x (cap + 1)
+    launch_negate(beta, nbeta, 2 * (cap + 1), s);
+    double* dout = (double*)scratch(c, "co_diag", (size_t)ng * 8);
+    enqueue_correct(c, ng, psi_cols, nbeta + (cap + 1), w.fine, 0, dout, nullptr, w.fine,
+                    w.diag_norms, h3, s, "co");
+    if (w.diag_ref)
+      enqueue_correct(c, ng, psi_cols, nbeta, w.diag_ref, 0, dout, nullptr, w.diag_ref,
+                      w.diag_norms + 4, h3, s, "co");
+  }
   if (w.corr_out)
     enqueue_correct(c, ng, psi_cols, coef, w.fine, 0, w.corr_out, w.prev, w.ref,
                     w.norms4 ? w.norms4 : nrm, h3, s, "co");

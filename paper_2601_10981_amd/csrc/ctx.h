@@ -180,6 +180,11 @@ struct CoarseWork {
   const double* prev;
   const double* ref;
   double* norms4;         // 4 doubles (|U-prev|^2, |U|^2, |U-ref|^2, |ref|^2)
+  // coarse-gap diagnostics (nullable): diag_norms[0..3] = the norms4 of
+  // fine - Psi beta_1 against fine, [4..7] those of diag_ref - Psi beta_0
+  // against diag_ref (diag_ref nullable)
+  double* diag_norms;
+  const double* diag_ref;
 };
 struct PhaseEvents;
 void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* ph);

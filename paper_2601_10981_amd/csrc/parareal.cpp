@@ -48,6 +48,7 @@ struct Plan {
   size_t fixed_bytes, perF, perS;
   int np;          // time-space pieces of the flow (1: steady)
   bool forced;     // forced, time-dependent flow
+  bool diag;       // coarse-gap diagnostics recorded per (k, n)
   long long ld;    // column stride (elements) of the multi-column blocks:
                    // snapshots, bases, L applied to bases, forcing fields
   size_t cs;       // bytes per column of those blocks (ld x field size)
@@ -77,6 +78,8 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
            "unknown mode");
   P.fixed = o->mode == PR_MODE_FIXED_POD;
   P.grid = o->mode == PR_MODE_COARSE_GRID;
+  P.diag = o->diag != 0;
+  PR_CHECK(!(P.diag && P.grid), "coarse-gap diagnostics need a POD coarse propagator");
   if (P.grid) PR_CHECK(p->n % 2 == 0 && p->n / 2 >= 4, "the coarse grid needs an even n >= 8");
   if (o->mode == PR_MODE_ADAPTIVE) {
     PR_CHECK(o->ml >= 0 && o->p >= 0 && o->p <= 1, "need m_l >= 0 and p in {0, 1}");
@@ -129,7 +132,8 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
                   (P.grid ? 0
                           : (P.fixed ? (size_t)P.n_s * cs + (1 + (size_t)P.np) * o->cap * cs
                                      : 2 * Np1 * o->cap0 * cs)) +
-                  (P.forced && !P.grid ? (size_t)P.np * cs : 0) + f8 + ((size_t)4 << 20);
+                  (P.forced && !P.grid ? (size_t)P.np * cs : 0) + f8 + ((size_t)4 << 20) +
+                  (P.diag ? (size_t)(P.max_iter + 1) * Np1 * 8 * 8 : 0);
   P.perF = plain ? 0 : (size_t)P.n_s * cs;        // snapshots of one subinterval
   // stage-2 basis and the pieces of L applied to it
   P.perS = plain ? 0 : (1 + (size_t)P.np) * o->cap * cs;
@@ -177,7 +181,8 @@ static size_t shared_scratch_bytes(const Plan& P) {
   return fine_scratch_item(P.ng, P.f32) * (size_t)std::max(P.waveF, 1) +
          pod_scratch_item(P.ng) * (size_t)std::max({P.waveF, P.waveS, 1}) +
          (1 + (size_t)P.np) * fs + f8 + (size_t)P.o.cap * fs +
-         nch * std::max<size_t>(10, gal) * 256 * 8 + grid + ((size_t)16 << 20);
+         nch * std::max<size_t>(10, gal) * 256 * 8 + grid + (P.diag ? f8 : 0) +
+         ((size_t)16 << 20);
 }
 
 static void choose_waves(Plan& P, size_t avail) {
@@ -221,6 +226,7 @@ struct pr_solve {
   char* Psi = nullptr;
   char* LPsi = nullptr;     // per wave slot: np blocks of cap columns (L_j Psi)
   char* forcing = nullptr;  // forced flows: f_j fields of the np pieces
+  double* gaps = nullptr;   // diag: (max_iter + 1) x N' x 8 norms of the coarse gaps
   double *norms = nullptr, *betas0 = nullptr, *S0 = nullptr, *dscal = nullptr;
   int *m0slot = nullptr, *mS = nullptr, *misc = nullptr, *ranks = nullptr;
   double* host = nullptr;  // pinned: e_k, err_k
@@ -333,6 +339,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * cs);
       if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * cs);
     }
+    if (P.diag) S->gaps = (double*)owned_alloc(c, S, (size_t)(P.max_iter + 1) * Np1 * 8 * 8);
     const int maxk = P.max_iter;
     const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 144, n_dscal = 8;
     const size_t n_dbl = n_norms + n_betas + n_S0 + n_dscal;
@@ -643,6 +650,10 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.n_c = P.n_c;
         w.t0 = t_hat(P, n);
         w.forcing = S->forcing;
+        if (P.diag) {
+          w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
+          w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+        }
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
         w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;
@@ -711,6 +722,10 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.n_c = P.n_c;
         w.t0 = t_hat(P, n);
         w.forcing = S->forcing;
+        if (P.diag) {
+          w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
+          w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+        }
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
         w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;
@@ -789,6 +804,27 @@ static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* 
                             hipMemcpyDeviceToHost, s));
     for (int i = 0; i < 5; ++i) rep->t_phase[i] = S->t_phase[i];
     rep->fine_updates = S->fine_updates;
+    if (rep->gap_fine || rep->gap_ref) {
+      // coarse-gap diagnostics: sqrt(|F - G|^2 / |F|^2) and sqrt(|U_ref - G|^2 /
+      // |U_ref|^2) per recorded sweep step, -1 elsewhere
+      std::vector<double> g;
+      if (P.diag && S->k > 0 && Np > 0) {
+        g.resize((size_t)(S->k + 1) * Np * 8);
+        PR_HIP(hipMemcpyAsync(g.data(), S->gaps, g.size() * 8, hipMemcpyDeviceToHost, s));
+        PR_HIP(hipStreamSynchronize(s));
+      }
+      for (int kk = 0; kk <= P.max_iter; ++kk)
+        for (int n = 0; n < Np; ++n) {
+          double gf = -1.0, gr = -1.0;
+          if (!g.empty() && kk >= 1 && kk <= S->k && n >= kk) {
+            const double* a = &g[((size_t)kk * Np + n) * 8];
+            if (a[3] > 0) gf = std::sqrt(a[1] / a[3]);
+            if (S->U_ref && a[7] > 0) gr = std::sqrt(a[5] / a[7]);
+          }
+          if (rep->gap_fine) rep->gap_fine[(size_t)kk * Np + n] = gf;
+          if (rep->gap_ref) rep->gap_ref[(size_t)kk * Np + n] = gr;
+        }
+    }
   }
   PR_HIP(hipStreamSynchronize(s));
   if (rep) rep->seconds = since(S);

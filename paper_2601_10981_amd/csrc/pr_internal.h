@@ -337,6 +337,8 @@ struct AugDesc {
   int* m_aug;          // m + flag
 };
 void launch_aug_decide(const AugDesc* d, int nitems, hipStream_t s);
+// out[i] = -in[i], i < n (one small vector, n <= 256).
+void launch_negate(const double* in, double* out, int n, hipStream_t s);
 
 // Partial-sum reduction of jump norms: per item sums partial (nwg x 4) in
 // fixed order into out (4 doubles, times h^3).

@@ -531,6 +531,17 @@ __global__ void k_aug_decide(const AugDesc* __restrict__ descs) {
   if (d.m_aug) *d.m_aug = *d.m + flag;
 }
 
+__global__ void k_negate(const double* __restrict__ in, double* __restrict__ out, int n) {
+  if ((int)threadIdx.x < n) out[threadIdx.x] = -in[threadIdx.x];
+}
+
+void launch_negate(const double* in, double* out, int n, hipStream_t s) {
+  if (n <= 0) return;
+  PR_CHECK(n <= 256, "negate: at most 256 values");
+  hipLaunchKernelGGL(k_negate, dim3(1), dim3(256), 0, s, in, out, n);
+  PR_HIP(hipGetLastError());
+}
+
 void launch_aug_decide(const AugDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
   hipLaunchKernelGGL(k_aug_decide, dim3(nd), dim3(64), 0, s, d);

@@ -238,3 +238,64 @@ def test_coarse_grid_mode_matches_oracle(ctx, prec):
                                                           fp=(1.0, 1.0, 1.0))),
                              opts, to_dev(W.blob_field(6, 1)))
     assert e.value.name == "PR_EINVAL"
+
+
+@pytest.mark.parametrize("mode", [W.MODE_ADAPTIVE, W.MODE_FIXED_POD], ids=["adaptive", "fixed"])
+def test_coarse_gap_diagnostics_match_oracle(ctx, mode):
+    """The coarse-gap diagnostics of Sec. 4 (dT = delta t: coarse_ratio 1)
+    against the oracle's, step by step; the gaps are relative differences
+    of iterates that agree to the round-off envelope, so they agree to
+    about envelope / gap."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    opts = W.PararealOpts(**{**opts.__dict__, "mode": mode, "diag": 1, "coarse_ratio": 1,
+                             "max_iter": 3})
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    oref = parareal.reference(prob, opts, u0)
+    ores = parareal.solve(prob, opts, u0, U_ref=oref)
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.iters == 3
+    for k in range(1, 4):
+        say(f"gaps k={k} mode={mode}: gpu {rep.gap_fine.get(k)} oracle {ores.gap_fine[k]}")
+        for name, g, o in (("fine", rep.gap_fine, ores.gap_fine), ("ref", rep.gap_ref, ores.gap_ref)):
+            assert len(g[k]) == len(o[k]) == opts.N - 1 - k, (name, k)
+            for a, b in zip(g[k], o[k]):
+                assert abs(a - b) <= 1e-5 * b + 1e-9, (name, k, a, b)
+    # without a reference only the fine-vs-coarse gap is recorded
+    _, rep2 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    assert rep2.gap_ref == {} and rep2.gap_fine[1] == rep.gap_fine[1]
+
+
+def test_coarse_gap_diagnostics_closed_form(ctx):
+    """A single Fourier mode under a uniform flow: the gap is the time
+    discretisation alone, |P4(dt lam)^n_f - P4(dT lam)^n_c| / |P4(dt lam)^n_f|."""
+    import paper_2601_10981_amd as pr
+    n, kappa, c = 10, 0.05, (0.6, -0.9, 0.4)
+    prob = W.Problem(n=n, kappa=kappa, flow=W.FLOW_UNIFORM, fp=c)
+    opts = W.PararealOpts(T=0.6, N=4, dt=0.01, cap0=4, cap=4, tol=0.0, coarse_ratio=5,
+                          gamma1=1.0, gamma2=1.0, gamma3=1.0, mode=W.MODE_FIXED_POD, diag=1)
+    h = 2 * math.pi / n
+    x = np.arange(n) * h
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    kv = (1, 2, -1)
+    u0 = np.cos(kv[0] * X + kv[1] * Y + kv[2] * Z + 0.3)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.m0 == 2
+    lam = (-kappa * sum(4.0 / h ** 2 * math.sin(k * h / 2) ** 2 for k in kv)
+           - 1j * sum(cd * math.sin(k * h) / h for cd, k in zip(c, kv)))
+    p4 = lambda z: 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    zF = p4(opts.T / opts.N / rep.n_f * lam) ** rep.n_f
+    zG = p4(opts.T / opts.N / rep.n_c * lam) ** rep.n_c
+    expect = abs(zF - zG) / abs(zF)
+    say(f"closed-form gap {expect:.6e}; gpu {rep.gap_fine}")
+    for k, row in rep.gap_fine.items():
+        for g in row:
+            assert abs(g - expect) <= 1e-6 * expect
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_parareal_solve(ctx, p, W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_COARSE_GRID}),
+                             to_dev(u0))
+    assert e.value.name == "PR_EINVAL"
