@@ -133,3 +133,44 @@ def test_smallest_grid_and_empty_batches(ctx):
     pr.pr_pod_build(ctx, [])
     pr.pr_coarse_propagate(ctx, [])
     assert pr.pr_solve_step_batch(ctx, []) == []
+
+
+def test_forced_fine_full_size_paper_kolmogorov128(ctx):
+    """The forced stencil at 128^3 in the launch shape the paper-flow bench
+    times (40 fields, start times 5 (i + 1), delta t = 1e-2, kappa = 0.01):
+    oracle parity after two steps, then over a whole 500-step subinterval
+    the properties that hold at any size -- the grid sum is conserved (the
+    Laplacian, the advection by a velocity whose components do not depend on
+    their own coordinate, and the forcing, full periods of sin and cos, all
+    sum to zero over the periodic grid) -- and batch invariance."""
+    import torch
+    import paper_2601_10981_amd as pr
+    n, B, dt, kappa = 128, 40, 1e-2, 0.01
+    prob = W.Problem(n=n, kappa=kappa, flow=W.FLOW_KOLMOGOROV_T, fp=(1.0, 1.0, 1.0))
+    p = pr.problem_of(prob)
+    fields = [W.fourier_field(n, 11 + i, n_modes=8, kmax=4.0) for i in (0, B - 1)]
+    uin = torch.stack([to_dev(fields[0] if i < B - 1 else fields[1]) * (1.0 + 0.01 * i)
+                       for i in range(B)])
+    out = torch.empty_like(uin)
+    items = [dict(prob=p, dt=dt, n_steps=2, u_in=uin[i], u_out=out[i], t0=5.0 * (i + 1))
+             for i in range(B)]
+    say("forced fine 128^3 x40, 2 steps")
+    pr.pr_fine_propagate(ctx, items)
+    torch.cuda.synchronize()
+    op = fd.Operator.of(prob)
+    for i in (0, B - 1):
+        ref, _ = fd.fine_propagate(op, to_np(uin[i]).reshape(n, n, n), dt, 2, t0=5.0 * (i + 1))
+        assert rel_l2(to_np(out[i]), ref) <= 1e-12, i
+    say("forced fine 128^3 x40, 500 steps")
+    for it in items:
+        it["n_steps"] = 500
+    pr.pr_fine_propagate(ctx, items)
+    torch.cuda.synchronize()
+    s0, s1 = uin.sum(dim=1).cpu().numpy(), out.sum(dim=1).cpu().numpy()
+    a0 = uin.abs().sum(dim=1).cpu().numpy()
+    assert np.all(np.abs(s1 - s0) <= 1e-10 * a0), np.max(np.abs(s1 - s0) / a0)
+    one = torch.empty_like(uin[7])
+    pr.pr_fine_propagate(ctx, [dict(prob=p, dt=dt, n_steps=500, u_in=uin[7], u_out=one,
+                                    t0=5.0 * 8)])
+    torch.cuda.synchronize()
+    assert torch.equal(one, out[7])

@@ -210,3 +210,15 @@ def test_forced_reference_differs_from_unforced():
     opts = W.PararealOpts(T=0.4, N=4, dt=0.01)
     ref = parareal.reference(prob, opts, np.zeros((8, 8, 8)))
     assert np.max(np.abs(ref[-1])) > 0.1
+
+
+@pytest.mark.parametrize("flow", FLOWS)
+def test_grid_sum_conserved(flow):
+    """Sum over the periodic grid is conserved: the Laplacian and the
+    advection (each velocity component independent of its own coordinate)
+    sum to zero, and so does the forcing (full periods of sin and cos)."""
+    op = fd.Operator(16, 0.01, flow, (1.0, 1.0, 1.0))
+    u = W.fourier_field(16, 3, n_modes=6, kmax=3.0) + 0.3
+    v, _ = fd.fine_propagate(op, u, 0.01, 50, t0=7.0)
+    assert abs(v.sum() - u.sum()) <= 1e-13 * np.abs(u).sum()
+    assert np.max(np.abs(v - u)) > 1e-3      # the field did change
