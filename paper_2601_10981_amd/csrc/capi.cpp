@@ -809,7 +809,9 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   }
   TsmmDesc* tdd = stage_push(c, td);
   stage_flush(c, s);
-  launch_tsmm(tdd, nitems, wg, s);
+  int max_cap = 1;
+  for (auto& it : items) max_cap = std::max(max_cap, it.cap);
+  launch_tsmm(tdd, nitems, wg, max_cap, s);
 
   // 5. CholQR in the M inner product (FP64 MFMA Gram, FP64 Cholesky). The
   // modes enter with kappa(R) ~ 1 + eps lambda_1 / lambda_m <= 1 + 1e-3, so
@@ -862,7 +864,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
     }
     TsmmDesc* t2d = stage_push(c, t2);
     stage_flush(c, s);
-    launch_tsmm(t2d, nitems, wg, s);
+    launch_tsmm(t2d, nitems, wg, max_cap, s);
   }
 }
 
@@ -981,7 +983,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     t.wg_begin = 0;
     TsmmDesc* td = stage_push1(c, t);
     stage_flush(c, s);
-    launch_tsmm(td, 1, tsmm_wgs(ng), s);
+    launch_tsmm(td, 1, tsmm_wgs(ng), 1, s);
     // second Gram-Schmidt pass: c2 = R^T M d~, d~ -= R c2
     GramWork g2 = g1;
     for (int j = cap; j < 32; ++j) g2.cols[j] = col_null();
@@ -994,7 +996,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     t2.add = dtil;
     TsmmDesc* td2 = stage_push1(c, t2);
     stage_flush(c, s);
-    launch_tsmm(td2, 1, tsmm_wgs(ng), s);
+    launch_tsmm(td2, 1, tsmm_wgs(ng), 1, s);
     // |d~|^2, |u|^2
     GramWork g3;
     g3.nrows = ng;

@@ -298,11 +298,15 @@ constexpr int kTsmmMaxOut = 32;
 constexpr int kTsmmMaxIn = 64;
 constexpr int kTsmmRowsPerWg = 512;
 
+// MAXOUT bounds nout of every item (the accumulators held per thread): a
+// narrow product (the sweep's projection residual has one output) then runs
+// at far higher occupancy, which is what hides this kernel's memory latency.
+template <int MAXOUT>
 __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs, int nd) {
   __shared__ const void* sp[kTsmmMaxIn];
   __shared__ int sf[kTsmmMaxIn];
   __shared__ int sv[kTsmmMaxIn];
-  __shared__ double sC[kTsmmMaxIn * kTsmmMaxOut];
+  __shared__ double sC[kTsmmMaxIn * MAXOUT];
   __shared__ int s_mo;
   const long long w = blockIdx.x;
   const int f = find_wg(descs, nd, w);
@@ -323,24 +327,42 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
   const bool v0 = r0 < d.nrows, v1 = r1 < d.nrows;
   if (!v0) return;
   const long long q1 = v1 ? r1 : r0;
-  double a0[kTsmmMaxOut], a1[kTsmmMaxOut];
+  double a0[MAXOUT], a1[MAXOUT];
 #pragma unroll
-  for (int j = 0; j < kTsmmMaxOut; ++j) a0[j] = a1[j] = 0.0;
-  for (int c = 0; c < nin; ++c) {
-    if (!sv[c]) continue;
-    double x0, x1;
-    if (sf[c]) {
-      const PR_GLOBAL float* p = gptr((const float*)sp[c]);
-      x0 = p[r0];
-      x1 = p[q1];
-    } else {
-      const PR_GLOBAL double* p = gptr((const double*)sp[c]);
-      x0 = p[r0];
-      x1 = p[q1];
+  for (int j = 0; j < MAXOUT; ++j) a0[j] = a1[j] = 0.0;
+  // wide outputs (few waves resident): four input columns per round, their
+  // loads issued together before the multiply-adds (an invalid column reads
+  // as zero, leaving every sum unchanged), so a wave waits for memory once
+  // per round; narrow ones already hide the latency with occupancy
+  auto ld = [&](int c, long long r) -> double {
+    if (!sv[c]) return 0.0;
+    if (sf[c]) return (double)gptr((const float*)sp[c])[r];
+    return gptr((const double*)sp[c])[r];
+  };
+  int c = 0;
+  for (; MAXOUT > 8 && c + 4 <= nin; c += 4) {
+    double x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      x0[u] = ld(c + u, r0);
+      x1[u] = ld(c + u, q1);
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double* Cr = sC + (c + u) * nout;
+#pragma unroll
+      for (int j = 0; j < MAXOUT; ++j)
+        if (j < nout) {
+          a0[j] += x0[u] * Cr[j];
+          a1[j] += x1[u] * Cr[j];
+        }
+    }
+  }
+  for (; c < nin; ++c) {
+    const double x0 = ld(c, r0), x1 = ld(c, q1);
     const double* Cr = sC + c * nout;
 #pragma unroll
-    for (int j = 0; j < kTsmmMaxOut; ++j)
+    for (int j = 0; j < MAXOUT; ++j)
       if (j < nout) {
         a0[j] += x0 * Cr[j];
         a1[j] += x1 * Cr[j];
@@ -350,7 +372,7 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
   const PR_GLOBAL double* add = d.add ? gptr(d.add) : nullptr;
   const double ad0 = add ? add[r0] : 0.0, ad1 = add ? add[q1] : 0.0;
 #pragma unroll
-  for (int j = 0; j < kTsmmMaxOut; ++j) {
+  for (int j = 0; j < MAXOUT; ++j) {
     if (j < nout) {
       double y0 = (j < mo) ? d.alpha * a0[j] : 0.0;
       double y1 = (j < mo) ? d.alpha * a1[j] : 0.0;
@@ -371,9 +393,15 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
   }
 }
 
-void launch_tsmm(const TsmmDesc* d, int nd, long long total_wg, hipStream_t s) {
+void launch_tsmm(const TsmmDesc* d, int nd, long long total_wg, int max_nout, hipStream_t s) {
   if (total_wg <= 0) return;
-  hipLaunchKernelGGL(k_tsmm, dim3((unsigned)total_wg), dim3(256), 0, s, d, nd);
+  PR_CHECK(max_nout >= 1 && max_nout <= kTsmmMaxOut, "tsmm: 1..32 outputs");
+  const dim3 g((unsigned)total_wg), b(256);
+  if (max_nout <= 1) hipLaunchKernelGGL(k_tsmm<1>, g, b, 0, s, d, nd);
+  else if (max_nout <= 8) hipLaunchKernelGGL(k_tsmm<8>, g, b, 0, s, d, nd);
+  else if (max_nout <= 16) hipLaunchKernelGGL(k_tsmm<16>, g, b, 0, s, d, nd);
+  else if (max_nout <= 24) hipLaunchKernelGGL(k_tsmm<24>, g, b, 0, s, d, nd);
+  else hipLaunchKernelGGL(k_tsmm<32>, g, b, 0, s, d, nd);
   PR_HIP(hipGetLastError());
 }
 

@@ -253,7 +253,8 @@ void launch_gemm_tn(const GemmDesc* d, int nitems, long long total_wg, int na, i
                     bool f32, hipStream_t s);
 void launch_gemm_reduce(const GemmDesc* d, int nitems, int na, int nb, hipStream_t s);
 
-void launch_tsmm(const TsmmDesc* d, int nitems, long long total_wg, hipStream_t s);
+// max_nout: the largest nout of the items (selects the accumulator count).
+void launch_tsmm(const TsmmDesc* d, int nitems, long long total_wg, int max_nout, hipStream_t s);
 void launch_correct(const CorrectDesc* d, int nitems, long long total_wg, hipStream_t s);
 
 // Small dense FP64 kernels (one workgroup per item).
