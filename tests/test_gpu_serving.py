@@ -1,8 +1,9 @@
 """Incremental solves (pr_solve_begin / pr_solve_step_batch / pr_solve_end):
 a solve advanced inside a mixed batch gives bitwise the iterates it gives
 alone through pr_parareal_solve, whatever the batch holds (other grid sizes,
-precisions and subinterval counts); admission under a budget; finished
-handles are left alone by later steps."""
+precisions, subinterval counts, modes, and steady or forced time-dependent
+flows, whose fine solves then run as two launch groups); admission under a
+budget; finished handles are left alone by later steps."""
 import numpy as np
 import pytest
 
@@ -29,6 +30,9 @@ CASES = [
           mode=W.MODE_FIXED_POD),
     _case(16, 6, W.PREC_MIXED, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.15, 14, tol=1e-7,
           mode=W.MODE_COARSE_GRID),
+    _case(12, 6, W.PREC_F64, W.FLOW_KOLMOGOROV_T, (1.0, 1.0, 1.0), 0.1, 15),
+    _case(16, 7, W.PREC_MIXED, W.FLOW_ABC_T, (1.0, 1.0, 1.0), 0.1, 16, tol=1e-7,
+          mode=W.MODE_FIXED_POD),
 ]
 
 
@@ -41,7 +45,8 @@ def _gpu_serial(ctx, p, opts, u0):
     out = torch.empty((opts.N + 1, ng), dtype=torch.float64, device="cuda")
     out[0].copy_(to_dev(u0))
     for j in range(opts.N):
-        pr.pr_fine_propagate(ctx, [dict(prob=p, dt=dt, n_steps=n_f, u_in=out[j], u_out=out[j + 1])])
+        pr.pr_fine_propagate(ctx, [dict(prob=p, dt=dt, n_steps=n_f, u_in=out[j], u_out=out[j + 1],
+                                        t0=j * opts.T / opts.N)])
     torch.cuda.synchronize()
     return out
 
