@@ -650,6 +650,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
       a.ncols = w.ncols;
       a.mptr = w.mptr;
+      a.skip_tail = w.skip_tail;
       a.tiles_q = tiles_q(w.prob->n);
       a.tiles_x = tiles_x(w.prob->n);
       a.tile_begin = tiles;
@@ -669,6 +670,7 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
       a.ncols = w.ncols;
       a.mptr = w.mptr;
+      a.skip_tail = w.skip_tail;
       a.tiles_q = tiles_q(w.prob->n);
       a.tiles_x = tiles_x(w.prob->n);
       a.tile_begin = tiles;
@@ -804,6 +806,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
     t.add = nullptr;
     t.alpha = 1.0;
     t.wg_begin = wg;
+    t.skip_tail = items[i].skip_tail;
     wg += tsmm_wgs(t.nrows);
     td.push_back(t);
   }
@@ -859,6 +862,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
       t.out_mptr = items[i].m_out;
       t.alpha = 1.0;
       t.wg_begin = wg;
+      t.skip_tail = items[i].skip_tail;
       wg += tsmm_wgs(t.nrows);
       t2.push_back(t);
     }
@@ -954,60 +958,37 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   const int* aug = nullptr;
   if (w.u_aug) {
     P.begin(3);
-    // c1 = R^T M u, |u|^2
-    GramWork g1;
-    g1.nrows = ng;
-    for (int j = 0; j < 32; ++j)
-      g1.cols.push_back(j < cap ? Rcol(j) : (j == cap ? f64col(w.u_aug) : col_null()));
-    g1.cols.push_back(f64col(w.u_aug));
-    g1.cols.resize(48, col_null());
-    g1.out = S1;
-    g1.ld = 16;
-    g1.scale = h3;
-    enqueue_gram(c, {g1}, 2, 1, false, s, "co_g");
-    // d~ = u - R c1
-    std::vector<ColDesc> rc;
-    for (int j = 0; j < cap; ++j) rc.push_back(Rcol(j));
-    TsmmDesc t{};
-    t.nrows = ng;
-    t.in = stage_push(c, rc);
-    t.nin = cap;
-    t.C = S1;
-    t.ldc = 16;
-    t.out = dtil;
-    t.out_ld = ng;
-    t.out_f32 = 0;
-    t.nout = 1;
-    t.add = w.u_aug;
-    t.alpha = -1.0;
-    t.wg_begin = 0;
-    TsmmDesc* td = stage_push1(c, t);
-    stage_flush(c, s);
-    launch_tsmm(td, 1, tsmm_wgs(ng), 1, s);
-    // second Gram-Schmidt pass: c2 = R^T M d~, d~ -= R c2
-    GramWork g2 = g1;
-    for (int j = cap; j < 32; ++j) g2.cols[j] = col_null();
-    g2.cols[32] = f64col(dtil);
-    g2.out = S2;
-    enqueue_gram(c, {g2}, 2, 1, false, s, "co_g");
-    TsmmDesc t2 = t;
-    t2.in = stage_push(c, rc);
-    t2.C = S2;
-    t2.add = dtil;
-    TsmmDesc* td2 = stage_push1(c, t2);
-    stage_flush(c, s);
-    launch_tsmm(td2, 1, tsmm_wgs(ng), 1, s);
-    // |d~|^2, |u|^2
-    GramWork g3;
-    g3.nrows = ng;
-    g3.cols.push_back(f64col(dtil));
-    g3.cols.push_back(f64col(w.u_aug));
-    g3.cols.resize(16, col_null());
-    g3.out = S3;
-    g3.ld = 16;
-    g3.scale = h3;
-    enqueue_gram(c, {g3}, 1, 0, false, s, "co_g");
-    AugDesc a{S3, S3 + 17, flag, dscale, w.m, nullptr};
+    // CGS2 of eqaug, one fused pass each: (1) c1 = R^T M u and |u|_M^2;
+    // (2) d~ = u - R c1 with c2 = R^T M d~; (3) d~ -= R c2 with |d~|_M^2
+    CgsArgs ga{};
+    for (int j = 0; j < cap; ++j) ga.col[j] = (const char*)w.R + (size_t)j * cld * sf;
+    ga.f32 = f32 ? 1 : 0;
+    ga.mptr = w.m;
+    ga.n = cap;
+    ga.nrows = ng;
+    ga.chunk_rows = cgs_chunk_rows(ng);
+    ga.nchunks = (int)((ng + ga.chunk_rows - 1) / ga.chunk_rows);
+    ga.partial = (double*)scratch(c, "co_cgs_part", (size_t)ga.nchunks * (kCgsMaxCols + 1) * 8);
+    ga.scale = h3;
+    CgsArgs a1 = ga;
+    a1.y = w.u_aug;
+    a1.dots = S1;
+    a1.norm = S1 + 32;
+    launch_cgs(a1, s);
+    CgsArgs a2 = ga;
+    a2.y = w.u_aug;
+    a2.c = S1;
+    a2.z = dtil;
+    a2.dots = S2;
+    a2.norm = S2 + 32;
+    launch_cgs(a2, s);
+    CgsArgs a3 = ga;
+    a3.y = dtil;
+    a3.c = S2;
+    a3.z = dtil;
+    a3.norm = S3;
+    launch_cgs(a3, s);
+    AugDesc a{S3, S1 + 32, flag, dscale, w.m, nullptr};
     AugDesc* ad = stage_push1(c, a);
     stage_flush(c, s);
     launch_aug_decide(ad, 1, s);

@@ -118,6 +118,8 @@ struct PodWork {
   int* m_out;
   double* lambda_out;          // nullable, >= cols.size()
   long long R_ld = 0;          // column stride of R_out in elements (0: N_g)
+  int skip_tail = 0;           // 1: R_out columns >= *m_out are left unwritten
+                               // (for consumers that mask by the rank)
 };
 void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
                  const std::string& tag);
@@ -144,6 +146,7 @@ struct ApplyLWork {
   const int* mptr;
   int piece = 0;          // forced flows: apply piece `piece` of L(t)
   long long ld = 0;       // column stride of in and out in elements (0: N_g)
+  int skip_tail = 0;      // 1: columns >= *mptr left unwritten (else zeroed)
 };
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
 void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,

@@ -84,6 +84,28 @@ struct PairList {
 
 constexpr int kFlushSteps = 4;  // FP32 MFMA: fold into FP64 every 4 x 64 rows
 
+// Runtime compaction of a column group (one wave): the valid columns among
+// cols[base, base + count) in their order. src[base + i] receives the
+// descriptor index of the i-th valid column and pos[base + c] the compact
+// position of column c (-1 if invalid); either may be null. Returns the
+// number of valid columns. Columns whose validity hangs on a device rank
+// (POD modes beyond m, an absent augmentation column) thus take no MFMA
+// tile of their own.
+__device__ int compact_group(const ColDesc* __restrict__ cols, int base, int count, short* src,
+                             short* pos, int lane) {
+  int off = 0;
+  for (int c0 = 0; c0 < count; c0 += 64) {
+    const int c = c0 + lane;
+    const bool v = c < count && col_valid(cols[base + c]);
+    const unsigned long long mask = __ballot(v);
+    const int p = off + __popcll(mask & ((1ull << lane) - 1ull));
+    if (v && src) src[base + p] = (short)(base + c);
+    if (c < count && pos) pos[base + c] = (short)(v ? p : -1);
+    off += __popcll(mask);
+  }
+  return off;
+}
+
 template <int NA, int NB, bool F32>
 __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ descs, int nd) {
   using M = Mfma<F32>;
@@ -100,13 +122,30 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ci = lane & 15, kq = lane >> 4;
 
+  // valid columns packed into the leading tiles of each group (A, then B);
+  // only tile pairs holding some of them are computed
+  __shared__ short s_src[NT * 16];
+  __shared__ int s_cnt[2];
+  if (wave == 0) {
+    const int na = compact_group(d.cols, 0, NA * 16, s_src, nullptr, lane);
+    const int nb = NB == 0 ? 0 : compact_group(d.cols, NA * 16, NB * 16, s_src, nullptr, lane);
+    if (lane == 0) {
+      s_cnt[0] = na;
+      s_cnt[1] = nb;
+    }
+  }
+  __syncthreads();
+  const int tA = (s_cnt[0] + 15) >> 4;
+  const int tB = NB == 0 ? tA : (s_cnt[1] + 15) >> 4;
   const void* cp[NT];
   int cf[NT];
   bool cv[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const ColDesc c = d.cols[t * 16 + ci];
-    cv[t] = col_valid(c);
+    const int slot = (t < NA) ? t * 16 + ci : (t - NA) * 16 + ci;
+    const int n_grp = (t < NA) ? s_cnt[0] : s_cnt[1];
+    cv[t] = slot < n_grp;
+    const ColDesc c = d.cols[cv[t] ? s_src[t * 16 + ci] : 0];
     cp[t] = c.ptr;
     cf[t] = c.f32;
   }
@@ -132,10 +171,11 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
       In v[NT][UL];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
+        const bool act = (t < NA) ? t < tA : t - NA < tB;
 #pragma unroll
         for (int u = 0; u < UL; ++u) {
           const long long row = r0 + 4 * kq + u0 + u;
-          v[t][u] = (cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+          v[t][u] = (act && cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
         }
       }
 #pragma unroll
@@ -149,6 +189,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
             if (NB == 0 && jb < ia) continue;
             const int p = (NB == 0) ? ia * NA - ia * (ia - 1) / 2 + (jb - ia) : ia * NB + jb;
             const int ib = (NB == 0) ? jb : NA + jb;
+            if (ia >= tA || jb >= tB) continue;
             if constexpr (F32)
               acc32[p] = M::op(v[ia][u], v[ib][u], acc32[p]);
             else
@@ -183,6 +224,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   PR_GLOBAL double* part = gptr(d.partial) + (long long)chunk * P * 256;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
+    if (PL::a(p) >= tA || PL::b(p) - (NB == 0 ? 0 : NA) >= tB) continue;  // uniform
 #pragma unroll
     for (int e = 0; e < 4; ++e) red[wave][e * 64 + lane] = acc[p][e];
     __syncthreads();
@@ -195,33 +237,56 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 
 // Sum of the per-chunk partials of one tile pair, scaled, written to the
 // output (and its mirror for the symmetric form). Workgroup (x, item) owns 64
-// of the pair's 256 entries (x = pair * 4 + quarter); its 16 wave groups each
-// sum the chunks q, q + 16, q + 32, ... in that order (four accumulators, one
-// per residue of the chunk index modulo 64), and the groups' sums combine in
-// a fixed tree. The order depends only on the chunk count, so the result
-// does not depend on the batch.
+// of the pair's 256 entries (x = pair * 4 + quarter) in the original column
+// order; each entry is looked up at its compact position (the compaction of
+// k_gemm_tn, redone here), and entries of invalid columns are zero. The 16
+// wave groups each sum the chunks q, q + 16, q + 32, ... in that order (four
+// accumulators, one per residue of the chunk index modulo 64), and the
+// groups' sums combine in a fixed tree. The order depends only on the chunk
+// count, so the result does not depend on the batch.
 template <int NA, int NB>
 __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
   using PL = PairList<NA, NB>;
   constexpr int P = PL::P;
   __shared__ double red[16][64];
+  __shared__ short s_pos[(NA + NB) * 16];
   const GemmDesc& d = descs[blockIdx.y];
   const int p = blockIdx.x >> 2;
   const int e = ((blockIdx.x & 3) << 6) | (threadIdx.x & 63);
   const int q = threadIdx.x >> 6;
-  const PR_GLOBAL double* src = gptr(d.partial) + (long long)p * 256 + e;
+  if (q == 0) {
+    compact_group(d.cols, 0, NA * 16, nullptr, s_pos, threadIdx.x);
+    if (NB != 0) compact_group(d.cols, NA * 16, NB * 16, nullptr, s_pos, threadIdx.x);
+  }
+  __syncthreads();
+  const int ta = PL::a(p), tb = PL::b(p);
+  int pa = s_pos[ta * 16 + (e >> 4)], pb = s_pos[tb * 16 + (e & 15)];
+  const bool valid = pa >= 0 && pb >= 0;
+  int pc = 0;
+  if (valid) {
+    if (NB == 0 && (pa >> 4) > (pb >> 4)) {
+      const int t = pa;
+      pa = pb;
+      pb = t;
+    }
+    const int ia = pa >> 4, jb = pb >> 4;
+    pc = (NB == 0) ? ia * NA - ia * (ia - 1) / 2 + (jb - ia) : ia * NB + jb;
+    pc = pc * 256 + (pa & 15) * 16 + (pb & 15);
+  }
+  const PR_GLOBAL double* src = gptr(d.partial) + pc;
   const long long stride = (long long)P * 256;
+  const int nch = valid ? d.nchunks : 0;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   int c = q;
-  for (; c + 48 < d.nchunks; c += 64) {
+  for (; c + 48 < nch; c += 64) {
     a0 += src[(long long)c * stride];
     a1 += src[(long long)(c + 16) * stride];
     a2 += src[(long long)(c + 32) * stride];
     a3 += src[(long long)(c + 48) * stride];
   }
-  if (c < d.nchunks) a0 += src[(long long)c * stride];
-  if (c + 16 < d.nchunks) a1 += src[(long long)(c + 16) * stride];
-  if (c + 32 < d.nchunks) a2 += src[(long long)(c + 32) * stride];
+  if (c < nch) a0 += src[(long long)c * stride];
+  if (c + 16 < nch) a1 += src[(long long)(c + 16) * stride];
+  if (c + 32 < nch) a2 += src[(long long)(c + 32) * stride];
   red[q][threadIdx.x & 63] = (a0 + a1) + (a2 + a3);
   __syncthreads();
   if (q != 0) return;
@@ -232,7 +297,6 @@ __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict
   const double sum =
       d.scale * (((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7])));
   const int row = e >> 4, col = e & 15;
-  const int ta = PL::a(p), tb = PL::b(p);
   PR_GLOBAL double* out = gptr(d.out);
   if (NB == 0) {
     out[(long long)(ta * 16 + row) * d.ld + tb * 16 + col] = sum;
@@ -290,8 +354,9 @@ void launch_gemm_reduce(const GemmDesc* d, int nd, int na, int nb, hipStream_t s
 
 // ---------------------------------------------------------------------------
 // out[:, j] = alpha * sum_c in_c * C[c][j] (+ add for j = 0); j < nout, and
-// columns j >= *out_mptr are zero. Rows are private to a thread, so the
-// output may alias the input columns (all reads of a row precede its writes).
+// columns j >= *out_mptr are zero (with skip_tail: not written). Rows are
+// private to a thread, so the output may alias the input columns (all reads
+// of a row precede its writes).
 // The column descriptors, their validity (which may depend on a device rank)
 // and C are staged in LDS once per workgroup; each thread owns two rows.
 constexpr int kTsmmMaxOut = 32;
@@ -320,13 +385,15 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
   }
   for (int e = threadIdx.x; e < nin * nout; e += 256)
     sC[e] = gptr(d.C)[(long long)(e / nout) * d.ldc + (e % nout)];
-  if (threadIdx.x == 0) s_mo = d.out_mptr ? *d.out_mptr : nout;
+  if (threadIdx.x == 0) s_mo = d.out_mptr ? min(*d.out_mptr, nout) : nout;
   __syncthreads();
   const long long r0 = (w - d.wg_begin) * kTsmmRowsPerWg + threadIdx.x;
   const long long r1 = r0 + 256;
   const bool v0 = r0 < d.nrows, v1 = r1 < d.nrows;
   if (!v0) return;
   const long long q1 = v1 ? r1 : r0;
+  // outputs j >= mo are zero (or left alone): no products for them
+  const int mo = s_mo;
   double a0[MAXOUT], a1[MAXOUT];
 #pragma unroll
   for (int j = 0; j < MAXOUT; ++j) a0[j] = a1[j] = 0.0;
@@ -352,7 +419,7 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
       const double* Cr = sC + (c + u) * nout;
 #pragma unroll
       for (int j = 0; j < MAXOUT; ++j)
-        if (j < nout) {
+        if (j < mo) {
           a0[j] += x0[u] * Cr[j];
           a1[j] += x1[u] * Cr[j];
         }
@@ -363,17 +430,17 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
     const double* Cr = sC + c * nout;
 #pragma unroll
     for (int j = 0; j < MAXOUT; ++j)
-      if (j < nout) {
+      if (j < mo) {
         a0[j] += x0 * Cr[j];
         a1[j] += x1 * Cr[j];
       }
   }
-  const int mo = s_mo;
+  const int nw = d.skip_tail ? mo : nout;
   const PR_GLOBAL double* add = d.add ? gptr(d.add) : nullptr;
   const double ad0 = add ? add[r0] : 0.0, ad1 = add ? add[q1] : 0.0;
 #pragma unroll
   for (int j = 0; j < MAXOUT; ++j) {
-    if (j < nout) {
+    if (j < nw) {
       double y0 = (j < mo) ? d.alpha * a0[j] : 0.0;
       double y1 = (j < mo) ? d.alpha * a1[j] : 0.0;
       if (j == 0) {
@@ -515,6 +582,142 @@ __global__ __launch_bounds__(256) void k_norm_reduce(const NormReduceDesc* __res
 void launch_norm_reduce(const NormReduceDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
   hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Gram-Schmidt pass of the augmentation (CgsArgs). Thread t of workgroup b
+// owns rows b * chunk_rows + t + 256 i; its column loads are coalesced across
+// the wave. Columns j >= m are read from column 0 (a finite value, in
+// bounds) and replaced by zero, so the loads of a row are branch-free and
+// issued together.
+template <int MAXC, bool DOTS, bool SUB, typename In>
+__global__ __launch_bounds__(256) void k_cgs(const CgsArgs a) {
+  __shared__ double red[4][MAXC + 1];
+  const int n = a.n;
+  const int m = a.mptr ? min(*a.mptr, n) : n;
+  const long long r_begin = (long long)blockIdx.x * a.chunk_rows;
+  const long long r_end = min(a.nrows, r_begin + (long long)a.chunk_rows);
+  const PR_GLOBAL In* p[MAXC];
+  double cj[MAXC];
+#pragma unroll
+  for (int j = 0; j < MAXC; ++j) {
+    p[j] = gptr((const In*)a.col[j < m ? j : 0]);
+    cj[j] = (SUB && j < m) ? a.c[j] : 0.0;
+  }
+  double acc[MAXC + 1];
+#pragma unroll
+  for (int j = 0; j <= MAXC; ++j) acc[j] = 0.0;
+  const PR_GLOBAL double* y = gptr(a.y);
+  PR_GLOBAL double* z = a.z ? gptr(a.z) : nullptr;
+  for (long long r = r_begin + threadIdx.x; r < r_end; r += 256) {
+    double x[MAXC];
+    if (m > 0) {
+#pragma unroll
+      for (int j = 0; j < MAXC; ++j) {
+        const double v = (double)p[j][r];
+        x[j] = j < m ? v : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < MAXC; ++j) x[j] = 0.0;
+    }
+    double v = y[r];
+    if constexpr (SUB) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < MAXC; ++j) s += cj[j] * x[j];
+      v -= s;
+    }
+    if (z) z[r] = v;
+    if constexpr (DOTS) {
+#pragma unroll
+      for (int j = 0; j < MAXC; ++j) acc[j] += x[j] * v;
+    }
+    acc[MAXC] += v * v;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j <= MAXC; ++j) {
+    if (!DOTS && j < MAXC) continue;
+    const double s = wave_sum(acc[j]);
+    if (lane == 0) red[wave][j] = s;
+  }
+  __syncthreads();
+  PR_GLOBAL double* part = gptr(a.partial) + (long long)blockIdx.x * (n + 1);
+  const int t = threadIdx.x;
+  if (t <= n) {
+    const int k = (t == n) ? MAXC : t;
+    double s = 0.0;
+    if (t == n || (DOTS && t < m)) s = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    part[t] = s;
+  }
+}
+
+// Per output j <= n (one workgroup each): scale * the chunk partials summed
+// in a fixed order (strided per thread, then a fixed tree).
+__global__ __launch_bounds__(256) void k_cgs_reduce(const CgsArgs a) {
+  __shared__ double red[256];
+  const int j = blockIdx.x == 0 ? a.n : (int)blockIdx.x - 1;
+  const PR_GLOBAL double* part = gptr(a.partial);
+  double s = 0.0;
+  for (int q = threadIdx.x; q < a.nchunks; q += 256) s += part[(long long)q * (a.n + 1) + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+#pragma unroll
+  for (int w = 128; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (j == a.n) *gptr(a.norm) = a.scale * red[0];
+    else gptr(a.dots)[j] = a.scale * red[0];
+  }
+}
+
+int cgs_chunk_rows(long long nrows) {
+  long long ch = (nrows + 1023) / 1024;
+  ch = std::max<long long>(ch, 1024);
+  return (int)((ch + 255) / 256 * 256);
+}
+
+template <int MAXC, bool DOTS, bool SUB>
+static void cgs_launch(const CgsArgs& a, hipStream_t s) {
+  const dim3 g((unsigned)a.nchunks), b(256);
+  if (a.f32) hipLaunchKernelGGL((k_cgs<MAXC, DOTS, SUB, float>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_cgs<MAXC, DOTS, SUB, double>), g, b, 0, s, a);
+}
+
+template <bool DOTS, bool SUB>
+static void cgs_width(const CgsArgs& a, hipStream_t s) {
+  // the column count rounded up to a multiple of 4 (few padding loads)
+  switch ((a.n + 3) / 4) {
+    case 0:
+    case 1: cgs_launch<4, DOTS, SUB>(a, s); break;
+    case 2: cgs_launch<8, DOTS, SUB>(a, s); break;
+    case 3: cgs_launch<12, DOTS, SUB>(a, s); break;
+    case 4: cgs_launch<16, DOTS, SUB>(a, s); break;
+    case 5: cgs_launch<20, DOTS, SUB>(a, s); break;
+    case 6: cgs_launch<24, DOTS, SUB>(a, s); break;
+    case 7: cgs_launch<28, DOTS, SUB>(a, s); break;
+    default: cgs_launch<32, DOTS, SUB>(a, s); break;
+  }
+}
+
+void launch_cgs(const CgsArgs& a, hipStream_t s) {
+  PR_CHECK(a.n >= 0 && a.n <= kCgsMaxCols, "cgs: 0..32 columns");
+  PR_CHECK(a.y && a.partial && a.norm, "cgs: null vector");
+  PR_CHECK(a.chunk_rows % 256 == 0 && a.chunk_rows > 0, "cgs: chunk rows");
+  PR_CHECK(a.nchunks == (int)((a.nrows + a.chunk_rows - 1) / a.chunk_rows), "cgs: chunk count");
+  for (int j = 0; j < a.n; ++j) PR_CHECK(a.col[j] != nullptr, "cgs: null column");
+  if (a.nchunks <= 0) return;
+  const bool dots = a.dots != nullptr, sub = a.c != nullptr;
+  PR_CHECK(dots || sub, "cgs: a pass without coefficients returns the dots");
+  if (dots && sub) cgs_width<true, true>(a, s);
+  else if (dots) cgs_width<true, false>(a, s);
+  else cgs_width<false, true>(a, s);
+  PR_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cgs_reduce, dim3(dots ? a.n + 1 : 1), dim3(256), 0, s, a);
   PR_HIP(hipGetLastError());
 }
 

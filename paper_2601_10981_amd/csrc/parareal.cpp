@@ -551,6 +551,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         const int slot = k % 2;
         w.R_out = S->R0 + ((size_t)slot * Np + n) * P.o.cap0 * cs;
         w.R_ld = P.ld;
+        w.skip_tail = 1;
         w.m_out = S->m0slot + slot * Np + n;
         w.lambda_out = nullptr;
         pw.push_back(w);
@@ -689,11 +690,12 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.R_ld = P.ld;
         w.m_out = S->mS + (n - n0);
         w.lambda_out = nullptr;
+        w.skip_tail = 1;
         pw.push_back(w);
         for (int jp = 0; jp < P.np; ++jp)
           aw.push_back(ApplyLWork{&S->P.prob, w.R_out,
                                   S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * P.cs, cap,
-                                  w.m_out, jp, P.ld});
+                                  w.m_out, jp, P.ld, 1});
       }
       ph.begin(1);
       for (int na = 1; na <= 4; ++na) {

@@ -170,9 +170,10 @@ struct ApplyLDesc {
   T* out;
   long long ld;    // column stride in elements (>= N_g)
   int ncols;
-  const int* mptr;  // valid columns (nullptr = all)
+  const int* mptr;  // valid columns (nullptr = all); the others are written as zero
   int tiles_q, tiles_x;
   long long tile_begin;  // tiles per column = tiles_q * tiles_x
+  int skip_tail;    // 1: columns >= *mptr are left unwritten instead
 };
 
 // ---- tall-skinny Gram / A^T B on MFMA --------------------------------------
@@ -204,6 +205,7 @@ struct TsmmDesc {
   const double* add;     // nullptr or N_g doubles added to column 0
   double alpha;
   long long wg_begin;
+  int skip_tail;         // 1: columns >= *out_mptr are left unwritten instead
 };
 
 // ---- correction with jump partials ----------------------------------------
@@ -252,6 +254,32 @@ void launch_applyL_f32(const ApplyLDesc<float>* d, int nitems, long long total_t
 void launch_gemm_tn(const GemmDesc* d, int nitems, long long total_wg, int na, int nb,
                     bool f32, hipStream_t s);
 void launch_gemm_reduce(const GemmDesc* d, int nitems, int na, int nb, hipStream_t s);
+
+// ---- one Gram-Schmidt pass of the augmentation (eqaug) ----------------------
+// Over the rows of one field: z = y - sum_{j < m} c[j] X_j (or z = y without
+// coefficients), then dots[j] = scale * X_j^T z (j < n, zero for j >= m) and
+// norm = scale * z^T z. Every column X_j (j < m) is read once, with the lanes
+// of a wave on consecutive rows; partial sums per row chunk are added in a
+// fixed order, so a result depends on the row count only.
+constexpr int kCgsMaxCols = 32;
+struct CgsArgs {
+  const void* col[kCgsMaxCols];  // X_j, j < n: N_g values each (all FP64 or all FP32)
+  int f32;
+  const int* mptr;     // device rank: columns j >= *mptr count as zero (nullptr: m = n)
+  int n;               // 0..32
+  long long nrows;
+  int chunk_rows;      // multiple of 256
+  int nchunks;
+  const double* y;     // N_g doubles
+  const double* c;     // nullptr, or n coefficients (device)
+  double* z;           // nullptr, or N_g doubles written (may alias y)
+  double* partial;     // nchunks x (n + 1)
+  double* dots;        // nullptr, or n doubles
+  double* norm;        // one double
+  double scale;
+};
+int cgs_chunk_rows(long long nrows);
+void launch_cgs(const CgsArgs& a, hipStream_t s);
 
 // max_nout: the largest nout of the items (selects the accumulator count).
 void launch_tsmm(const TsmmDesc* d, int nitems, long long total_wg, int max_nout, hipStream_t s);

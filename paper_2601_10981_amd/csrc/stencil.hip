@@ -379,6 +379,7 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   PR_GLOBAL T* out = gptr(d.out) + (long long)col * d.ld;
   const bool valid = (d.mptr == nullptr) || (col < *d.mptr);
   if (!valid) {
+    if (d.skip_tail) return;
     const long long plane = (long long)n * n;
     for (int x = x0; x < x1; ++x) out[(long long)x * plane + q] = (T)0;
     return;
