@@ -640,6 +640,11 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
   if (items.empty()) return;
   const bool f32 = items[0].prob->precision == PR_MIXED;
   long long tiles = 0;
+  // x planes per workgroup: kChunkX, or a quarter of it when that leaves a
+  // launch (one column of L d in the sweep) under 2048 workgroups
+  long long wide = 0;
+  for (auto& w : items) wide += (long long)tiles_q(w.prob->n) * tiles_x(w.prob->n) * w.ncols;
+  const int cx = wide < 2048 ? kChunkX / 4 : kChunkX;
   if (f32) {
     std::vector<ApplyLDesc<float>> d;
     for (auto& w : items) {
@@ -652,7 +657,8 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.mptr = w.mptr;
       a.skip_tail = w.skip_tail;
       a.tiles_q = tiles_q(w.prob->n);
-      a.tiles_x = tiles_x(w.prob->n);
+      a.chunk_x = cx;
+      a.tiles_x = (w.prob->n + cx - 1) / cx;
       a.tile_begin = tiles;
       tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
       d.push_back(a);
@@ -672,7 +678,8 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       a.mptr = w.mptr;
       a.skip_tail = w.skip_tail;
       a.tiles_q = tiles_q(w.prob->n);
-      a.tiles_x = tiles_x(w.prob->n);
+      a.chunk_x = cx;
+      a.tiles_x = (w.prob->n + cx - 1) / cx;
       a.tile_begin = tiles;
       tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
       d.push_back(a);
@@ -812,8 +819,11 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   }
   TsmmDesc* tdd = stage_push(c, td);
   stage_flush(c, s);
+  // accumulator class: every column written, or, when the columns beyond
+  // the rank are left alone, the rank bound min(cap, input columns)
   int max_cap = 1;
-  for (auto& it : items) max_cap = std::max(max_cap, it.cap);
+  for (auto& it : items)
+    max_cap = std::max(max_cap, it.skip_tail ? std::min(it.cap, (int)it.cols.size()) : it.cap);
   launch_tsmm(tdd, nitems, wg, max_cap, s);
 
   // 5. CholQR in the M inner product (FP64 MFMA Gram, FP64 Cholesky). The
@@ -998,55 +1008,58 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     enqueue_applyL_pieces(c, p, dcol, Ld, 1, flag, s);
   }
   P.begin(2);
-  // Galerkin products of Psi against [Psi, L Psi, u_in]
+  // Galerkin products of Psi = [R, d] against [Psi, L_j Psi per piece,
+  // u_in, f_j per piece], the B columns packed (cap + 1 per block) so the
+  // launch shape follows the columns that can be valid
   GramWork gb;
   gb.nrows = ng;
+  const int npsi = cap + 1;
   std::vector<ColDesc> psi;
-  for (int j = 0; j < 32; ++j) {
-    ColDesc cd = col_null();
-    if (j < cap) cd = Rcol(j);
-    else if (j == cap && aug) cd = ColDesc{dcol, aug, 0, f32 ? 1 : 0};
-    psi.push_back(cd);
-  }
+  for (int j = 0; j < npsi; ++j)
+    psi.push_back(j < cap ? Rcol(j)
+                          : (aug ? ColDesc{dcol, aug, 0, f32 ? 1 : 0} : col_null()));
+  const int na = (npsi + 15) / 16;
   gb.cols = psi;                                   // A tiles
-  gb.cols.insert(gb.cols.end(), psi.begin(), psi.end());  // B: Psi
+  gb.cols.resize((size_t)na * 16, col_null());
+  std::vector<ColDesc> bc(psi);                    // B: Psi
   for (int jp = 0; jp < np; ++jp)                  // B: L_j Psi per piece
-    for (int j = 0; j < 32; ++j) {
-      ColDesc cd = col_null();
-      if (j < cap) cd = LRcol(jp, j);
-      else if (j == cap && aug) cd = ColDesc{(const char*)Ld + (size_t)jp * ng * sf, aug, 0, f32 ? 1 : 0};
-      gb.cols.push_back(cd);
-    }
-  for (int j = 0; j < 16; ++j) {                   // B: states, then forcing fields
-    ColDesc cd = col_null();
-    if (j < w.n_in) cd = f64col(w.u_in[j]);
-    else if (forced && j >= 2 && j < 2 + np)
-      cd = col_of(forcing, j - 2, cld, f32, nullptr);
-    gb.cols.push_back(cd);
-  }
-  const int nb = 2 + 2 * np + 1;
+    for (int j = 0; j < npsi; ++j)
+      bc.push_back(j < cap ? LRcol(jp, j)
+                           : (aug ? ColDesc{(const char*)Ld + (size_t)jp * ng * sf, aug, 0,
+                                            f32 ? 1 : 0}
+                                  : col_null()));
+  const int off_U = (int)bc.size();
+  for (int i = 0; i < w.n_in; ++i) bc.push_back(f64col(w.u_in[i]));   // B: states
+  const int off_F = (int)bc.size();
+  for (int jp = 0; forced && jp < np; ++jp)                            // B: forcing
+    bc.push_back(col_of(forcing, jp, cld, f32, nullptr));
+  const int nb = ((int)bc.size() + 15) / 16;
+  bc.resize((size_t)nb * 16, col_null());
+  gb.cols.insert(gb.cols.end(), bc.begin(), bc.end());
   gb.out = Sbig;
   gb.ld = 16 * nb;
   gb.scale = h3;
-  enqueue_gram(c, {gb}, 2, nb, false, s, "co_g");
+  PR_CHECK(32 * gb.ld * 8 <= 57344 - 20480, "Galerkin block exceeds its scratch");
+  enqueue_gram(c, {gb}, na, nb, false, s, "co_g");
 
   P.begin(4);
   double* beta = w.beta_out ? w.beta_out : betas;
   ReducedDesc rd{};
   rd.S = Sbig;
   rd.ld = 16 * nb;
+  rd.ld_piece = npsi;
   rd.cap = cap;
   rd.m = w.m;
   rd.aug = aug;
   rd.off_M = 0;
-  rd.off_L = 32;
-  rd.off_U = 32 + 32 * np;
+  rd.off_L = npsi;
+  rd.off_U = off_U;
   rd.n_in = w.n_in;
   rd.dT = w.dT;
   rd.n_c = w.n_c;
   rd.forced = forced ? geom_of(c, p).forced : 0;
   rd.npieces = np;
-  rd.off_F = rd.off_U + 2;
+  rd.off_F = off_F;
   rd.w = forced ? p.fp[2] : 0.0;
   rd.t0 = w.t0;
   rd.beta = beta;

@@ -322,8 +322,12 @@ static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
                      d);
 }
 
+// Symmetric Grams of 1..4 tiles; A^T B for the Galerkin products (A: the
+// basis, 1 or 2 tiles; B: the packed blocks, at most 5 tiles beside one A
+// tile and 3..9 beside two)
 #define PR_GEMM_SHAPES(X) \
-  X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 1) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(2, 7) X(2, 9) X(1, 2) X(1, 4)
+  X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(1, 5) \
+  X(2, 3) X(2, 4) X(2, 5) X(2, 6) X(2, 7) X(2, 8) X(2, 9)
 
 void launch_gemm_tn(const GemmDesc* d, int nd, long long total_wg, int na, int nb, bool f32,
                     hipStream_t s) {
@@ -357,57 +361,72 @@ void launch_gemm_reduce(const GemmDesc* d, int nd, int na, int nb, hipStream_t s
 // columns j >= *out_mptr are zero (with skip_tail: not written). Rows are
 // private to a thread, so the output may alias the input columns (all reads
 // of a row precede its writes).
-// The column descriptors, their validity (which may depend on a device rank)
-// and C are staged in LDS once per workgroup; each thread owns two rows.
+// The valid input columns (validity may depend on a device rank) are
+// compacted into LDS with their rows of C, once per workgroup, so the
+// products run over valid inputs and outputs j < *out_mptr only; each thread
+// owns two rows.
 constexpr int kTsmmMaxOut = 32;
 constexpr int kTsmmMaxIn = 64;
 constexpr int kTsmmRowsPerWg = 512;
 
-// MAXOUT bounds nout of every item (the accumulators held per thread): a
-// narrow product (the sweep's projection residual has one output) then runs
-// at far higher occupancy, which is what hides this kernel's memory latency.
+// MAXOUT bounds the outputs formed (the accumulators held per thread): a
+// narrow product (a low-rank basis) then runs at far higher occupancy, which
+// is what hides this kernel's memory latency.
 template <int MAXOUT>
 __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs, int nd) {
   __shared__ const void* sp[kTsmmMaxIn];
   __shared__ int sf[kTsmmMaxIn];
-  __shared__ int sv[kTsmmMaxIn];
+  __shared__ int so[kTsmmMaxIn];
   __shared__ double sC[kTsmmMaxIn * MAXOUT];
-  __shared__ int s_mo;
+  __shared__ int s_mo, s_nv;
   const long long w = blockIdx.x;
   const int f = find_wg(descs, nd, w);
   const TsmmDesc& d = descs[f];
   const int nin = d.nin, nout = d.nout;
-  if (threadIdx.x < nin) {
-    const ColDesc cd = d.in[threadIdx.x];
-    sp[threadIdx.x] = cd.ptr;
-    sf[threadIdx.x] = cd.f32;
-    sv[threadIdx.x] = col_valid(cd) ? 1 : 0;
+  if (threadIdx.x < 64) {
+    // compact the valid inputs (nin <= 64: one wave)
+    const int c = threadIdx.x;
+    ColDesc cd{};
+    const bool v = c < nin && col_valid(cd = d.in[c]);
+    const unsigned long long mask = __ballot(v);
+    const int p = __popcll(mask & ((1ull << c) - 1ull));
+    if (v) {
+      sp[p] = cd.ptr;
+      sf[p] = cd.f32;
+      so[p] = c;
+    }
+    if (c == 0) {
+      s_nv = __popcll(mask);
+      s_mo = min(d.out_mptr ? min(*d.out_mptr, nout) : nout, MAXOUT);
+    }
   }
-  for (int e = threadIdx.x; e < nin * nout; e += 256)
-    sC[e] = gptr(d.C)[(long long)(e / nout) * d.ldc + (e % nout)];
-  if (threadIdx.x == 0) s_mo = d.out_mptr ? min(*d.out_mptr, nout) : nout;
+  __syncthreads();
+  const int nv = s_nv;
+  // outputs j >= mo are zero (or left alone): no products for them
+  const int mo = s_mo;
+  for (int e = threadIdx.x; e < nv * mo; e += 256) {
+    const int k = e / mo, j = e - k * mo;
+    sC[k * MAXOUT + j] = gptr(d.C)[(long long)so[k] * d.ldc + j];
+  }
   __syncthreads();
   const long long r0 = (w - d.wg_begin) * kTsmmRowsPerWg + threadIdx.x;
   const long long r1 = r0 + 256;
   const bool v0 = r0 < d.nrows, v1 = r1 < d.nrows;
   if (!v0) return;
   const long long q1 = v1 ? r1 : r0;
-  // outputs j >= mo are zero (or left alone): no products for them
-  const int mo = s_mo;
   double a0[MAXOUT], a1[MAXOUT];
 #pragma unroll
   for (int j = 0; j < MAXOUT; ++j) a0[j] = a1[j] = 0.0;
   // wide outputs (few waves resident): four input columns per round, their
-  // loads issued together before the multiply-adds (an invalid column reads
-  // as zero, leaving every sum unchanged), so a wave waits for memory once
-  // per round; narrow ones already hide the latency with occupancy
+  // loads issued together before the multiply-adds, so a wave waits for
+  // memory once per round; narrow ones already hide the latency with
+  // occupancy
   auto ld = [&](int c, long long r) -> double {
-    if (!sv[c]) return 0.0;
     if (sf[c]) return (double)gptr((const float*)sp[c])[r];
     return gptr((const double*)sp[c])[r];
   };
   int c = 0;
-  for (; MAXOUT > 8 && c + 4 <= nin; c += 4) {
+  for (; MAXOUT > 8 && c + 4 <= nv; c += 4) {
     double x0[4], x1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -416,7 +435,7 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double* Cr = sC + (c + u) * nout;
+      const double* Cr = sC + (c + u) * MAXOUT;
 #pragma unroll
       for (int j = 0; j < MAXOUT; ++j)
         if (j < mo) {
@@ -425,9 +444,9 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
         }
     }
   }
-  for (; c < nin; ++c) {
+  for (; c < nv; ++c) {
     const double x0 = ld(c, r0), x1 = ld(c, q1);
-    const double* Cr = sC + c * nout;
+    const double* Cr = sC + c * MAXOUT;
 #pragma unroll
     for (int j = 0; j < MAXOUT; ++j)
       if (j < mo) {

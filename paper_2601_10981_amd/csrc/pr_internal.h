@@ -172,6 +172,7 @@ struct ApplyLDesc {
   int ncols;
   const int* mptr;  // valid columns (nullptr = all); the others are written as zero
   int tiles_q, tiles_x;
+  int chunk_x;      // x planes per workgroup (tiles_x = ceil(n / chunk_x))
   long long tile_begin;  // tiles per column = tiles_q * tiles_x
   int skip_tail;    // 1: columns >= *mptr are left unwritten instead
 };
@@ -314,12 +315,13 @@ void launch_cholqr_coef(const CholDesc* d, int nitems, hipStream_t s);
 // read from the Gram output: S (q x ld) with Psi^T M Psi in columns
 // [0, q) and Psi^T M L Psi in columns [q_off_L, q_off_L + q) and the
 // projections Psi^T M u_i in column q_off_U + i.
-// Forced flows: S holds Psi^T M L_j Psi in columns [off_L + 32 j, ...) for
-// piece j < npieces and Psi^T M f_j in column off_F + j; the system is
+// Forced flows: S holds Psi^T M L_j Psi in columns [off_L + ld_piece j, ...)
+// for piece j < npieces and Psi^T M f_j in column off_F + j; the system is
 // M_r beta' = sum_j theta_j(t) (L_r,j beta + f_r,j) from t0.
 struct ReducedDesc {
   const double* S;
   int ld;            // leading dimension of S (row = basis index)
+  int ld_piece;      // column distance of the L pieces in S (0: 32)
   int cap;           // R columns (rows 0..cap-1); the augmented column is row cap
   const int* m;      // valid R columns
   const int* aug;    // device flag: 1 if column `cap` (d) is present
@@ -341,6 +343,7 @@ void launch_reduced(const ReducedDesc* d, int nitems, hipStream_t s);
 struct Reduced0Desc {
   const double* S;
   int ld, cap;
+  int ld_piece;      // column distance of the L pieces in S (0: 32)
   const int* m;
   int off_M, off_L, off_U;
   double dT;

@@ -26,12 +26,28 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
   __shared__ int order[kMaxN];
   __shared__ double sgn[kMaxN];
   __shared__ int m_sh;
+  // rows with an exactly zero diagonal (masked columns: a PSD Gram's zero
+  // diagonal means a zero row) hold eigenvalue 0 with eigenvector e_i; the
+  // rotations run on the other rows only, compacted (kid: compact ->
+  // original, kpos: original -> compact or -1)
+  __shared__ int kid[kMaxN], kpos[kMaxN];
+  __shared__ int nk_sh;
   const int tid = threadIdx.x;
   const int nc = d.nc;
-  const int N = nc + (nc & 1);
+  if (tid < 64) {
+    const bool v = tid < nc && d.G[(long long)tid * d.ldg + tid] != 0.0;
+    const unsigned long long mask = __ballot(v);
+    const int p = __popcll(mask & ((1ull << tid) - 1ull));
+    if (v) kid[p] = tid;
+    if (tid < nc) kpos[tid] = v ? p : -1;
+    if (tid == 0) nk_sh = __popcll(mask);
+  }
+  __syncthreads();
+  const int nk = nk_sh;
+  const int N = nk + (nk & 1);
   for (int e = tid; e < N * N; e += 256) {
     const int i = e / N, j = e % N;
-    A[i][j] = (i < nc && j < nc) ? d.G[(long long)i * d.ldg + j] : 0.0;
+    A[i][j] = (i < nk && j < nk) ? d.G[(long long)kid[i] * d.ldg + kid[j]] : 0.0;
     V[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -91,12 +107,13 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
     if (!rotated) break;
     __syncthreads();
   }
-  // descending order, ties by index
+  // descending order over all nc (original) indices, ties by index
+  auto val = [&](int i) -> double { const int p = kpos[i]; return p >= 0 ? A[p][p] : 0.0; };
   if (tid < nc) {
-    const double li = A[tid][tid];
+    const double li = val(tid);
     int rank = 0;
     for (int j = 0; j < nc; ++j) {
-      const double lj = A[j][j];
+      const double lj = val(j);
       if (lj > li || (lj == li && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -104,14 +121,20 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
   __syncthreads();
   if (tid < nc) {
     const int col = order[tid];
-    lam[tid] = A[col][col];
-    int kmax = 0;
-    double vmax = -1.0;
-    for (int k = 0; k < nc; ++k) {
-      const double v = fabs(V[k][col]);
-      if (v > vmax) { vmax = v; kmax = k; }
+    const int pc = kpos[col];
+    lam[tid] = val(col);
+    double sg = 1.0;
+    if (pc >= 0) {
+      // kid is increasing: the lowest compact index is the lowest original one
+      int kmax = 0;
+      double vmax = -1.0;
+      for (int k = 0; k < nk; ++k) {
+        const double v = fabs(V[k][pc]);
+        if (v > vmax) { vmax = v; kmax = k; }
+      }
+      sg = (V[kmax][pc] < 0.0) ? -1.0 : 1.0;
     }
-    sgn[tid] = (V[kmax][col] < 0.0) ? -1.0 : 1.0;
+    sgn[tid] = sg;
   }
   __syncthreads();
   if (tid == 0) {
@@ -141,10 +164,11 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
   const int m = m_sh;
   if (d.lambda)
     for (int i = tid; i < nc; i += 256) d.lambda[i] = lam[i];
+  // columns j < m have lam > 0, hence a kept (compact) eigenvector
   for (int e = tid; e < nc * d.ld_coef; e += 256) {
     const int c = e / d.ld_coef, j = e % d.ld_coef;
     double v = 0.0;
-    if (j < m) v = sgn[j] * V[c][order[j]] / sqrt(lam[j]);
+    if (j < m && kpos[c] >= 0) v = sgn[j] * V[kpos[c]][kpos[order[j]]] / sqrt(lam[j]);
     d.coef[e] = v;
   }
 }
@@ -424,13 +448,14 @@ __global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__
   __syncthreads();
   const int q = sh.q;
   const int np = d.forced ? d.npieces : 1;
+  const int ps = d.ld_piece > 0 ? d.ld_piece : 32;
   for (int e = tid; e < q * q; e += 256) {
     const int a = e / q, b = e % q;
     const double* row = d.S + (long long)sh.idx[a] * d.ld;
     sh.M[a][b] = row[d.off_M + sh.idx[b]];
     sh.K[a][b] = row[d.off_L + sh.idx[b]];
-    if (np > 1) sh.B[a][b] = row[d.off_L + 32 + sh.idx[b]];
-    if (np > 2) sh.T[a][b] = row[d.off_L + 64 + sh.idx[b]];
+    if (np > 1) sh.B[a][b] = row[d.off_L + ps + sh.idx[b]];
+    if (np > 2) sh.T[a][b] = row[d.off_L + 2 * ps + sh.idx[b]];
   }
   if (tid < d.n_in * q) {
     const int v = tid / q, a = tid % q;
@@ -489,13 +514,14 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   __syncthreads();
   const int q = sh.q;
   const int np = d.forced ? d.npieces : 1;
+  const int ps = d.ld_piece > 0 ? d.ld_piece : 32;
   for (int e = tid; e < q * q; e += 256) {
     const int a = e / q, b = e % q;
     const double* row = d.S + (long long)a * d.ld;
     sh.M[a][b] = row[d.off_M + b];
     sh.K[a][b] = row[d.off_L + b];
-    if (np > 1) sh.B[a][b] = row[d.off_L + 32 + b];
-    if (np > 2) sh.T[a][b] = row[d.off_L + 64 + b];
+    if (np > 1) sh.B[a][b] = row[d.off_L + ps + b];
+    if (np > 2) sh.T[a][b] = row[d.off_L + 2 * ps + b];
   }
   if (tid < q) sh.beta[0][tid] = d.S[(long long)tid * d.ld + d.off_U];
   if (d.forced && tid < np * q) sh.g[tid / q][tid % q] = d.S[(long long)(tid % q) * d.ld + d.off_F + tid / q];

@@ -42,6 +42,7 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
   const int xm0 = (x0 == 0) ? n - 1 : x0 - 1;
   T cm = in[(long long)xm0 * plane + q];
   T c0 = in[(long long)x0 * plane + q];
+#pragma unroll 4
   for (int x = x0; x < x1; ++x) {
     const int xp = (x == n - 1) ? 0 : x + 1;
     const long long base = (long long)x * plane;
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   const int q = tq * kTileQ + threadIdx.x;
   if (q >= n * n) return;
   const int j = q / n, k = q - (q / n) * n;
-  const int x0 = tx * kChunkX, x1 = min(n, x0 + kChunkX);
+  const int x0 = tx * d.chunk_x, x1 = min(n, x0 + d.chunk_x);
   const PR_GLOBAL T* in = gptr(d.in) + (long long)col * d.ld;
   PR_GLOBAL T* out = gptr(d.out) + (long long)col * d.ld;
   const bool valid = (d.mptr == nullptr) || (col < *d.mptr);
