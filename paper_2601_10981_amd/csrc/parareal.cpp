@@ -668,6 +668,9 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       const int n1 = std::min(Np, n0 + P.waveS);
       std::vector<PodWork> pw;
       std::vector<ApplyLWork> aw;
+      // a stage-1 basis has rank <= min(cap0, n_s): only those slots of each
+      // block enter W^k_n (the rest are masked out by the rank anyway)
+      const int r0max = std::min(cap0, P.n_s);
       for (int n = n0; n < n1; ++n) {
         PodWork w;
         w.prob = &S->P.prob;
@@ -675,13 +678,13 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           const int slot = std::min(k, j + 1) % 2;
           const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * P.cs;
           const int* mp = S->m0slot + slot * Np + j;
-          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+          for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
         }
         if (P.o.p >= 1 && k - 1 >= 1) {
           const int slot = (k - 1) % 2;
           const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * P.cs;
           const int* mp = S->m0slot + slot * Np + n;
-          for (int c0 = 0; c0 < cap0; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+          for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
         }
         w.gamma = P.o.gamma3;
         w.cap = cap;
