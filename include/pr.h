@@ -136,8 +136,13 @@ pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, v
  * floor(log2(batch)), steady or forced flows -- a batch mixing the two runs
  * as two launches per step) by timing one step of the first such batch in
  * each candidate tiling and x-chunk length (that first call synchronises
- * `stream`). The environment variables PR_FUSED_CFG=<index> (steady flows),
- * PR_FORCED_CFG=<index> (forced flows) and PR_FUSED_CHUNK=<policy> force one.
+ * `stream`). The chunk policies: 0 and 1 halve the chunk while a launch has
+ * fewer than 2048 / 768 workgroups; 2 takes the length of least modelled
+ * time, rounds of the workgroups the device holds at once times the planes
+ * each marches. The environment variables PR_FUSED_CFG=<index> (steady
+ * flows), PR_FORCED_CFG=<index> (forced flows) and PR_FUSED_CHUNK=<policy>
+ * force one; PR_TUNE_LOG=1 prints each tuning's timings (us per launch, by
+ * code = tiling + 8 x policy) to stderr.
  * pr_fine_tuned reports, for a key (forced = 1: the forced-flow stencil), the
  * workgroup's output tile (tile_y x tile_z points of the (y, z) plane), its
  * thread count and the x planes it marches through (for `batch` fields of

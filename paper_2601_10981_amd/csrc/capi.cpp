@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <set>
 
 #include "ctx.h"
 
@@ -339,10 +340,15 @@ int gram_chunk_rows(long long nrows) {
 
 // ---------------------------------------------------------------------------
 // fine propagator
-// Chunk-length policies of the fused stencil (fine_chunk): the least number
-// of workgroups a launch should have before chunks are halved.
+// Chunk-length policies of the fused stencil (fine_chunk). Policies 0 and 1
+// halve chunks while a launch has fewer than 2048 / 768 workgroups. Policy 2
+// takes the length of least modelled time, ceil(workgroups / resident
+// workgroups) x (planes + warm-up planes): a launch runs in rounds of the
+// workgroups the chip holds at once, each marching its whole chunk, so a
+// partly filled last round costs about a full one.
 constexpr int kChunkPolicies = 3;
-constexpr long long kChunkMinWgs[kChunkPolicies] = {2048, 768, 256};
+constexpr long long kChunkMinWgs[kChunkPolicies] = {2048, 768, -1};
+constexpr int kWarmPlanes = 6;   // planes a chunk marches before its first output
 
 // Tile configuration of the fused stencil: PR_FUSED_CFG=<index> forces one;
 // otherwise each (precision, largest grid, batch size class) is tuned once
@@ -374,19 +380,47 @@ static int forced_cfg_forced() {
 // Longer chunks re-read fewer warm-up planes (6 per chunk); shorter ones give
 // more workgroups. The tuner tries both policies.
 static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min_wgs,
-                      bool forced) {
+                      bool forced, long long slots) {
   int xc = forced ? kForcedChunk : kMaxChunk;
+  int nmax = 1;
   auto total = [&](int x) {
     long long t = 0;
     for (auto& w : items) {
       const long long ty = (w.prob->n + fused_ty(cfg) - 1) / fused_ty(cfg);
       const long long tz = (w.prob->n + fused_tz(cfg) - 1) / fused_tz(cfg);
       t += ty * tz * ((w.prob->n + x - 1) / x);
+      nmax = std::max(nmax, w.prob->n);
     }
     return t;
   };
-  while (xc > 8 && total(xc) < min_wgs) xc /= 2;
-  return xc;
+  if (min_wgs >= 0) {
+    while (xc > 8 && total(xc) < min_wgs) xc /= 2;
+    return xc;
+  }
+  int best = xc;
+  double best_cost = 0.0;
+  for (int x = xc; x >= 8; x /= 2) {
+    const long long rounds = (total(x) + slots - 1) / slots;
+    const double cost = (double)rounds * (std::min(x, nmax) + kWarmPlanes);
+    if (x == xc || cost < best_cost) {   // ties keep the longer chunk
+      best_cost = cost;
+      best = x;
+    }
+  }
+  return best;
+}
+
+// Workgroups of tiling cfg the device holds at once (cached per context).
+static long long resident_slots(const pr_ctx* c, int cfg, bool f32, bool forced) {
+  const int key = cfg * 4 + (f32 ? 1 : 0) + (forced ? 2 : 0);
+  auto it = c->fused_slots.find(key);
+  if (it != c->fused_slots.end()) return it->second;
+  if (c->n_cu <= 0)
+    PR_HIP(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int per_cu = forced ? forced_blocks_per_cu(cfg, f32) : fused_blocks_per_cu(cfg, f32);
+  const long long v = std::max<long long>(1, (long long)per_cu * std::max(1, c->n_cu));
+  c->fused_slots[key] = v;
+  return v;
 }
 
 // Descriptors of one launch shape: per-item buffers fixed in `base`, tiles
@@ -394,10 +428,13 @@ static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min
 // A launch shape: tiling kFusedCfgs[code % kNumFusedCfgs], chunk policy
 // code / kNumFusedCfgs.
 template <typename T>
-static long long shape_descs(const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
-                             int code, bool forced) {
+static long long shape_descs(pr_ctx* c, const std::vector<FineWork>& items,
+                             std::vector<FineDesc<T>>& d, int code, bool forced) {
   const int cfg = code % kNumFusedCfgs;
-  const int xc = fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs], forced);
+  const long long min_wgs = kChunkMinWgs[code / kNumFusedCfgs];
+  const long long slots =
+      min_wgs < 0 ? resident_slots(c, cfg, std::is_same<T, float>::value, forced) : 0;
+  const int xc = fine_chunk(items, cfg, min_wgs, forced, slots);
   long long tiles = 0;
   for (size_t i = 0; i < items.size(); ++i) {
     const int n = items[i].prob->n;
@@ -442,10 +479,10 @@ static std::string tune_key(int value_bytes, int nmax, int batch, bool forced) {
 // Launch shapes the tuner tries: every tiling (the forced stencil: those of
 // kForcedCfgs; in FP64 not a 1024-thread one with two columns per thread,
 // whose four waves per SIMD leave too few registers) under every chunk
-// policy.
+// policy, the modelled one first.
 static std::vector<int> shape_codes(bool forced, int value_bytes) {
   std::vector<int> v;
-  for (int pol = 0; pol < kChunkPolicies; ++pol) {
+  for (int pol = kChunkPolicies - 1; pol >= 0; --pol) {
     if (forced) {
       for (int i = 0; i < kNumForcedCfgs; ++i)
         if (!(value_bytes == 8 && kFusedCfgs[kForcedCfgs[i]].nt > 512 &&
@@ -458,12 +495,16 @@ static std::vector<int> shape_codes(bool forced, int value_bytes) {
   return v;
 }
 
-// Autotuner: time step 0 of the actual batch in every configuration (one
-// warm-up and kTuneReps timed launches each) and keep the fastest for this
-// key.
+// Autotuner: time step 0 of the actual batch in every launch shape (one
+// warm-up and kTuneReps timed launches each), then time the kTuneFinal
+// fastest again in kTuneRounds interleaved rounds (so a clock change during
+// tuning hits every finalist alike), each keeping its fastest launch, and keep
+// the fastest finalist for this key.
 // Step 0 reads the inputs and writes buffers no other step 0 reads, so
 // repeating it is harmless; every configuration gives bitwise the same
-// values. Synchronises `s` once, at the first batch of a key.
+// values. Synchronises `s` at the first batch of a key.
+constexpr int kTuneFinal = 4;
+constexpr int kTuneRounds = 6;
 template <typename T>
 static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
                      bool forced, hipStream_t s) {
@@ -473,27 +514,53 @@ static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
   hipEvent_t e0 = event_get(c), e1 = event_get(c);
-  float best_ms = 0;
   const std::vector<int> codes = shape_codes(forced, (int)sizeof(T));
-  int best = codes[0];
-  for (size_t ic = 0; ic < codes.size(); ++ic) {
-    const int code = codes[ic];
+  auto time_code = [&](int code, int reps) {
     const int cfg = code % kNumFusedCfgs;
-    const long long tiles = shape_descs<T>(items, d, code, forced);
+    const long long tiles = shape_descs<T>(c, items, d, code, forced);
     FineDesc<T>* dd = stage_push(c, d);
     stage_flush(c, s);
     launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
     PR_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < kTuneReps; ++r)
-      launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
+    for (int r = 0; r < reps; ++r) launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
     PR_HIP(hipEventRecord(e1, s));
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0;
     PR_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ic == 0 || ms < best_ms) {
-      best_ms = ms;
-      best = code;
+    return ms / reps;
+  };
+  // a policy giving a launch already timed (same tiling and workgroup count,
+  // hence the same chunk length) is not timed again: the earlier code keeps it
+  std::set<std::pair<int, long long>> seen;
+  std::vector<std::pair<float, int>> timed;   // (ms per launch, code), in code order
+  for (const int code : codes) {
+    const long long tiles = shape_descs<T>(c, items, d, code, forced);
+    if (!seen.insert({code % kNumFusedCfgs, tiles}).second) continue;
+    timed.push_back({time_code(code, kTuneReps), code});
+  }
+  std::stable_sort(timed.begin(), timed.end(),
+                   [](const std::pair<float, int>& a, const std::pair<float, int>& b) {
+                     return a.first < b.first;
+                   });
+  const int nf = std::min<int>(kTuneFinal, (int)timed.size());
+  std::vector<float> fin(nf, 0.0f);
+  for (int r = 0; r < kTuneRounds; ++r)
+    for (int i = 0; i < nf; ++i) {
+      const float ms = time_code(timed[i].second, 1);
+      if (r == 0 || ms < fin[i]) fin[i] = ms;
     }
+  int bi = 0;
+  for (int i = 1; i < nf; ++i)
+    if (fin[i] < fin[bi]) bi = i;
+  const int best = timed[bi].second;
+  const char* lg = getenv("PR_TUNE_LOG");
+  if (lg && *lg && *lg != '0') {
+    // diagnostics: every shape's first-pass time, then the finalists'
+    std::fprintf(stderr, "tune %s:", key.c_str());
+    for (auto& t : timed) std::fprintf(stderr, " %d=%.1f", t.second, 1000.0f * t.first);
+    std::fprintf(stderr, " | final:");
+    for (int i = 0; i < nf; ++i) std::fprintf(stderr, " %d=%.1f", timed[i].second, 1000.0f * fin[i]);
+    std::fprintf(stderr, " -> %d\n", best);
   }
   event_put(c, e0);
   event_put(c, e1);
@@ -553,7 +620,7 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, bool force
     int code = forced ? forced_cfg_forced() : forced_cfg();
     if (code < 0) code = tune_fine<T>(c, items, descs, forced, s);
     const int cfg = code % kNumFusedCfgs;
-    const long long tiles = shape_descs<T>(items, descs, code, forced);
+    const long long tiles = shape_descs<T>(c, items, descs, code, forced);
     FineDesc<T>* dd = stage_push(c, descs);
     stage_flush(c, s);
     if (forced) {
@@ -1183,7 +1250,10 @@ pr_status pr_fine_tuned(const pr_ctx* c, int precision, int forced, int n, int b
     pr_grid_problem p{};
     p.n = n;
     const std::vector<FineWork> items(batch, FineWork{&p, 0.0, 0, nullptr, nullptr, 0, nullptr});
-    *planes = std::min(n, fine_chunk(items, cfg, kChunkMinWgs[code / kNumFusedCfgs], forced != 0));
+    const long long min_wgs = kChunkMinWgs[code / kNumFusedCfgs];
+    const long long slots =
+        min_wgs < 0 ? resident_slots(c, cfg, precision == PR_MIXED, forced != 0) : 0;
+    *planes = std::min(n, fine_chunk(items, cfg, min_wgs, forced != 0, slots));
   }
   return PR_OK;
 }

@@ -26,6 +26,10 @@ struct pr_ctx {
   std::multimap<size_t, void*> pool;
   std::map<std::string, void*> tables;   // velocity tables by problem key
   std::map<std::string, int> tuned;      // fused-stencil configuration by batch key
+  // resident stencil workgroups by tiling and the device's compute units
+  // (caches filled on first use, also through const queries)
+  mutable std::map<int, long long> fused_slots;
+  mutable int n_cu = 0;
 
   // Descriptor staging: a ring of pinned host slots mirrored by device slots.
   static constexpr int kSlots = 8;

@@ -295,6 +295,30 @@ static void launch_forced_impl(const FineDesc<T>* d, int nd, long long total, in
   }
 }
 
+template <typename T, int TY, int TZ, int NT>
+static int occ_forced_cfg() {
+  int n = 0;
+  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rk4_forced<T, TY, TZ, NT>, NT, 0));
+  return n;
+}
+
+template <typename T>
+static int occ_forced_impl(int cfg) {
+  switch (cfg) {
+    case 2: return occ_forced_cfg<T, 16, 32, 512>();
+    case 3: return occ_forced_cfg<T, 32, 32, 1024>();
+    case 4: return occ_forced_cfg<T, 8, 32, 256>();
+    case 6: return occ_forced_cfg<T, 8, 64, 512>();
+    case 7: return occ_forced_cfg<T, 16, 32, 1024>();
+    default: fail(PR_EINVAL, "tiling not available for the forced-flow stencil");
+  }
+  return 0;
+}
+
+int forced_blocks_per_cu(int cfg, bool f32) {
+  return f32 ? occ_forced_impl<float>(cfg) : occ_forced_impl<double>(cfg);
+}
+
 void launch_forced_step_f64(const FineDesc<double>* d, int nd, long long total, int step, int cfg,
                             hipStream_t s) {
   launch_forced_impl<double>(d, nd, total, step, cfg, s);

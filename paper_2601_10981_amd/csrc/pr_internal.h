@@ -243,6 +243,10 @@ void launch_forced_step_f64(const FineDesc<double>* d_descs, int nfields, long l
                             int step, int cfg, hipStream_t s);
 void launch_forced_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
                             int step, int cfg, hipStream_t s);
+// Workgroups of a tiling resident per CU at once (registers, LDS, threads),
+// from the runtime's occupancy calculator.
+int fused_blocks_per_cu(int cfg, bool f32);
+int forced_blocks_per_cu(int cfg, bool f32);
 // f_j of piece j of a forced flow written as an N_g field (double or float).
 void launch_forcing_field(const Geom& g, int piece, void* out, int out_f32, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, long long n, hipStream_t s);

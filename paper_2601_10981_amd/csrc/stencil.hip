@@ -337,6 +337,33 @@ static void launch_step_impl(const FineDesc<T>* d, int nd, long long total, int 
   }
 }
 
+template <typename T, int TY, int TZ, int NT>
+static int occ_cfg() {
+  int n = 0;
+  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rk4_fused<T, TY, TZ, NT>, NT, 0));
+  return n;
+}
+
+template <typename T>
+static int occ_impl(int cfg) {
+  switch (cfg) {
+    case 0: return occ_cfg<T, 32, 32, 512>();
+    case 1: return occ_cfg<T, 16, 32, 256>();
+    case 2: return occ_cfg<T, 16, 32, 512>();
+    case 3: return occ_cfg<T, 32, 32, 1024>();
+    case 4: return occ_cfg<T, 8, 32, 256>();
+    case 5: return occ_cfg<T, 16, 64, 512>();
+    case 6: return occ_cfg<T, 8, 64, 512>();
+    case 7: return occ_cfg<T, 16, 32, 1024>();
+    default: fail(PR_EINVAL, "unknown fused stencil configuration");
+  }
+  return 0;
+}
+
+int fused_blocks_per_cu(int cfg, bool f32) {
+  return f32 ? occ_impl<float>(cfg) : occ_impl<double>(cfg);
+}
+
 void launch_fine_step_f64(const FineDesc<double>* d, int nd, long long total, int step, int cfg,
                           hipStream_t s) {
   launch_step_impl<double>(d, nd, total, step, cfg, s);
