@@ -140,7 +140,22 @@ def test_forced_stability_bound(ctx):
     assert e.value.name == "PR_EUNSTABLE"
 
 
-def _coarse_setup(n, flow, kappa, cap, seed=3, t0=0.0):
+def _coarse_setup_wide(n, flow, kappa, m, seed=3, t0=0.0):
+    """An M-orthonormal basis of m smooth Fourier fields (any basis serves the
+    coarse propagator) and states from a fine trajectory outside its span."""
+    op = fd.Operator(n, kappa, flow, PAPER)
+    h3 = op.h ** 3
+    F = np.stack([W.fourier_field(n, seed + 11 * i, n_modes=4, kmax=2.5).reshape(-1)
+                  for i in range(m)], axis=1)
+    Q, _ = np.linalg.qr(F)
+    R = Q / np.sqrt(h3)
+    u0 = W.fourier_field(n, seed, n_modes=8, kmax=3.0)
+    U1, _ = fd.fine_propagate(op, u0, 0.01, 40, t0=t0)
+    U2 = U1 + 0.05 * W.random_field(n, seed + 7)
+    return op, h3, R, U1.reshape(-1), U2.reshape(-1)
+
+
+def _coarse_setup_smooth(n, flow, kappa, cap, seed=3, t0=0.0):
     op = fd.Operator(n, kappa, flow, PAPER)
     h3 = op.h ** 3
     u0 = W.fourier_field(n, seed, n_modes=8, kmax=3.0)
@@ -158,7 +173,7 @@ def test_forced_coarse_parity(ctx, flow, t0, dT, n_c):
     import paper_2601_10981_amd as pr
     say(f"forced coarse flow={flow} t0={t0}")
     n, cap, kappa = 12, 10, 0.05
-    op, h3, R, m, U1, U2 = _coarse_setup(n, flow, kappa, cap, t0=t0)
+    op, h3, R, m, U1, U2 = _coarse_setup_smooth(n, flow, kappa, cap, t0=t0)
     Psi, aug = coarse.augment(R, U1, h3)
     assert aug
     lifted, betas, nc = coarse.coarse_propagate(op, Psi, [U1, U2], dT, n_c, h3, t0=t0)
@@ -180,6 +195,43 @@ def test_forced_coarse_parity(ctx, flow, t0, dT, n_c):
     for i in range(2):
         bg = np.concatenate([b[i, :m], b[i, cap:cap + 1]])
         assert np.max(np.abs(bg - betas[i])) <= 1e-11 * np.max(np.abs(betas[i]))
+
+
+@pytest.mark.parametrize("flow", [KT, AT, W.FLOW_ABC], ids=["kolmogorov", "abc", "abc_steady"])
+@pytest.mark.parametrize("cap", [20, 31])
+def test_coarse_parity_wide_basis(ctx, flow, cap):
+    """Bases of more than 16 columns: two MFMA tiles of basis columns, and
+    the Galerkin blocks of every time-space piece packed up to nine tiles
+    (31 columns, three pieces); the rank m = cap - 2 fills both tiles."""
+    import torch
+    import paper_2601_10981_amd as pr
+    n, kappa, t0, dT, n_c = 12, 0.05, 1.3, 0.3, 3
+    m = cap - 2
+    op, h3, R, U1, U2 = _coarse_setup_wide(n, flow, kappa, m, t0=t0)
+    say(f"forced coarse wide basis flow={flow} cap={cap} m={m}")
+    Psi, aug = coarse.augment(R, U1, h3)
+    lifted, betas, nc = coarse.coarse_propagate(op, Psi, [U1, U2], dT, n_c, h3, t0=t0)
+    Rp = np.zeros((n ** 3, cap))
+    Rp[:, :m] = R
+    ins = [to_dev(U1), to_dev(U2)]
+    outs = [torch.empty_like(x) for x in ins]
+    beta = torch.zeros((2, cap + 1), dtype=torch.float64, device="cuda")
+    nco = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pr.pr_coarse_propagate(ctx, [dict(prob=pr.problem(n, kappa, flow, PAPER), R=to_dev(Rp.T),
+                                      cap=cap, m=torch.tensor([m], dtype=torch.int32, device="cuda"),
+                                      u_in=ins, dT_total=dT, n_c=n_c, u_out=outs, beta_out=beta,
+                                      n_c_out=nco, u_aug=to_dev(U1), t0=t0)])
+    torch.cuda.synchronize()
+    assert int(nco.item()) == nc
+    # the basis is M-orthonormal to rounding, so the reduced solve is well
+    # conditioned; the bound covers the Galerkin sums over 12^3 rows
+    for o, l in zip(outs, lifted):
+        assert rel_l2(to_np(o), l) <= 1e-10
+    b = to_np(beta)
+    for i in range(2):
+        q = m + (1 if aug else 0)
+        bg = np.concatenate([b[i, :m], b[i, cap:cap + 1]])[:q]
+        assert np.max(np.abs(bg - betas[i])) <= 1e-10 * np.max(np.abs(betas[i]))
 
 
 def gpu_serial(ctx, prob, opts, u0):
