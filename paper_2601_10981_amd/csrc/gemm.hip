@@ -34,6 +34,29 @@ __device__ __forceinline__ In load_col(const void* p, int f32, long long row) {
   return f32 ? (In)gptr((const float*)p)[row] : (In)gptr((const double*)p)[row];
 }
 
+typedef double v2d_t __attribute__((ext_vector_type(2)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+// Rows row .. row + 3 of a column in vector loads: row a multiple of 4 and
+// the column base 16-byte aligned (checked by the caller).
+template <typename In>
+__device__ __forceinline__ void load_col4(const void* p, int f32, long long row, In* v) {
+  if (f32) {
+    const v4f_t a = *(const PR_GLOBAL v4f_t*)(gptr((const float*)p) + row);
+    v[0] = (In)a.x;
+    v[1] = (In)a.y;
+    v[2] = (In)a.z;
+    v[3] = (In)a.w;
+  } else {
+    const v2d_t a = *(const PR_GLOBAL v2d_t*)(gptr((const double*)p) + row);
+    const v2d_t b = *(const PR_GLOBAL v2d_t*)(gptr((const double*)p) + row + 2);
+    v[0] = (In)a.x;
+    v[1] = (In)a.y;
+    v[2] = (In)b.x;
+    v[3] = (In)b.y;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // MFMA 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16]
 // and B[l / 16][l % 16]; the 16x16 result has lane l holding, in its
@@ -139,7 +162,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   const int tB = NB == 0 ? tA : (s_cnt[1] + 15) >> 4;
   const void* cp[NT];
   int cf[NT];
-  bool cv[NT];
+  bool cv[NT], c16[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int slot = (t < NA) ? t * 16 + ci : (t - NA) * 16 + ci;
@@ -148,6 +171,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
     const ColDesc c = d.cols[cv[t] ? s_src[t * 16 + ci] : 0];
     cp[t] = c.ptr;
     cf[t] = c.f32;
+    c16[t] = ((unsigned long long)c.ptr & 15ull) == 0;
   }
 
   v4d acc[P];
@@ -172,10 +196,17 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bool act = (t < NA) ? t < tA : t - NA < tB;
+        const long long rb = r0 + 4 * kq + u0;
+        // vector loads pay in the symmetric (POD) Grams; the sweep's one-item
+        // Galerkin products measured slower with them
+        if (UL == 4 && NB == 0 && act && cv[t] && c16[t] && rb + 3 < r_end) {
+          load_col4<In>(cp[t], cf[t], rb, v[t]);
+        } else {
 #pragma unroll
-        for (int u = 0; u < UL; ++u) {
-          const long long row = r0 + 4 * kq + u0 + u;
-          v[t][u] = (act && cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+          for (int u = 0; u < UL; ++u) {
+            const long long row = rb + u;
+            v[t][u] = (act && cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+          }
         }
       }
 #pragma unroll
