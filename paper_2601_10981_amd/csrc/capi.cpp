@@ -707,11 +707,11 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
   if (items.empty()) return;
   const bool f32 = items[0].prob->precision == PR_MIXED;
   long long tiles = 0;
-  // x planes per workgroup: kChunkX, or a quarter of it when that leaves a
-  // launch (one column of L d in the sweep) under 2048 workgroups
+  // x planes per workgroup: kChunkX, or 4 when that leaves a launch (one
+  // column of L d in the sweep) under 2048 workgroups
   long long wide = 0;
   for (auto& w : items) wide += (long long)tiles_q(w.prob->n) * tiles_x(w.prob->n) * w.ncols;
-  const int cx = wide < 2048 ? kChunkX / 4 : kChunkX;
+  const int cx = wide < 2048 ? 4 : kChunkX;
   if (f32) {
     std::vector<ApplyLDesc<float>> d;
     for (auto& w : items) {

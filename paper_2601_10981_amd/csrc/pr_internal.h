@@ -33,7 +33,7 @@ struct Error {
   } while (0)
 
 constexpr int kTileQ = 256;     // stencil: (y, z) points per workgroup
-constexpr int kChunkX = 16;     // stencil: x planes per workgroup
+constexpr int kChunkX = 32;     // L applied to columns: x planes per workgroup
 constexpr int kMaxPodCols = 64;  // columns of one POD input (4 MFMA tiles)
 constexpr int kMaxCap = 31;      // basis columns; cap + 1 fits two MFMA tiles
 constexpr double kTauRankF64 = 1e-13;

@@ -1,9 +1,9 @@
 """GPU parity of the fine propagator (pr_fine_propagate) against the oracle.
 
 FP64: relative L2 <= 1e-12 per field and per snapshot; FP32 stencil (mixed):
-<= 1e-5. Shapes span several tiles with ragged tails (n = 20: n^2 = 400 is
-not a multiple of the 256-point tile and 20 planes split 16 + 4; n = 33 is
-odd). Batches mix sizes, flows, steps and dt in one launch.
+<= 1e-5. Shapes span several tiles with ragged tails (n = 20 leaves partial
+(y, z) tiles and, at 16-plane chunks, an x split 16 + 4; n = 33 is odd).
+Batches mix sizes, flows, steps and dt in one launch.
 """
 import math
 
