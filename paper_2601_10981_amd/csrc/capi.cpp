@@ -1229,6 +1229,7 @@ void pr_ctx_destroy(pr_ctx* c) {
   }
   if (c->host_scalars) (void)hipHostFree(c->host_scalars);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }
 

@@ -40,6 +40,7 @@ struct pr_ctx {
   int slot = -1;
   size_t off = 0, flushed = 0;
   hipStream_t stream = nullptr;   // stream of the current staging session
+  hipStream_t aux = nullptr;      // second stream of the solver (created on first use)
 
   // Small pinned host buffer for scalars read back by the solver.
   double* host_scalars = nullptr;

@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "ctx.h"
@@ -508,11 +509,23 @@ static void iterate_batch(pr_ctx* c, const std::vector<pr_solve*>& ss, hipStream
   }
 }
 
+// Parts a sweep wave is cut into (PR_SWEEP_PARTS, default 4; 1 runs the
+// stage-2 POD of the whole wave before its sweep), each of at least
+// kMinPartItems subintervals.
+constexpr int kMinPartItems = 4;
+static int sweep_parts() {
+  const char* e = getenv("PR_SWEEP_PARTS");
+  const int v = (e && *e) ? atoi(e) : 4;
+  return std::max(1, std::min(v, 16));
+}
+
 static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hipStream_t s) {
   PhaseEvents shared;  // phases shared by the batch are charged to each solve
   shared.c = c;
   shared.s = s;
   std::vector<PhaseEvents> own(live.size());
+  std::vector<PhaseEvents> aux_ph(live.size());   // work on the auxiliary stream
+  std::vector<hipEvent_t> used_events;
   stage_begin(c, s);
   for (auto* S : live) ++S->k;
 
@@ -663,15 +676,19 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         enqueue_coarse(c, w, s, &ph);
       }
     }
-    // (ii) + (iv)
+    // (ii) + (iv). A wave is cut into parts: the stage-2 POD and L Psi of
+    // part i + 1 run on the auxiliary stream while the sweep crosses part i
+    // (they read only the stage-1 bases, and each part has its own Psi,
+    // L Psi and rank slots); the sweep of a part waits for its preparation.
     for (int n0 = k; n0 < Np && !P.fixed && !P.grid; n0 += P.waveS) {
       const int n1 = std::min(Np, n0 + P.waveS);
-      std::vector<PodWork> pw;
-      std::vector<ApplyLWork> aw;
       // a stage-1 basis has rank <= min(cap0, n_s): only those slots of each
       // block enter W^k_n (the rest are masked out by the rank anyway)
       const int r0max = std::min(cap0, P.n_s);
-      for (int n = n0; n < n1; ++n) {
+      auto prep = [&](int a, int b, hipStream_t st, PhaseEvents& pe) {
+      std::vector<PodWork> pw;
+      std::vector<ApplyLWork> aw;
+      for (int n = a; n < b; ++n) {
         PodWork w;
         w.prob = &S->P.prob;
         for (int j = std::max(0, n - P.o.ml); j <= n; ++j) {
@@ -700,18 +717,44 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
                                   S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * P.cs, cap,
                                   w.m_out, jp, P.ld, 1});
       }
-      ph.begin(1);
+      pe.begin(1);
       for (int na = 1; na <= 4; ++na) {
         std::vector<PodWork> g;
         for (auto& x : pw)
           if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
-        if (!g.empty()) enqueue_pod(c, g, s, "sol_pod");
+        if (!g.empty()) enqueue_pod(c, g, st, "sol_pod");
       }
-      ph.begin(2);
-      enqueue_applyL_batch(c, aw, s);
-      PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + n0, S->mS, (size_t)(n1 - n0) * 4,
-                            hipMemcpyDeviceToDevice, s));
-      for (int n = n0; n < n1; ++n) {
+      pe.begin(2);
+      enqueue_applyL_batch(c, aw, st);
+      PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + a, S->mS + (a - n0), (size_t)(b - a) * 4,
+                            hipMemcpyDeviceToDevice, st));
+      pe.end();
+      };
+      const int nparts = std::max(1, std::min(sweep_parts(), (n1 - n0) / kMinPartItems));
+      std::vector<int> cut;
+      for (int i = 0; i <= nparts; ++i) cut.push_back(n0 + (int)((long long)(n1 - n0) * i / nparts));
+      std::vector<hipEvent_t> ready(nparts, nullptr);
+      prep(cut[0], cut[1], s, ph);
+      if (nparts > 1) {
+        if (!c->aux) PR_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+        aux_ph[si].c = c;
+        aux_ph[si].s = c->aux;
+        // the auxiliary stream follows everything enqueued on s so far (the
+        // stage-1 bases, and the first part's use of the POD scratch)
+        hipEvent_t go = event_get(c);
+        PR_HIP(hipEventRecord(go, s));
+        PR_HIP(hipStreamWaitEvent(c->aux, go, 0));
+        used_events.push_back(go);
+        for (int i = 1; i < nparts; ++i) {
+          prep(cut[i], cut[i + 1], c->aux, aux_ph[si]);
+          ready[i] = event_get(c);
+          PR_HIP(hipEventRecord(ready[i], c->aux));
+          used_events.push_back(ready[i]);
+        }
+      }
+      for (int i = 0; i < nparts; ++i) {
+      if (ready[i]) PR_HIP(hipStreamWaitEvent(s, ready[i], 0));
+      for (int n = cut[i]; n < cut[i + 1]; ++n) {
         CoarseWork w{};
         w.prob = &S->P.prob;
         w.R = S->Psi + (size_t)(n - n0) * cap * P.cs;
@@ -738,6 +781,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.norms4 = S->norms + 4 * (n + 1);
         enqueue_coarse(c, w, s, &ph);
       }
+      }
     }
     ph.end();
     // (v) jump and error
@@ -746,12 +790,14 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
     PR_HIP(hipMemcpyAsync(S->host, S->dscal, 4 * 8, hipMemcpyDeviceToHost, s));
   }
   stage_end(c, s);
-  PR_HIP(hipStreamSynchronize(s));
+  PR_HIP(hipStreamSynchronize(s));   // s waited for every auxiliary part
+  for (hipEvent_t e : used_events) event_put(c, e);
   shared.collect();
   for (size_t si = 0; si < live.size(); ++si) {
     pr_solve* S = live[si];
     own[si].collect();
-    for (int i = 0; i < 5; ++i) S->t_phase[i] += own[si].t[i] + shared.t[i];
+    aux_ph[si].collect();
+    for (int i = 0; i < 5; ++i) S->t_phase[i] += own[si].t[i] + aux_ph[si].t[i] + shared.t[i];
     const double e_k = S->host[0], err_k = S->host[3];
     S->jump.push_back(e_k);
     S->err.push_back(err_k);
