@@ -107,7 +107,7 @@ const char* pr_last_error(const pr_ctx* ctx);
 size_t pr_ctx_scratch_bytes(const pr_ctx* ctx);
 
 /* ---------------------------------------------------------------------------
- * Fine propagator F (Sec. 2; Algorithm 2, line 8; snapshot matrix W of
+ * Fine propagator F (Sec. 2; Algorithm 2, fine step; snapshot matrix W of
  * Sec. 3.2 Case I): n_steps RK4 steps of size dt from u_in, for every item of
  * the batch in the same launches (items may differ in n, flow, kappa, dt and
  * n_steps but share the precision).

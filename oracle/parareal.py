@@ -6,18 +6,18 @@ in the paper's runs), so the parareal partition of [T_0, T] has N' = N - 1
 subintervals and states U_n at t_hat_n = (n + 1) DeltaT, n = 0..N'. U_0 is the
 fine solution at T_0 (u_hat_0 of Case I).
 
-k = 0 (Algorithm 2, lines 3-5): fine solve on [0, T_0] with snapshots,
+k = 0 (Algorithm 2, initialisation): fine solve on [0, T_0] with snapshots,
 POD_Mode(W, gamma_1) gives G_0, and U^0_{n+1} = G_0(P U^0_n).
 
-k >= 1 (lines 7-19):
-  (i)   F(U^{k-1}_n) and the snapshots W^k_{n,0} for n = k-1..N'-1 (line 8);
-        POD_Mode(W^k_{n,0}, gamma_2) -> R^k_{n,0} (line 9).
+k >= 1 (Algorithm 2, the iteration):
+  (i)   F(U^{k-1}_n) and the snapshots W^k_{n,0} for n = k-1..N'-1;
+        POD_Mode(W^k_{n,0}, gamma_2) -> R^k_{n,0}.
   (ii)  W^k_n = [R_{n-m_l,0} .. R_{n,0} (latest iteration of each),
         R^{k-1}_{n,0} .. R^{k-p}_{n,0}]; blocks with index < 0 or iteration
-        < 1 are omitted; POD_Mode(W^k_n, gamma_3) -> R^k_n (line 10).
+        < 1 are omitted; POD_Mode(W^k_n, gamma_3) -> R^k_n.
   (iii) U^k_j = U^{k-1}_j for j < k and U^k_k = F(U^{k-1}_{k-1}): the two
         coarse terms cancel there because U^k_{k-1} = U^{k-1}_{k-1}.
-  (iv)  sequentially for n = k..N'-1 (lines 12-17): augment R^k_n with U^k_n
+  (iv)  sequentially for n = k..N'-1 (the sweep): augment R^k_n with U^k_n
         (eq12), then U^k_{n+1} = G(P U^k_n) + F(U^{k-1}_n) - G(P U^{k-1}_n).
   (v)   stopping ("while not converged" is unspecified): the jump
         e_k = max_{n>=1} ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M <= tol, or

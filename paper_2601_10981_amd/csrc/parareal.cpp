@@ -10,14 +10,14 @@
 // Per iteration k >= 1:
 //   (i)   fine solves F(U^{k-1}_n) with snapshots for n = k-1..N'-1, batched
 //         in waves (and across solves), and POD_Mode(gamma_2) of each
-//         snapshot set (Alg. 2 lines 8-9)
+//         snapshot set (Algorithm 2, fine step and first POD)
 //   (ii)  POD_Mode(gamma_3) of W^k_n = [R_{n-m_l,0} .. R_{n,0}, R^{k-1}_{n,0}]
-//         batched over n, and L applied to the modes (Alg. 2 lines 9-10)
+//         batched over n, and L applied to the modes (Algorithm 2, second POD)
 //   (iii) U^k_j = U^{k-1}_j (j < k) and U^k_k = F_{k-1} (the coarse terms
 //         cancel there)
 //   (iv)  the sequential sweep n = k..N'-1: augmentation by U^k_n (eq12),
 //         Galerkin system of eq13, RK4 of both projections and the
-//         correction of formula4 with jump partials (Alg. 2 lines 12-17)
+//         correction of formula4 with jump partials (Algorithm 2, the sweep)
 //   (v)   e_k = max_n ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M read back (8 B)
 // The basis of subinterval j last computed at iteration min(k, j + 1) sits
 // in slot min(k, j + 1) % 2 of a two-slot ring, which also holds
@@ -299,7 +299,7 @@ static void enqueue_grid_step(pr_ctx* c, pr_solve* S, const double* a, const dou
   launch_norm_reduce(nrd, 1, s);
 }
 
-// Allocate the solve, enqueue k = 0 (Alg. 2 lines 3-5) and synchronise.
+// Allocate the solve, enqueue k = 0 (Algorithm 2, initialisation) and synchronise.
 static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_parareal_opts* opts,
                              const double* u0, double* U_out, hipStream_t s) {
   PR_CHECK(u0 != nullptr, "null initial field");
