@@ -1064,11 +1064,10 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     a3.c = S2;
     a3.z = dtil;
     a3.norm = S3;
+    a3.nu2 = S1 + 32;     // with the decision on d~ (eqaug's degenerate case)
+    a3.flag = flag;
+    a3.dscale = dscale;
     launch_cgs(a3, s);
-    AugDesc a{S3, S1 + 32, flag, dscale, w.m, nullptr};
-    AugDesc* ad = stage_push1(c, a);
-    stage_flush(c, s);
-    launch_aug_decide(ad, 1, s);
     launch_scale_into(dtil, dcol, f32, ng, dscale, s);
     aug = flag;
     P.begin(2);
@@ -1133,9 +1132,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   rd.coef = coef;
   rd.n_c_out = w.n_c_out;
   rd.status = status;
-  ReducedDesc* rdd = stage_push1(c, rd);
-  stage_flush(c, s);
-  launch_reduced(rdd, 1, s);
+  launch_reduced_one(rd, s);
   std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
   if (w.diag_norms && w.n_in == 2 && w.fine) {
     // coarse-gap diagnostics: F(U_old) - G(U_old) and U_ref - G(U_new) with

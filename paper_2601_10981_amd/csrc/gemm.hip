@@ -720,8 +720,19 @@ __global__ __launch_bounds__(256) void k_cgs_reduce(const CgsArgs a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    if (j == a.n) *gptr(a.norm) = a.scale * red[0];
-    else gptr(a.dots)[j] = a.scale * red[0];
+    if (j == a.n) {
+      const double nd2 = a.scale * red[0];
+      *gptr(a.norm) = nd2;
+      if (a.flag) {
+        // the degenerate-augmentation test (||d~|| <= tau ||u||), squared
+        const double nu2 = *gptr(a.nu2);
+        const int flag = (nd2 > 0.0 && nd2 > kTauAug * kTauAug * nu2) ? 1 : 0;
+        *gptr(a.flag) = flag;
+        *gptr(a.dscale) = flag ? 1.0 / sqrt(nd2) : 0.0;
+      }
+    } else {
+      gptr(a.dots)[j] = a.scale * red[0];
+    }
   }
 }
 
@@ -763,6 +774,7 @@ void launch_cgs(const CgsArgs& a, hipStream_t s) {
   if (a.nchunks <= 0) return;
   const bool dots = a.dots != nullptr, sub = a.c != nullptr;
   PR_CHECK(dots || sub, "cgs: a pass without coefficients returns the dots");
+  PR_CHECK(!a.flag || (a.nu2 && a.dscale), "cgs: the augmentation decision needs nu2 and dscale");
   if (dots && sub) cgs_width<true, true>(a, s);
   else if (dots) cgs_width<true, false>(a, s);
   else cgs_width<false, true>(a, s);

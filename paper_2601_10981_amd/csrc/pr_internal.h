@@ -282,6 +282,11 @@ struct CgsArgs {
   double* dots;        // nullptr, or n doubles
   double* norm;        // one double
   double scale;
+  // nullptr, or the augmentation decision taken from norm (||d~||_M^2) and
+  // *nu2 (||u||_M^2): *flag = 1 and *dscale = 1 / ||d~||_M if d~ is kept
+  const double* nu2;
+  int* flag;
+  double* dscale;
 };
 int cgs_chunk_rows(long long nrows);
 void launch_cgs(const CgsArgs& a, hipStream_t s);
@@ -341,6 +346,7 @@ struct ReducedDesc {
   int* status;       // nullable: set to 1 if M_r is not positive definite
 };
 void launch_reduced(const ReducedDesc* d, int nitems, hipStream_t s);
+void launch_reduced_one(const ReducedDesc& d, hipStream_t s);
 
 // k = 0 recurrence: beta_{n+1} = S^{n_c} beta_n for n = 0..count-1 written
 // into coef rows (count x ld_out) for the lift.
@@ -361,18 +367,6 @@ struct Reduced0Desc {
 };
 void launch_reduced0(const Reduced0Desc* d, hipStream_t s);
 
-// Augmentation helpers.
-// aug_decide: given c2 = ||d~||_M^2 and u2 = ||u||_M^2 (from partial sums),
-// set flag and scale = 1/||d~||_M (or 0).
-struct AugDesc {
-  const double* nd2;   // device scalar
-  const double* nu2;   // device scalar
-  int* flag;
-  double* scale;
-  const int* m;        // R columns valid
-  int* m_aug;          // m + flag
-};
-void launch_aug_decide(const AugDesc* d, int nitems, hipStream_t s);
 // out[i] = -in[i], i < n (one small vector, n <= 256).
 void launch_negate(const double* in, double* out, int n, hipStream_t s);
 

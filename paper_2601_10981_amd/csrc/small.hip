@@ -432,8 +432,7 @@ __device__ void red_advance(RedShared& sh, int q, int nv) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__ descs) {
-  const ReducedDesc d = descs[blockIdx.x];
+__device__ void reduced_run(const ReducedDesc& d) {
   __shared__ RedShared sh;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -495,9 +494,22 @@ __global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__
   }
 }
 
+__global__ __launch_bounds__(256) void k_reduced(const ReducedDesc* __restrict__ descs) {
+  const ReducedDesc d = descs[blockIdx.x];
+  reduced_run(d);
+}
+
+// One system, its descriptor passed as the kernel argument (no staging copy).
+__global__ __launch_bounds__(256) void k_reduced_one(const ReducedDesc d) { reduced_run(d); }
+
 void launch_reduced(const ReducedDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
   hipLaunchKernelGGL(k_reduced, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+void launch_reduced_one(const ReducedDesc& d, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduced_one, dim3(1), dim3(256), 0, s, d);
   PR_HIP(hipGetLastError());
 }
 
@@ -547,16 +559,6 @@ void launch_reduced0(const Reduced0Desc* d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_aug_decide(const AugDesc* __restrict__ descs) {
-  const AugDesc d = descs[blockIdx.x];
-  if (threadIdx.x != 0) return;
-  const double nd2 = *d.nd2, nu2 = *d.nu2;
-  const int flag = (nd2 > 0.0 && nd2 > kTauAug * kTauAug * nu2) ? 1 : 0;
-  *d.flag = flag;
-  *d.scale = flag ? 1.0 / sqrt(nd2) : 0.0;
-  if (d.m_aug) *d.m_aug = *d.m + flag;
-}
-
 __global__ void k_negate(const double* __restrict__ in, double* __restrict__ out, int n) {
   if ((int)threadIdx.x < n) out[threadIdx.x] = -in[threadIdx.x];
 }
@@ -565,12 +567,6 @@ void launch_negate(const double* in, double* out, int n, hipStream_t s) {
   if (n <= 0) return;
   PR_CHECK(n <= 256, "negate: at most 256 values");
   hipLaunchKernelGGL(k_negate, dim3(1), dim3(256), 0, s, in, out, n);
-  PR_HIP(hipGetLastError());
-}
-
-void launch_aug_decide(const AugDesc* d, int nd, hipStream_t s) {
-  if (nd <= 0) return;
-  hipLaunchKernelGGL(k_aug_decide, dim3(nd), dim3(64), 0, s, d);
   PR_HIP(hipGetLastError());
 }
 
