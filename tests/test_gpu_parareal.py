@@ -299,3 +299,36 @@ def test_coarse_gap_diagnostics_closed_form(ctx):
         pr.pr_parareal_solve(ctx, p, W.PararealOpts(**{**opts.__dict__, "mode": W.MODE_COARSE_GRID}),
                              to_dev(u0))
     assert e.value.name == "PR_EINVAL"
+
+
+def test_parareal_waves_and_streams_do_not_change_bits(ctx, monkeypatch):
+    """The execution plan leaves every item's arithmetic alone. That covers:
+    a memory budget that cuts the fine and sweep waves (wave slots reused
+    within an iteration), the sweep cut into parts whose stage-2 POD runs on
+    the second stream, and no overlap at all. Each gives the solve and its
+    ranks bit for bit."""
+    import paper_2601_10981_amd as pr
+    say("parareal waves and streams bitwise")
+    prob, opts = _tiny(n=16, N=14, T=1.4, max_iter=5)
+    u0 = W.fourier_field(prob.n, 5, n_modes=6, kmax=2.5)
+    p = pr.problem_of(prob)
+    monkeypatch.setenv("PR_SWEEP_PARTS", "1")
+    U1, rep1 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    monkeypatch.setenv("PR_SWEEP_PARTS", "3")
+    U3, rep3 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    assert np.array_equal(to_np(U1), to_np(U3))
+    assert rep1.ranks == rep3.ranks and rep1.jump == rep3.jump
+    full = pr.pr_footprint(p, opts)
+    ran = 0
+    for frac in (0.8, 0.65, 0.5):
+        with pr.Context(0, budget_bytes=int(frac * full)) as c:
+            try:
+                Ub, repb = pr.pr_parareal_solve(c, p, opts, to_dev(u0))
+            except pr.PrError as e:
+                assert e.name == "PR_ENOMEM"
+                continue
+            assert np.array_equal(to_np(Ub), to_np(U3)), frac
+            assert repb.ranks == rep3.ranks and repb.jump == rep3.jump
+            ran += 1
+    assert ran >= 1
+    monkeypatch.delenv("PR_SWEEP_PARTS")
