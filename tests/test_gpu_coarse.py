@@ -128,3 +128,28 @@ def test_coarse_mixed_precision(ctx):
     outs, beta, ncg = _gpu(ctx, op.n, R, m, 8, [U1, U2], 0.2, 4, u_aug=U1, prec=W.PREC_MIXED)
     for o, l in zip(outs, lifted):
         assert rel_l2(o, l) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
+def test_coarse_rank_zero_basis_augments_by_u(ctx, prec):
+    """A basis of rank 0 (every column masked): both Gram-Schmidt passes
+    leave u unchanged, so the coarse space is span{u} and the propagation
+    is the scalar reduced system of that one column."""
+    say(f"coarse rank-0 basis prec={prec}")
+    cap = 8
+    op, h3, R, m, U1, U2 = _setup(cap=cap)
+    R0 = np.zeros((op.n ** 3, 0))
+    Psi, aug = coarse.augment(R0, U1, h3)
+    assert aug and Psi.shape[1] == 1
+    lifted, betas, nc = coarse.coarse_propagate(op, Psi, [U1, U2], 0.2, 4, h3)
+    # garbage in the masked columns must not leak into the result
+    Rg = np.full((op.n ** 3, cap), np.nan)
+    outs, beta, ncg = _gpu(ctx, op.n, Rg, 0, cap, [U1, U2], 0.2, 4, u_aug=U1, prec=prec)
+    assert ncg == nc
+    tol = 1e-12 if prec == W.PREC_F64 else 1e-6
+    for o, l in zip(outs, lifted):
+        assert np.all(np.isfinite(o))
+        assert rel_l2(o, l) <= tol
+    for i in range(2):
+        assert abs(beta[i, cap] - betas[i][0]) <= tol * abs(betas[i][0])
+        assert np.all(beta[i, :cap] == 0.0)

@@ -332,3 +332,17 @@ def test_parareal_waves_and_streams_do_not_change_bits(ctx, monkeypatch):
             ran += 1
     assert ran >= 1
     monkeypatch.delenv("PR_SWEEP_PARTS")
+
+
+def test_parareal_zero_initial_state(ctx):
+    """u0 = 0: every snapshot and basis has rank 0, every state stays exactly
+    zero and the first jump (0 / 0, taken as 0) ends the solve."""
+    import paper_2601_10981_amd as pr
+    say("parareal zero initial state")
+    prob, opts = _tiny(tol=1e-8)
+    p = pr.problem_of(prob)
+    u0 = np.zeros(prob.n ** 3)
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    assert rep.converged and rep.iters == 1 and rep.m0 == 0
+    assert np.all(to_np(U) == 0.0)
+    assert rep.jump == [0.0]
