@@ -170,3 +170,24 @@ def test_pod_mixed_precision_leading_modes(ctx):
         L_ = lead[-1] + 1
         assert np.max(np.abs(_proj(Rg[:, :L_], h3) - _proj(Ro[:, :L_], h3))) <= 1e-5
     assert np.max(np.abs(h3 * (Rg[:, :mg].T @ Rg[:, :mg]) - np.eye(mg))) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
+def test_pod_masked_columns_are_never_read(ctx, prec):
+    """Columns beyond a block's device valid count hold NaN: the Gram, the
+    eigenproblem and the mode formation skip them, so the result is bitwise
+    that of the same blocks with those columns zeroed."""
+    n = 10
+    B = [_snapshots(n, 6, s) for s in (3, 4, 5)]
+    valid = [4, None, 2]
+    Bz = [b.copy() for b in B]
+    Bn = [b.copy() for b in B]
+    for b_z, b_n, v in zip(Bz, Bn, valid):
+        if v is not None:
+            b_z[:, v:] = 0.0
+            b_n[:, v:] = np.nan
+    Rz, mz, lz = _gpu_pod(ctx, n, Bz, 1 - 1e-10, 8, prec=prec, valid=valid)
+    Rn, mn, ln = _gpu_pod(ctx, n, Bn, 1 - 1e-10, 8, prec=prec, valid=valid)
+    assert mn == mz and mz > 0
+    assert np.array_equal(Rn, Rz)
+    assert np.array_equal(ln, lz)
