@@ -180,7 +180,8 @@ def paper_projection(rep, serial_s, N):
     return {"T_F_s": round(T_F, 6), "T_C_s": round(T_C, 6), "T_U_s": round(T_U, 6),
             "T_A_s": round(T_A, 6), "T_G_s": round(T_G, 6), "T_total_s": round(T_total, 6),
             "k": K, "speedup_estimate": round(costmodel.speedup_estimate(T_F, T_total, N, K), 4),
-            "note": "one processor group per subinterval, as the paper's estimate assumes"}
+            "note": "one processor group per subinterval, as the paper's estimate assumes; "
+                    "phase times from a solve with one stream"}
 
 
 def mixed256_run(args):
@@ -680,7 +681,25 @@ def main():
         "m0": rep.m0,
         "roofline": roofline,
     }
-    out["paper_projection"] = paper_projection(rep, serial_s, N)
+    # The timed solves prepare the next part of each sweep wave on a second
+    # stream, so their phase times overlap and each includes the other's
+    # contention. The paper's per-term estimate takes them from one more
+    # (untimed) solve with that overlap off.
+    if serial_s is not None:
+        log("solve without the second stream, for the per-phase estimate")
+        old = os.environ.get("PR_SWEEP_PARTS")
+        os.environ["PR_SWEEP_PARTS"] = "1"
+        try:
+            _, rep1 = one_solve()
+        finally:
+            if old is None:
+                del os.environ["PR_SWEEP_PARTS"]
+            else:
+                os.environ["PR_SWEEP_PARTS"] = old
+        out["t_phase_s_serial_streams"] = {k: round(v, 4) for k, v in rep1.t_phase.items()}
+        out["paper_projection"] = paper_projection(rep1, serial_s, N)
+    else:
+        out["paper_projection"] = None
     if args.serve_requests > 0:
         del U_ref
         torch.cuda.empty_cache()
