@@ -686,49 +686,49 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       // block enter W^k_n (the rest are masked out by the rank anyway)
       const int r0max = std::min(cap0, P.n_s);
       auto prep = [&](int a, int b, hipStream_t st, PhaseEvents& pe) {
-      std::vector<PodWork> pw;
-      std::vector<ApplyLWork> aw;
-      for (int n = a; n < b; ++n) {
-        PodWork w;
-        w.prob = &S->P.prob;
-        for (int j = std::max(0, n - P.o.ml); j <= n; ++j) {
-          const int slot = std::min(k, j + 1) % 2;
-          const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * P.cs;
-          const int* mp = S->m0slot + slot * Np + j;
-          for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+        std::vector<PodWork> pw;
+        std::vector<ApplyLWork> aw;
+        for (int n = a; n < b; ++n) {
+          PodWork w;
+          w.prob = &S->P.prob;
+          for (int j = std::max(0, n - P.o.ml); j <= n; ++j) {
+            const int slot = std::min(k, j + 1) % 2;
+            const char* base = S->R0 + ((size_t)slot * Np + j) * cap0 * P.cs;
+            const int* mp = S->m0slot + slot * Np + j;
+            for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+          }
+          if (P.o.p >= 1 && k - 1 >= 1) {
+            const int slot = (k - 1) % 2;
+            const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * P.cs;
+            const int* mp = S->m0slot + slot * Np + n;
+            for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+          }
+          w.gamma = P.o.gamma3;
+          w.cap = cap;
+          w.force_m = -1;
+          w.R_out = S->Psi + (size_t)(n - n0) * cap * P.cs;
+          w.R_ld = P.ld;
+          w.m_out = S->mS + (n - n0);
+          w.lambda_out = nullptr;
+          w.skip_tail = 1;
+          pw.push_back(w);
+          for (int jp = 0; jp < P.np; ++jp)
+            aw.push_back(ApplyLWork{&S->P.prob, w.R_out,
+                                    S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * P.cs, cap,
+                                    w.m_out, jp, P.ld, 1});
         }
-        if (P.o.p >= 1 && k - 1 >= 1) {
-          const int slot = (k - 1) % 2;
-          const char* base = S->R0 + ((size_t)slot * Np + n) * cap0 * P.cs;
-          const int* mp = S->m0slot + slot * Np + n;
-          for (int c0 = 0; c0 < r0max; ++c0) w.cols.push_back(colp(base, c0, P.ld, P.f32, mp));
+        pe.begin(1);
+        for (int na = 1; na <= 4; ++na) {
+          std::vector<PodWork> g;
+          for (auto& x : pw)
+            if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
+          if (!g.empty()) enqueue_pod(c, g, st, "sol_pod");
         }
-        w.gamma = P.o.gamma3;
-        w.cap = cap;
-        w.force_m = -1;
-        w.R_out = S->Psi + (size_t)(n - n0) * cap * P.cs;
-        w.R_ld = P.ld;
-        w.m_out = S->mS + (n - n0);
-        w.lambda_out = nullptr;
-        w.skip_tail = 1;
-        pw.push_back(w);
-        for (int jp = 0; jp < P.np; ++jp)
-          aw.push_back(ApplyLWork{&S->P.prob, w.R_out,
-                                  S->LPsi + ((size_t)(n - n0) * P.np + jp) * cap * P.cs, cap,
-                                  w.m_out, jp, P.ld, 1});
-      }
-      pe.begin(1);
-      for (int na = 1; na <= 4; ++na) {
-        std::vector<PodWork> g;
-        for (auto& x : pw)
-          if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
-        if (!g.empty()) enqueue_pod(c, g, st, "sol_pod");
-      }
-      pe.begin(2);
-      enqueue_applyL_batch(c, aw, st);
-      PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + a, S->mS + (a - n0), (size_t)(b - a) * 4,
-                            hipMemcpyDeviceToDevice, st));
-      pe.end();
+        pe.begin(2);
+        enqueue_applyL_batch(c, aw, st);
+        PR_HIP(hipMemcpyAsync(S->ranks + (size_t)k * Np + a, S->mS + (a - n0), (size_t)(b - a) * 4,
+                              hipMemcpyDeviceToDevice, st));
+        pe.end();
       };
       const int nparts = std::max(1, std::min(sweep_parts(), (n1 - n0) / kMinPartItems));
       std::vector<int> cut;
@@ -753,34 +753,34 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         }
       }
       for (int i = 0; i < nparts; ++i) {
-      if (ready[i]) PR_HIP(hipStreamWaitEvent(s, ready[i], 0));
-      for (int n = cut[i]; n < cut[i + 1]; ++n) {
-        CoarseWork w{};
-        w.prob = &S->P.prob;
-        w.R = S->Psi + (size_t)(n - n0) * cap * P.cs;
-        w.LR = S->LPsi + (size_t)(n - n0) * P.np * cap * P.cs;
-        w.ld = P.ld;
-        w.cap = cap;
-        w.m = S->mS + (n - n0);
-        w.u_aug = Ucur + (size_t)n * ng;
-        w.n_in = 2;
-        w.u_in[0] = Ucur + (size_t)n * ng;
-        w.u_in[1] = Uprev + (size_t)n * ng;
-        w.dT = P.dTs;
-        w.n_c = P.n_c;
-        w.t0 = t_hat(P, n);
-        w.forcing = S->forcing;
-        if (P.diag) {
-          w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
-          w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+        if (ready[i]) PR_HIP(hipStreamWaitEvent(s, ready[i], 0));
+        for (int n = cut[i]; n < cut[i + 1]; ++n) {
+          CoarseWork w{};
+          w.prob = &S->P.prob;
+          w.R = S->Psi + (size_t)(n - n0) * cap * P.cs;
+          w.LR = S->LPsi + (size_t)(n - n0) * P.np * cap * P.cs;
+          w.ld = P.ld;
+          w.cap = cap;
+          w.m = S->mS + (n - n0);
+          w.u_aug = Ucur + (size_t)n * ng;
+          w.n_in = 2;
+          w.u_in[0] = Ucur + (size_t)n * ng;
+          w.u_in[1] = Uprev + (size_t)n * ng;
+          w.dT = P.dTs;
+          w.n_c = P.n_c;
+          w.t0 = t_hat(P, n);
+          w.forcing = S->forcing;
+          if (P.diag) {
+            w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
+            w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+          }
+          w.corr_out = Ucur + (size_t)(n + 1) * ng;
+          w.fine = S->Fn + (size_t)n * ng;
+          w.prev = Uprev + (size_t)(n + 1) * ng;
+          w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+          w.norms4 = S->norms + 4 * (n + 1);
+          enqueue_coarse(c, w, s, &ph);
         }
-        w.corr_out = Ucur + (size_t)(n + 1) * ng;
-        w.fine = S->Fn + (size_t)n * ng;
-        w.prev = Uprev + (size_t)(n + 1) * ng;
-        w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
-        w.norms4 = S->norms + 4 * (n + 1);
-        enqueue_coarse(c, w, s, &ph);
-      }
       }
     }
     ph.end();
