@@ -621,7 +621,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
     const Plan& P = S->P;
     const int k = S->k, Np = P.Np, cap = P.o.cap, cap0 = P.o.cap0;
     const long long ng = P.ng;
-    const size_t f8 = (size_t)ng * 8, fs = (size_t)ng * P.sf;
+    const size_t f8 = (size_t)ng * 8;
     const double h = spacing(P.prob), h3 = h * h * h;
     double* Uprev = S->U[S->prev];
     double* Ucur = S->U[1 - S->prev];
