@@ -993,16 +993,16 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   const int np = flow_pieces(p);
   const bool forced = forced_flow(p);
   char* sm = (char*)scratch(c, "co_small", 64 * 1024);
-  double* S1 = (double*)(sm);              // 32 x 16
-  double* S2 = (double*)(sm + 4096);       // 32 x 16
-  double* S3 = (double*)(sm + 8192);       // 16 x 16
+  double* S1 = (double*)(sm);              // CGS2 pass 1: R^T M u (cap), |u|^2 at [32]
+  double* S2 = (double*)(sm + 4096);       // pass 2: R^T M d~ (cap), |d~|^2 at [32]
+  double* S3 = (double*)(sm + 8192);       // pass 3: |d~|^2 after the second projection
   int* flag = (int*)(sm + 12288);
   int* status = (int*)(sm + 12288 + 64);
   double* dscale = (double*)(sm + 12288 + 128);
   double* coef = (double*)(sm + 16384);    // cap + 1
   double* betas = (double*)(sm + 16384 + 512);  // 2 x (cap + 1)
   double* nrm = (double*)(sm + 16384 + 1024);   // scratch norms
-  double* Sbig = (double*)(sm + 20480);    // 32 x (16 (2 + 2 np + 1)), <= 32 x 144
+  double* Sbig = (double*)(sm + 20480);    // Galerkin products: 32 rows x 16 nb (nb <= 9)
 
   PhaseEvents dummy;
   PhaseEvents& P = ph ? *ph : dummy;
