@@ -284,6 +284,11 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *                 ||U_{n+1}||_M (report gap_fine / gap_ref). POD modes only
  *                 (PR_EINVAL with PR_MODE_COARSE_GRID); costs two extra field
  *                 passes per sweep step
+ * Environment: PR_SWEEP_PARTS (default 4; 1 = no second stream) cuts each
+ * sweep wave into parts whose stage-2 POD overlaps the sweep of the part
+ * before; PR_DEFER_CHOLQR (default 1; 0 = off) folds the stage-1 CholQR
+ * into stage 2's block whitening. Neither changes the ranks; the first
+ * leaves every bit alone, the second the iterates up to round-off.
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */

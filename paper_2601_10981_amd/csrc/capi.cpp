@@ -841,6 +841,39 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   }
   enqueue_gram(c, gw, na, 0, f32, s, tag + "_g1");
 
+  // 1b. inputs made of blocks whose own M-orthonormalisation was deferred:
+  // whiten the Gram by the blocks' Cholesky factors
+  const int wbs = items[0].whiten_bs;
+  const int cq = items[0].cholqr;
+  for (auto& w : items)
+    PR_CHECK(w.whiten_bs == wbs && w.cholqr == cq, "POD batch items must share their options");
+  WhitenDesc* wdd = nullptr;
+  if (wbs > 0) {
+    PR_CHECK(wbs <= 32, "whitening blocks of at most 32 columns");
+    double* wT = (double*)scratch(c, tag + "_wT", (size_t)nitems * kWhitenMaxCols * 32 * 8);
+    int* wm = (int*)scratch(c, tag + "_wm", (size_t)nitems * kWhitenMaxCols * 4);
+    std::vector<WhitenDesc> wd;
+    for (int i = 0; i < nitems; ++i) {
+      const int nc = (int)items[i].cols.size();
+      PR_CHECK(nc % wbs == 0 && nc <= kWhitenMaxCols, "whitening needs whole blocks");
+      WhitenDesc x{};
+      x.G = G + (size_t)i * ldg * ldg;
+      x.ldg = ldg;
+      x.nb = nc / wbs;
+      x.bs = wbs;
+      for (int b = 0; b < x.nb; ++b) x.m[b] = items[i].cols[(size_t)b * wbs].mptr;
+      x.T = wT + (size_t)i * kWhitenMaxCols * 32;
+      x.meff = wm + (size_t)i * kWhitenMaxCols;
+      x.coef = coef + (size_t)i * 64 * 32;
+      x.ld_coef = items[i].cap;
+      x.ncoef = items[i].cap;
+      wd.push_back(x);
+    }
+    wdd = stage_push(c, wd);
+    stage_flush(c, s);
+    launch_block_whiten(wdd, nitems, s);
+  }
+
   // 2-3. eigen-decomposition, rank and mode coefficients
   std::vector<EigDesc> ed;
   for (int i = 0; i < nitems; ++i) {
@@ -861,6 +894,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   EigDesc* edd = stage_push(c, ed);
   stage_flush(c, s);
   launch_eig_select(edd, nitems, s);
+  if (wdd) launch_block_unwhiten(wdd, nitems, s);   // coefficients of the raw blocks
 
   // 4. modes R = W Y_m Lambda_m^{-1/2}
   std::vector<TsmmDesc> td;
@@ -896,7 +930,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   // 5. CholQR in the M inner product (FP64 MFMA Gram, FP64 Cholesky). The
   // modes enter with kappa(R) ~ 1 + eps lambda_1 / lambda_m <= 1 + 1e-3, so
   // one pass already leaves eps kappa^2 ~ eps loss of orthogonality.
-  for (int pass = 0; pass < kCholQRPasses; ++pass) {
+  for (int pass = 0; pass < (cq ? kCholQRPasses : 0); ++pass) {
     std::vector<GramWork> g2;
     std::vector<std::vector<ColDesc>> rcols(nitems);
     for (int i = 0; i < nitems; ++i) {

@@ -125,6 +125,10 @@ struct PodWork {
   long long R_ld = 0;          // column stride of R_out in elements (0: N_g)
   int skip_tail = 0;           // 1: R_out columns >= *m_out are left unwritten
                                // (for consumers that mask by the rank)
+  int cholqr = 1;              // 0: the modes are left as W y_i / sqrt(lambda_i)
+  int whiten_bs = 0;           // > 0: the input is blocks of whiten_bs columns
+                               // (block b's rank in cols[b whiten_bs].mptr),
+                               // each taken as M-orthonormalised (WhitenDesc)
 };
 void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
                  const std::string& tag);

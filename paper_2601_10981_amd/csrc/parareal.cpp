@@ -509,6 +509,13 @@ static void iterate_batch(pr_ctx* c, const std::vector<pr_solve*>& ss, hipStream
   }
 }
 
+// Stage-1 modes left without their CholQR, which stage 2 folds into a block
+// whitening of its Gram (PR_DEFER_CHOLQR, default 1; 0 keeps the stage-1 CholQR).
+static bool defer_cholqr() {
+  const char* e = getenv("PR_DEFER_CHOLQR");
+  return !(e && *e == '0');
+}
+
 // Parts a sweep wave is cut into (PR_SWEEP_PARTS, default 4; 1 runs the
 // stage-2 POD of the whole wave before its sweep), each of at least
 // kMinPartItems subintervals.
@@ -565,6 +572,8 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.R_out = S->R0 + ((size_t)slot * Np + n) * P.o.cap0 * cs;
         w.R_ld = P.ld;
         w.skip_tail = 1;
+        // the M-orthonormalisation of the stage-1 modes happens in stage 2
+        w.cholqr = defer_cholqr() ? 0 : 1;
         w.m_out = S->m0slot + slot * Np + n;
         w.lambda_out = nullptr;
         pw.push_back(w);
@@ -711,6 +720,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           w.m_out = S->mS + (n - n0);
           w.lambda_out = nullptr;
           w.skip_tail = 1;
+          w.whiten_bs = defer_cholqr() ? r0max : 0;
           pw.push_back(w);
           for (int jp = 0; jp < P.np; ++jp)
             aw.push_back(ApplyLWork{&S->P.prob, w.R_out,

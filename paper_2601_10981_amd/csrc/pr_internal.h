@@ -320,6 +320,28 @@ struct CholDesc {
 };
 void launch_cholqr_coef(const CholDesc* d, int nitems, hipStream_t s);
 
+// Block whitening of a Gram over nb blocks of bs columns (block b's first
+// *m[b] columns valid, the rest zero rows and columns): with the Cholesky
+// factors T_b^T T_b = G_bb of the diagonal blocks (a pivot <= kDropPivot
+// ends block b's valid columns there), G <- D^{-T} G D^{-1}, D = blockdiag(T_b):
+// the Gram the blocks would have after an M-orthonormalisation of each. Then,
+// after the eigenproblem, coefficients C (rows = the same columns) become
+// D^{-1} C, so W D^{-1} C = W (D^{-1} C) forms the modes from the raw blocks.
+constexpr int kWhitenMaxCols = 64;
+struct WhitenDesc {
+  double* G;         // nb bs x nb bs, leading dimension ldg (in place)
+  int ldg;
+  int nb, bs;        // nb * bs <= 64, bs <= 32
+  const int* m[kWhitenMaxCols];  // per block: device rank (nullptr: bs)
+  double* T;         // nb x bs x bs: the factors (written by whiten)
+  int* meff;         // nb: valid columns kept per block (written by whiten)
+  double* coef;      // nb bs x ld_coef (unwhiten, in place)
+  int ld_coef;
+  int ncoef;         // coefficient columns
+};
+void launch_block_whiten(const WhitenDesc* d, int nitems, hipStream_t s);
+void launch_block_unwhiten(const WhitenDesc* d, int nitems, hipStream_t s);
+
 // Reduced propagation (one item per coarse solve). The reduced matrices are
 // read from the Gram output: S (q x ld) with Psi^T M Psi in columns
 // [0, q) and Psi^T M L Psi in columns [q_off_L, q_off_L + q) and the

@@ -246,6 +246,113 @@ void launch_cholqr_coef(const CholDesc* d, int nd, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Block whitening (WhitenDesc). One workgroup of 64 threads per item.
+__global__ __launch_bounds__(64) void k_block_whiten(const WhitenDesc* __restrict__ descs) {
+  const WhitenDesc& d = descs[blockIdx.x];
+  __shared__ double A[kWhitenMaxCols][kWhitenMaxCols + 1];
+  __shared__ double Ts[kWhitenMaxCols * 32];
+  __shared__ int mb[kWhitenMaxCols];
+  const int tid = threadIdx.x;
+  const int nb = d.nb, bs = d.bs, nc = nb * bs;
+  for (int e = tid; e < nc * nc; e += 64) A[e / nc][e % nc] = d.G[(long long)(e / nc) * d.ldg + e % nc];
+  if (tid < nb) mb[tid] = d.m[tid] ? min(*d.m[tid], bs) : bs;
+  __syncthreads();
+  // Cholesky of each diagonal block, one thread per block (rows in order)
+  if (tid < nb) {
+    const int o = tid * bs;
+    double* T = Ts + tid * bs * bs;
+    int m = mb[tid];
+    for (int j = 0; j < m; ++j) {
+      double dj = A[o + j][o + j];
+      for (int k = 0; k < j; ++k) dj -= T[k * bs + j] * T[k * bs + j];
+      if (!(dj > kDropPivot)) {
+        m = j;
+        break;
+      }
+      const double tjj = sqrt(dj);
+      T[j * bs + j] = tjj;
+      for (int i = j + 1; i < m; ++i) {
+        double v = A[o + j][o + i];
+        for (int k = 0; k < j; ++k) v -= T[k * bs + j] * T[k * bs + i];
+        T[j * bs + i] = v / tjj;
+      }
+    }
+    mb[tid] = m;
+  }
+  __syncthreads();
+  // left: column c of each block row b <- T_b^{-T} (forward substitution);
+  // rows beyond the kept columns become zero
+  if (tid < nc) {
+    const int c = tid;
+    for (int b = 0; b < nb; ++b) {
+      const int o = b * bs, m = mb[b];
+      const double* T = Ts + b * bs * bs;
+      for (int i = 0; i < bs; ++i) {
+        if (i >= m) {
+          A[o + i][c] = 0.0;
+          continue;
+        }
+        double v = A[o + i][c];
+        for (int k = 0; k < i; ++k) v -= T[k * bs + i] * A[o + k][c];
+        A[o + i][c] = v / T[i * bs + i];
+      }
+    }
+  }
+  __syncthreads();
+  // right: row r of each block column b <- (.) T_b^{-1}
+  if (tid < nc) {
+    const int r = tid;
+    for (int b = 0; b < nb; ++b) {
+      const int o = b * bs, m = mb[b];
+      const double* T = Ts + b * bs * bs;
+      for (int i = 0; i < bs; ++i) {
+        if (i >= m) {
+          A[r][o + i] = 0.0;
+          continue;
+        }
+        double v = A[r][o + i];
+        for (int k = 0; k < i; ++k) v -= A[r][o + k] * T[k * bs + i];
+        A[r][o + i] = v / T[i * bs + i];
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nc * nc; e += 64) d.G[(long long)(e / nc) * d.ldg + e % nc] = A[e / nc][e % nc];
+  for (int e = tid; e < nb * bs * bs; e += 64) d.T[e] = Ts[e];
+  if (tid < nb) d.meff[tid] = mb[tid];
+}
+
+// coef rows of block b <- T_b^{-1} (back substitution), one thread per column
+__global__ __launch_bounds__(64) void k_block_unwhiten(const WhitenDesc* __restrict__ descs) {
+  const WhitenDesc& d = descs[blockIdx.x];
+  const int nb = d.nb, bs = d.bs;
+  for (int j = threadIdx.x; j < d.ncoef; j += 64) {
+    for (int b = 0; b < nb; ++b) {
+      const int o = b * bs, m = d.meff[b];
+      const double* T = d.T + b * bs * bs;
+      for (int i = m - 1; i >= 0; --i) {
+        double v = d.coef[(long long)(o + i) * d.ld_coef + j];
+        for (int k = i + 1; k < m; ++k) v -= T[i * bs + k] * d.coef[(long long)(o + k) * d.ld_coef + j];
+        d.coef[(long long)(o + i) * d.ld_coef + j] = v / T[i * bs + i];
+      }
+      for (int i = m; i < bs; ++i) d.coef[(long long)(o + i) * d.ld_coef + j] = 0.0;
+    }
+  }
+}
+
+void launch_block_whiten(const WhitenDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_block_whiten, dim3(nd), dim3(64), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+void launch_block_unwhiten(const WhitenDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_block_unwhiten, dim3(nd), dim3(64), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Reduced system helpers shared by the sweep and the k = 0 recurrence.
 struct RedShared {
   double M[kMaxQ + 1][kMaxQ + 2];
