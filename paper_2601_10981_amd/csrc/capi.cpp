@@ -107,11 +107,36 @@ void* stage_push_bytes(pr_ctx* c, const void* src, size_t bytes) {
   return c->dev_slot[c->slot] + o;
 }
 
+// Flushes of up to kUploadMax bytes travel in the arguments of k_upload
+// launches (PR_STAGE_UPLOAD=0: always a copy). The range is widened to whole
+// 4-byte words inside the slot; bytes below `flushed` are rewritten with the
+// values they already hold.
+constexpr size_t kUploadMax = 4 * sizeof(UploadBlob);
+static bool stage_upload() {
+  static const bool on = [] {
+    const char* e = getenv("PR_STAGE_UPLOAD");
+    return !(e && *e == '0');
+  }();
+  return on;
+}
+
 void stage_flush(pr_ctx* c, hipStream_t s) {
   c->stream = s;
   if (c->off > c->flushed) {
-    PR_HIP(hipMemcpyAsync(c->dev_slot[c->slot] + c->flushed, c->host_slot[c->slot] + c->flushed,
-                          c->off - c->flushed, hipMemcpyHostToDevice, s));
+    const size_t b0 = c->flushed & ~size_t(3);
+    const size_t b1 = (c->off + 3) & ~size_t(3);
+    static_assert(pr_ctx::kSlotBytes % 4 == 0, "slots hold whole words");
+    if (stage_upload() && b1 - b0 <= kUploadMax) {
+      UploadBlob blob;
+      for (size_t b = b0; b < b1; b += sizeof(UploadBlob)) {
+        const size_t nb = std::min(sizeof(UploadBlob), b1 - b);
+        memcpy(blob.w, c->host_slot[c->slot] + b, nb);
+        launch_upload(blob, (unsigned int*)(c->dev_slot[c->slot] + b), (int)(nb / 4), s);
+      }
+    } else {
+      PR_HIP(hipMemcpyAsync(c->dev_slot[c->slot] + c->flushed, c->host_slot[c->slot] + c->flushed,
+                            c->off - c->flushed, hipMemcpyHostToDevice, s));
+    }
     c->flushed = c->off;
   }
 }

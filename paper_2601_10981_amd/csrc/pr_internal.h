@@ -250,6 +250,15 @@ int forced_blocks_per_cu(int cfg, bool f32);
 // f_j of piece j of a forced flow written as an N_g field (double or float).
 void launch_forcing_field(const Geom& g, int piece, void* out, int out_f32, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, long long n, hipStream_t s);
+
+// Small host-to-device uploads carried in the kernel arguments: words[0, nw)
+// of the blob are written to dst (4-byte aligned). Cheaper than a copy whose
+// engine reads pinned host memory across the bus.
+constexpr int kUploadWords = 512;
+struct UploadBlob {
+  unsigned int w[kUploadWords];
+};
+void launch_upload(const UploadBlob& b, unsigned int* dst, int nw, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, long long n, hipStream_t s);
 void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, hipStream_t s);
 void launch_applyL_f32(const ApplyLDesc<float>* d, int nitems, long long total_tiles, hipStream_t s);

@@ -246,6 +246,19 @@ void launch_cholqr_coef(const CholDesc* d, int nd, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Descriptor upload through the kernel arguments.
+__global__ __launch_bounds__(256) void k_upload(const UploadBlob b, unsigned int* __restrict__ dst,
+                                                int nw) {
+  for (int i = threadIdx.x; i < nw; i += 256) dst[i] = b.w[i];
+}
+
+void launch_upload(const UploadBlob& b, unsigned int* dst, int nw, hipStream_t s) {
+  PR_CHECK(nw > 0 && nw <= kUploadWords, "upload of at most kUploadWords words");
+  hipLaunchKernelGGL(k_upload, dim3(1), dim3(256), 0, s, b, dst, nw);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Block whitening (WhitenDesc). One workgroup of 64 threads per item.
 __global__ __launch_bounds__(64) void k_block_whiten(const WhitenDesc* __restrict__ descs) {
   const WhitenDesc& d = descs[blockIdx.x];
