@@ -711,6 +711,21 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
     d.out = it.out;
     d.ld = it.ld;
     d.scale = it.scale;
+    if (it.a_in_b) {
+      PR_CHECK(nb >= na, "A inside B needs at least as many B tiles");
+      bool tail = false;
+      for (int i = 0; i < na * 16; ++i) {
+        const ColDesc& a = it.cols[i];
+        const ColDesc& b = it.cols[(size_t)na * 16 + i];
+        if (a.ptr == nullptr) {
+          tail = true;
+          continue;
+        }
+        PR_CHECK(!tail && a.ptr == b.ptr && a.mptr == b.mptr && a.idx == b.idx && a.f32 == b.f32,
+                 "A columns must be a prefix of the B columns");
+      }
+      d.a_in_b = 1;
+    }
     part_off.push_back((long long)part_total);
     part_total += (size_t)d.nchunks * P * 256;
     descs.push_back(d);
@@ -1164,6 +1179,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   gb.out = Sbig;
   gb.ld = 16 * nb;
   gb.scale = h3;
+  gb.a_in_b = 1;                                   // A = B's leading Psi block
   PR_CHECK(32 * gb.ld * 8 <= 57344 - 20480, "Galerkin block exceeds its scratch");
   enqueue_gram(c, {gb}, na, nb, false, s, "co_g");
 

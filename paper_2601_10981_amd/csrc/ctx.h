@@ -141,6 +141,8 @@ struct GramWork {
   double* out;
   int ld;
   double scale;
+  int a_in_b = 0;              // 1: the A columns are a prefix of the B columns
+                               // (then null slots); A is taken from B's loads
 };
 void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
                   hipStream_t s, const std::string& tag);

@@ -160,6 +160,12 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
   __syncthreads();
   const int tA = (s_cnt[0] + 15) >> 4;
   const int tB = NB == 0 ? tA : (s_cnt[1] + 15) >> 4;
+  // A's packed tiles are B's leading packed tiles: only B is loaded, and B's
+  // registers serve as the A operand (the 16x16x4 operand layouts of A^T and
+  // B coincide). Entries at packed A positions past A's count then hold B
+  // columns; the reduction never reads them.
+  constexpr bool kCanAinB = NB >= NA;
+  const bool a_in_b = kCanAinB && d.a_in_b != 0;
   const void* cp[NT];
   int cf[NT];
   bool cv[NT], c16[NT];
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
       In v[NT][UL];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        const bool act = (t < NA) ? t < tA : t - NA < tB;
+        const bool act = (t < NA) ? (t < tA && !a_in_b) : t - NA < tB;
         const long long rb = r0 + 4 * kq + u0;
         // vector loads pay in the symmetric (POD) Grams; the sweep's one-item
         // Galerkin products measured slower with them
@@ -221,10 +227,11 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
             const int p = (NB == 0) ? ia * NA - ia * (ia - 1) / 2 + (jb - ia) : ia * NB + jb;
             const int ib = (NB == 0) ? jb : NA + jb;
             if (ia >= tA || jb >= tB) continue;
+            const In va = (kCanAinB && a_in_b) ? v[kCanAinB ? NA + ia : ia][u] : v[ia][u];
             if constexpr (F32)
-              acc32[p] = M::op(v[ia][u], v[ib][u], acc32[p]);
+              acc32[p] = M::op(va, v[ib][u], acc32[p]);
             else
-              acc[p] = M::op(v[ia][u], v[ib][u], acc[p]);
+              acc[p] = M::op(va, v[ib][u], acc[p]);
           }
         }
       }

@@ -189,6 +189,9 @@ struct GemmDesc {
   double* out;           // reduced output (ld x ...), row = A column
   int ld;
   double scale;
+  int a_in_b;            // 1: A's slots are a prefix of B's slots followed by
+                         //  null ones, so A's packed tiles are B's leading
+                         //  packed tiles; A is not loaded separately
 };
 
 // ---- tall-skinny times small (out = sum_c in_c C[c][j] (+ add)) ------------
