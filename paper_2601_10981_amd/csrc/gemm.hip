@@ -314,18 +314,23 @@ __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict
   const PR_GLOBAL double* src = gptr(d.partial) + pc;
   const long long stride = (long long)P * 256;
   const int nch = valid ? d.nchunks : 0;
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  // eight chunk loads in flight per round (the sum is latency-bound: a few
+  // MB spread over few workgroups)
+  double a[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) a[u] = 0.0;
   int c = q;
-  for (; c + 48 < nch; c += 64) {
-    a0 += src[(long long)c * stride];
-    a1 += src[(long long)(c + 16) * stride];
-    a2 += src[(long long)(c + 32) * stride];
-    a3 += src[(long long)(c + 48) * stride];
+  for (; c + 7 * 16 < nch; c += 8 * 16) {
+    double t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = src[(long long)(c + 16 * u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += t[u];
   }
-  if (c < nch) a0 += src[(long long)c * stride];
-  if (c + 16 < nch) a1 += src[(long long)(c + 16) * stride];
-  if (c + 32 < nch) a2 += src[(long long)(c + 32) * stride];
-  red[q][threadIdx.x & 63] = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int u = 0; u < 7; ++u)
+    if (c + 16 * u < nch) a[u] += src[(long long)(c + 16 * u) * stride];
+  red[q][threadIdx.x & 63] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
   if (q != 0) return;
   const int l = threadIdx.x & 63;
