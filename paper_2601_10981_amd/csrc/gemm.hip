@@ -283,16 +283,19 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 // groups' sums combine in a fixed tree. The order depends only on the chunk
 // count, so the result does not depend on the batch.
 template <int NA, int NB>
-__global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
+// One workgroup of 256 threads per 16 entries of a tile pair: 16 chunk
+// groups q of 16 entries each. Small workgroups start in the gaps that
+// concurrent kernels leave (a 1024-thread one waits for a nearly free CU).
+__global__ __launch_bounds__(256) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
   using PL = PairList<NA, NB>;
   constexpr int P = PL::P;
-  __shared__ double red[16][64];
+  __shared__ double red[16][16];
   __shared__ short s_pos[(NA + NB) * 16];
   const GemmDesc& d = descs[blockIdx.y];
-  const int p = blockIdx.x >> 2;
-  const int e = ((blockIdx.x & 3) << 6) | (threadIdx.x & 63);
-  const int q = threadIdx.x >> 6;
-  if (q == 0) {
+  const int p = blockIdx.x >> 4;
+  const int e = ((blockIdx.x & 15) << 4) | (threadIdx.x & 15);
+  const int q = threadIdx.x >> 4;
+  if (threadIdx.x < 64) {   // wave 0
     compact_group(d.cols, 0, NA * 16, nullptr, s_pos, threadIdx.x);
     if (NB != 0) compact_group(d.cols, NA * 16, NB * 16, nullptr, s_pos, threadIdx.x);
   }
@@ -330,10 +333,10 @@ __global__ __launch_bounds__(1024) void k_gemm_reduce(const GemmDesc* __restrict
 #pragma unroll
   for (int u = 0; u < 7; ++u)
     if (c + 16 * u < nch) a[u] += src[(long long)(c + 16 * u) * stride];
-  red[q][threadIdx.x & 63] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  red[q][threadIdx.x & 15] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   __syncthreads();
   if (q != 0) return;
-  const int l = threadIdx.x & 63;
+  const int l = threadIdx.x & 15;
   double t[8];
 #pragma unroll
   for (int g = 0; g < 8; ++g) t[g] = red[2 * g][l] + red[2 * g + 1][l];
@@ -361,7 +364,7 @@ static void launch_gemm_shape(const GemmDesc* d, int nd, long long total_wg, boo
 
 template <int NA, int NB>
 static void launch_reduce_shape(const GemmDesc* d, int nd, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P * 4, nd), dim3(1024), 0, s,
+  hipLaunchKernelGGL((k_gemm_reduce<NA, NB>), dim3(PairList<NA, NB>::P * 16, nd), dim3(256), 0, s,
                      d);
 }
 
