@@ -233,6 +233,10 @@ struct pr_solve {
   double* host = nullptr;  // pinned: e_k, err_k
   std::vector<std::pair<void*, size_t>> owned;
   bool ext_out = false;    // U[0] lives in the caller's U_out
+  // stage-1 POD items of this iteration waiting for the sweep part that first
+  // needs them (subinterval, item), in increasing subinterval order
+  std::vector<std::pair<int, PodWork>> pod1_pending;
+  size_t pod1_next = 0;
   int k = 0;
   int prev = 0;            // U[prev] holds the latest iterate
   bool done = false;
@@ -516,6 +520,28 @@ static bool defer_cholqr() {
   return !(e && *e == '0');
 }
 
+// Stage-1 POD run per sweep part, just before the part's stage-2 POD (on the
+// second stream beside the sweep of the part before), rather than after the
+// fine phase (PR_DEFER_POD1, default 1). Only for a solve whose fine phase is
+// one wave, so its snapshots stay in place until the sweep.
+static bool defer_pod1() {
+  const char* e = getenv("PR_DEFER_POD1");
+  return !(e && *e == '0');
+}
+
+// Enqueues the pending stage-1 items of S below subinterval `below`.
+static void flush_pod1(pr_ctx* c, pr_solve* S, int below, hipStream_t st) {
+  std::vector<PodWork> pw;
+  while (S->pod1_next < S->pod1_pending.size() && S->pod1_pending[S->pod1_next].first < below)
+    pw.push_back(S->pod1_pending[S->pod1_next++].second);
+  for (int na = 1; na <= 4; ++na) {
+    std::vector<PodWork> g;
+    for (auto& x : pw)
+      if (((int)x.cols.size() + 15) / 16 == na) g.push_back(x);
+    if (!g.empty()) enqueue_pod(c, g, st, "sol_pod");
+  }
+}
+
 // Parts a sweep wave is cut into (PR_SWEEP_PARTS, default 4; 1 runs the
 // stage-2 POD of the whole wave before its sweep), each of at least
 // kMinPartItems subintervals.
@@ -544,8 +570,13 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       const Plan& P = S->P;
       const int k = S->k, Np = P.Np;
       const int n0 = (k - 1) + round * P.waveF;
+      if (round == 0) {
+        S->pod1_pending.clear();
+        S->pod1_next = 0;
+      }
       if (n0 >= Np) continue;
       const int n1 = std::min(Np, n0 + P.waveF);
+      const bool defer1 = round == 0 && n1 == Np && defer_pod1();
       const size_t cs = P.cs;
       const double* Uprev = S->U[S->prev];
       for (int n = n0; n < n1; ++n) {
@@ -576,6 +607,13 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.cholqr = defer_cholqr() ? 0 : 1;
         w.m_out = S->m0slot + slot * Np + n;
         w.lambda_out = nullptr;
+        if (defer1) {
+          S->pod1_pending.emplace_back(n, w);
+          PodWork none;
+          none.prob = &S->P.prob;
+          pw.push_back(none);
+          continue;
+        }
         pw.push_back(w);
       }
       S->fine_updates += (double)(n1 - n0) * P.n_f * P.ng;
@@ -728,6 +766,9 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
                                     w.m_out, jp, P.ld, 1});
         }
         pe.begin(1);
+        // stage-1 bases of subintervals up to b - 1 (W^k_n reads those of
+        // n - m_l .. n)
+        flush_pod1(c, S, b, st);
         for (int na = 1; na <= 4; ++na) {
           std::vector<PodWork> g;
           for (auto& x : pw)
@@ -792,6 +833,12 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           enqueue_coarse(c, w, s, &ph);
         }
       }
+    }
+    // stage-1 items no sweep part took (the sweep of the last iteration is
+    // empty): their bases still complete the iteration
+    if (S->pod1_next < S->pod1_pending.size()) {
+      ph.begin(1);
+      flush_pod1(c, S, Np, s);
     }
     ph.end();
     // (v) jump and error
