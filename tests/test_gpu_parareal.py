@@ -305,8 +305,9 @@ def test_parareal_waves_and_streams_do_not_change_bits(ctx, monkeypatch):
     """The execution plan leaves every item's arithmetic alone. That covers:
     a memory budget that cuts the fine and sweep waves (wave slots reused
     within an iteration), the sweep cut into parts whose stage-2 POD runs on
-    the second stream, and no overlap at all. Each gives the solve and its
-    ranks bit for bit."""
+    the second stream, no overlap at all, and the stage-1 POD run after the
+    fine phase instead of per sweep part. Each gives the solve and its ranks
+    bit for bit."""
     import paper_2601_10981_amd as pr
     say("parareal waves and streams bitwise")
     prob, opts = _tiny(n=16, N=14, T=1.4, max_iter=5)
@@ -318,6 +319,11 @@ def test_parareal_waves_and_streams_do_not_change_bits(ctx, monkeypatch):
     U3, rep3 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
     assert np.array_equal(to_np(U1), to_np(U3))
     assert rep1.ranks == rep3.ranks and rep1.jump == rep3.jump
+    monkeypatch.setenv("PR_DEFER_POD1", "0")
+    U0, rep0 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    monkeypatch.delenv("PR_DEFER_POD1")
+    assert np.array_equal(to_np(U0), to_np(U3))
+    assert rep0.ranks == rep3.ranks and rep0.jump == rep3.jump
     full = pr.pr_footprint(p, opts)
     ran = 0
     for frac in (0.8, 0.65, 0.5):
