@@ -546,6 +546,15 @@ static void flush_pod1(pr_ctx* c, pr_solve* S, int below, hipStream_t st) {
 // stage-2 POD of the whole wave before its sweep), each of at least
 // kMinPartItems subintervals.
 constexpr int kMinPartItems = 4;
+// Subintervals in the first part of a sweep wave of wlen: PR_SWEEP_FIRST if
+// set (0 splits the wave evenly), else wlen / 8. The first part's
+// preparation is the only one the sweep cannot overlap.
+static int sweep_first(int wlen) {
+  const char* e = getenv("PR_SWEEP_FIRST");
+  if (e && *e) return std::max(0, atoi(e));
+  return std::max(1, wlen / 8);
+}
+
 static int sweep_parts() {
   const char* e = getenv("PR_SWEEP_PARTS");
   const int v = (e && *e) ? atoi(e) : 4;
@@ -783,7 +792,15 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
       };
       const int nparts = std::max(1, std::min(sweep_parts(), (n1 - n0) / kMinPartItems));
       std::vector<int> cut;
-      for (int i = 0; i <= nparts; ++i) cut.push_back(n0 + (int)((long long)(n1 - n0) * i / nparts));
+      const int wlen = n1 - n0, first = sweep_first(wlen);
+      if (nparts > 1 && first > 0 && first <= wlen - (nparts - 1)) {
+        // a short first part: its preparation is the only one not overlapped
+        cut.push_back(n0);
+        for (int i = 0; i < nparts; ++i)
+          cut.push_back(n0 + first + (int)((long long)(wlen - first) * i / (nparts - 1)));
+      } else {
+        for (int i = 0; i <= nparts; ++i) cut.push_back(n0 + (int)((long long)wlen * i / nparts));
+      }
       std::vector<hipEvent_t> ready(nparts, nullptr);
       prep(cut[0], cut[1], s, ph);
       if (nparts > 1) {
