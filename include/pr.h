@@ -285,10 +285,14 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *                 (PR_EINVAL with PR_MODE_COARSE_GRID); costs two extra field
  *                 passes per sweep step
  * Environment: PR_SWEEP_PARTS (default 4; 1 = no second stream) cuts each
- * sweep wave into parts whose stage-2 POD overlaps the sweep of the part
- * before; PR_DEFER_CHOLQR (default 1; 0 = off) folds the stage-1 CholQR
- * into stage 2's block whitening. Neither changes the ranks; the first
- * leaves every bit alone, the second the iterates up to round-off.
+ * sweep wave into parts whose preparation (stage-1 and stage-2 POD, L Psi)
+ * overlaps the sweep of the part before; PR_SWEEP_FIRST (default wave / 8;
+ * 0 = even split) sizes the first part; PR_DEFER_POD1 (default 1; 0 = off)
+ * moves the stage-1 POD into those preparations; PR_DEFER_CHOLQR (default
+ * 1; 0 = off) folds the stage-1 CholQR into stage 2's block whitening;
+ * PR_STAGE_UPLOAD (default 1; 0 = off, read once per process) writes small
+ * descriptor blocks through kernel arguments. All keep the ranks; all but
+ * PR_DEFER_CHOLQR keep every bit, and that one the iterates up to round-off.
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
