@@ -290,9 +290,12 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  * 0 = even split) sizes the first part; PR_DEFER_POD1 (default 1; 0 = off)
  * moves the stage-1 POD into those preparations; PR_DEFER_CHOLQR (default
  * 1; 0 = off) folds the stage-1 CholQR into stage 2's block whitening;
+ * PR_SMALL_CHOLQR (default 1; 0 = off) takes stage 2's CholQR factor from
+ * C^T G C instead of a Gram pass over the formed modes;
  * PR_STAGE_UPLOAD (default 1; 0 = off, read once per process) writes small
  * descriptor blocks through kernel arguments. All keep the ranks; all but
- * PR_DEFER_CHOLQR keep every bit, and that one the iterates up to round-off.
+ * the two CholQR switches keep every bit, and those the iterates up to
+ * round-off.
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
  * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */

@@ -842,6 +842,14 @@ static ColDesc col_null() { return ColDesc{nullptr, nullptr, 0, 0}; }
 
 static long long tsmm_wgs(long long nrows) { return (nrows + 511) / 512; }
 
+// Whitened (stage-2) POD items take their CholQR factor from the coefficient
+// Gram C^T G C instead of a Gram pass over the formed modes
+// (PR_SMALL_CHOLQR, default 1; 0 = a pass over the modes).
+static bool small_cholqr() {
+  const char* e = getenv("PR_SMALL_CHOLQR");
+  return !(e && *e == '0');
+}
+
 void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
                  const std::string& tag) {
   if (items.empty()) return;
@@ -934,6 +942,33 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   EigDesc* edd = stage_push(c, ed);
   stage_flush(c, s);
   launch_eig_select(edd, nitems, s);
+  // whitened items: the CholQR factor from C^T G C (the modes' Gram in exact
+  // arithmetic) applied to the coefficients, so the modes are formed once
+  const bool small_cq = wdd && cq && small_cholqr();
+  if (small_cq) {
+    std::vector<CoefGramDesc> gd;
+    std::vector<CholDesc> cd;
+    for (int i = 0; i < nitems; ++i) {
+      CoefGramDesc x{};
+      x.G = G + (size_t)i * ldg * ldg;
+      x.ldg = ldg;
+      x.nc = (int)items[i].cols.size();
+      x.C = ed[i].coef;
+      x.ldc = items[i].cap;
+      x.cap = items[i].cap;
+      x.G2 = G2 + (size_t)i * 32 * 32;
+      x.U = coef2 + (size_t)i * 32 * 32;
+      PR_CHECK(x.nc <= 64 && x.cap <= 32, "coefficient Gram of at most 64 x 32");
+      gd.push_back(x);
+      cd.push_back(CholDesc{x.G2, 32, items[i].cap, items[i].m_out, coef2 + (size_t)i * 32 * 32});
+    }
+    CoefGramDesc* gdd = stage_push(c, gd);
+    CholDesc* cdd = stage_push(c, cd);
+    stage_flush(c, s);
+    launch_coef_gram(gdd, nitems, s);
+    launch_cholqr_coef(cdd, nitems, s);
+    launch_coef_apply(gdd, nitems, s);
+  }
   if (wdd) launch_block_unwhiten(wdd, nitems, s);   // coefficients of the raw blocks
 
   // 4. modes R = W Y_m Lambda_m^{-1/2}
@@ -970,7 +1005,7 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   // 5. CholQR in the M inner product (FP64 MFMA Gram, FP64 Cholesky). The
   // modes enter with kappa(R) ~ 1 + eps lambda_1 / lambda_m <= 1 + 1e-3, so
   // one pass already leaves eps kappa^2 ~ eps loss of orthogonality.
-  for (int pass = 0; pass < (cq ? kCholQRPasses : 0); ++pass) {
+  for (int pass = 0; pass < (cq && !small_cq ? kCholQRPasses : 0); ++pass) {
     std::vector<GramWork> g2;
     std::vector<std::vector<ColDesc>> rcols(nitems);
     for (int i = 0; i < nitems; ++i) {

@@ -332,6 +332,23 @@ struct CholDesc {
 };
 void launch_cholqr_coef(const CholDesc* d, int nitems, hipStream_t s);
 
+// CholQR of modes W C taken from the Gram G of W instead of a pass over the
+// modes: G2 = C^T G C (rows i of C with G_ii = 0 are skipped: zero columns of
+// W), then, after launch_cholqr_coef on G2, C <- C U with U its upper
+// triangular factor (zero beyond the rank).
+struct CoefGramDesc {
+  const double* G;   // nc x nc, leading dimension ldg
+  int ldg;
+  int nc;            // <= 64
+  double* C;         // nc x cap, leading dimension ldc (in place)
+  int ldc;
+  int cap;           // <= 32
+  double* G2;        // cap x cap, leading dimension 32
+  const double* U;   // cap x cap, leading dimension cap (launch_cholqr_coef's)
+};
+void launch_coef_gram(const CoefGramDesc* d, int nitems, hipStream_t s);
+void launch_coef_apply(const CoefGramDesc* d, int nitems, hipStream_t s);
+
 // Block whitening of a Gram over nb blocks of bs columns (block b's first
 // *m[b] columns valid, the rest zero rows and columns): with the Cholesky
 // factors T_b^T T_b = G_bb of the diagonal blocks (a pivot <= kDropPivot

@@ -246,6 +246,70 @@ void launch_cholqr_coef(const CholDesc* d, int nd, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// CholQR factors from the coefficient Gram (CoefGramDesc). One workgroup of
+// 256 threads per item.
+__global__ __launch_bounds__(256) void k_coef_gram(const CoefGramDesc* __restrict__ descs) {
+  const CoefGramDesc& d = descs[blockIdx.x];
+  __shared__ double Cs[64][33];
+  __shared__ double H[64][33];
+  __shared__ int live[64];
+  const int nc = d.nc, cap = d.cap, tid = threadIdx.x;
+  if (tid < 64) live[tid] = tid < nc && d.G[(long long)tid * d.ldg + tid] != 0.0;
+  __syncthreads();
+  for (int e = tid; e < nc * cap; e += 256) {
+    const int i = e / cap, a = e % cap;
+    Cs[i][a] = live[i] ? d.C[(long long)i * d.ldc + a] : 0.0;
+  }
+  __syncthreads();
+  // H = G C (G read from memory: at most 64 x 64, cached)
+  for (int e = tid; e < nc * cap; e += 256) {
+    const int i = e / cap, a = e % cap;
+    double v = 0.0;
+    if (live[i]) {
+      const double* gi = d.G + (long long)i * d.ldg;
+      for (int j = 0; j < nc; ++j)
+        if (live[j]) v += gi[j] * Cs[j][a];
+    }
+    H[i][a] = v;
+  }
+  __syncthreads();
+  // G2 = C^T H
+  for (int e = tid; e < cap * cap; e += 256) {
+    const int a = e / cap, b = e % cap;
+    double v = 0.0;
+    for (int i = 0; i < nc; ++i) v += Cs[i][a] * H[i][b];
+    d.G2[a * 32 + b] = v;
+  }
+}
+
+// C <- C U, U upper triangular (cap x cap, leading dimension 32)
+__global__ __launch_bounds__(256) void k_coef_apply(const CoefGramDesc* __restrict__ descs) {
+  const CoefGramDesc& d = descs[blockIdx.x];
+  __shared__ double Cs[64][33];
+  const int nc = d.nc, cap = d.cap, tid = threadIdx.x;
+  for (int e = tid; e < nc * cap; e += 256) Cs[e / cap][e % cap] = d.C[(long long)(e / cap) * d.ldc + e % cap];
+  __syncthreads();
+  for (int e = tid; e < nc * cap; e += 256) {
+    const int i = e / cap, a = e % cap;
+    double v = 0.0;
+    for (int b = 0; b <= a; ++b) v += Cs[i][b] * d.U[b * cap + a];
+    d.C[(long long)i * d.ldc + a] = v;
+  }
+}
+
+void launch_coef_gram(const CoefGramDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_coef_gram, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+void launch_coef_apply(const CoefGramDesc* d, int nd, hipStream_t s) {
+  if (nd <= 0) return;
+  hipLaunchKernelGGL(k_coef_apply, dim3(nd), dim3(256), 0, s, d);
+  PR_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
 // Descriptor upload through the kernel arguments.
 __global__ __launch_bounds__(256) void k_upload(const UploadBlob b, unsigned int* __restrict__ dst,
                                                 int nw) {

@@ -340,21 +340,24 @@ def test_parareal_waves_and_streams_do_not_change_bits(ctx, monkeypatch):
     monkeypatch.delenv("PR_SWEEP_PARTS")
 
 
-@pytest.mark.parametrize("defer", ["0", "1"])
-def test_parareal_stage1_cholqr_deferred_or_not(ctx, monkeypatch, defer):
-    """The stage-1 modes M-orthonormalised by their own CholQR (0) or left as
-    W y / sqrt(lambda), their Cholesky factors applied to the diagonal blocks
-    of the stage-2 Gram instead (1): the same iterates up to round-off and the
-    oracle's stage-2 ranks either way, with p = 1 so W^k_n holds three
+@pytest.mark.parametrize("defer,small", [("0", "1"), ("1", "1"), ("1", "0")])
+def test_parareal_stage1_cholqr_deferred_or_not(ctx, monkeypatch, defer, small):
+    """The stage-1 modes M-orthonormalised by their own CholQR (defer 0) or
+    left as W y / sqrt(lambda), their Cholesky factors applied to the
+    diagonal blocks of the stage-2 Gram instead (defer 1). The stage-2 CholQR
+    factor either comes from a Gram pass over the formed modes (small 0) or
+    from C^T G C (small 1). Every combination gives the same iterates up to
+    round-off and the oracle's stage-2 ranks, with p = 1 so W^k_n holds three
     stage-1 bases."""
     import paper_2601_10981_amd as pr
-    say(f"parareal stage-1 CholQR deferred={defer}")
+    say(f"parareal stage-1 CholQR deferred={defer} small={small}")
     prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
     u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
     p = pr.problem_of(prob)
     ores = parareal.solve(prob, opts, u0, keep_history=True)
     env = _roundoff_envelope(prob, opts, u0, ores, 3)
     monkeypatch.setenv("PR_DEFER_CHOLQR", defer)
+    monkeypatch.setenv("PR_SMALL_CHOLQR", small)
     for k in (2, 3):
         o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
         U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0))
@@ -365,6 +368,7 @@ def test_parareal_stage1_cholqr_deferred_or_not(ctx, monkeypatch, defer):
         say(f"  k={k} worst iterate rel L2 vs oracle {worst:.3e} (round-off envelope {env[k]:.3e})")
         assert worst <= 10.0 * env[k] + 1e-12
     monkeypatch.delenv("PR_DEFER_CHOLQR")
+    monkeypatch.delenv("PR_SMALL_CHOLQR")
 
 
 def test_parareal_zero_initial_state(ctx):
