@@ -1106,7 +1106,6 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   double* S2 = (double*)(sm + 4096);       // pass 2: R^T M d~ (cap), |d~|^2 at [32]
   double* S3 = (double*)(sm + 8192);       // pass 3: |d~|^2 after the second projection
   int* flag = (int*)(sm + 12288);
-  int* status = (int*)(sm + 12288 + 64);
   double* dscale = (double*)(sm + 12288 + 128);
   double* coef = (double*)(sm + 16384);    // cap + 1
   double* betas = (double*)(sm + 16384 + 512);  // 2 x (cap + 1)
@@ -1241,7 +1240,6 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   rd.beta = beta;
   rd.coef = coef;
   rd.n_c_out = w.n_c_out;
-  rd.status = status;
   launch_reduced_one(rd, s);
   std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
   if (w.diag_norms && w.n_in == 2 && w.fine) {

@@ -274,18 +274,19 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
 }
 
 // Sum of the per-chunk partials of one tile pair, scaled, written to the
-// output (and its mirror for the symmetric form). Workgroup (x, item) owns 64
-// of the pair's 256 entries (x = pair * 4 + quarter) in the original column
-// order; each entry is looked up at its compact position (the compaction of
-// k_gemm_tn, redone here), and entries of invalid columns are zero. The 16
-// wave groups each sum the chunks q, q + 16, q + 32, ... in that order (four
-// accumulators, one per residue of the chunk index modulo 64), and the
-// groups' sums combine in a fixed tree. The order depends only on the chunk
-// count, so the result does not depend on the batch.
+// output (and its mirror for the symmetric form). Workgroup (x, item) owns 16
+// of the pair's 256 entries (x = pair * 16 + sixteenth) in the original
+// column order; each entry is looked up at its compact position (the
+// compaction of k_gemm_tn, redone here), and entries of invalid columns are
+// zero. Its 256 threads form 16 chunk groups q = 0..15 of 16 threads (one per
+// entry). Group q sums the chunks q, q + 16, q + 32, ... into eight
+// accumulators, accumulator u taking the chunks congruent to q + 16 u modulo
+// 128 in increasing order; the eight combine as ((0+1)+(2+3))+((4+5)+(6+7)),
+// and the 16 groups' sums as the same tree over the pairs (2g, 2g + 1). The
+// order depends only on the chunk count, so the result does not depend on
+// the batch. Small workgroups start in the gaps that concurrent kernels leave
+// (a 1024-thread one waits for a nearly free CU).
 template <int NA, int NB>
-// One workgroup of 256 threads per 16 entries of a tile pair: 16 chunk
-// groups q of 16 entries each. Small workgroups start in the gaps that
-// concurrent kernels leave (a 1024-thread one waits for a nearly free CU).
 __global__ __launch_bounds__(256) void k_gemm_reduce(const GemmDesc* __restrict__ descs) {
   using PL = PairList<NA, NB>;
   constexpr int P = PL::P;
@@ -799,22 +800,27 @@ void launch_cgs(const CgsArgs& a, hipStream_t s) {
 }
 
 // out[0] = max_i sqrt(n[i][0] / n[i][1]) (jump), out[1] = max_i
-// sqrt(n[i][2] / n[i][3]) (error); NaN propagates.
+// sqrt(n[i][2] / n[i][3]) (error). A NaN in any of an item's norms (a NaN
+// or Inf in the iterate, the previous iterate or the reference) makes the
+// corresponding output NaN; fmax alone would drop it.
 __global__ void k_jump_max(const double* __restrict__ n4, int count, double* out) {
   if (threadIdx.x != 0) return;
   double e = 0.0, r = 0.0;
-  bool bad = false;
+  bool bad = false, bad_r = false;
   for (int i = 0; i < count; ++i) {
     const double j = n4[4 * i + 0], u = n4[4 * i + 1];
     const double ee = n4[4 * i + 2], rr = n4[4 * i + 3];
-    double q = (u > 0) ? sqrt(j / u) : (j > 0 ? INFINITY : 0.0);
+    if (j != j || u != u) bad = true;
+    if (ee != ee || rr != rr) bad_r = true;
+    const double q = (u > 0) ? sqrt(j / u) : (j > 0 ? INFINITY : 0.0);
     if (q != q) bad = true;
     e = fmax(e, q);
-    double qe = (rr > 0) ? sqrt(ee / rr) : 0.0;
+    const double qe = (rr > 0) ? sqrt(ee / rr) : 0.0;
+    if (qe != qe) bad_r = true;
     r = fmax(r, qe);
   }
   out[0] = bad ? NAN : e;
-  out[1] = r;
+  out[1] = bad_r ? NAN : r;
 }
 
 void launch_jump_max(const double* norms4, int count, double* out, hipStream_t s) {

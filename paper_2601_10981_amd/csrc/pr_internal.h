@@ -394,7 +394,6 @@ struct ReducedDesc {
   double* beta;      // n_in x (cap + 1): beta_i(dT)
   double* coef;      // nullable: (cap+1): beta_0 - beta_1 (correction coefficients)
   int* n_c_out;      // nullable
-  int* status;       // nullable: set to 1 if M_r is not positive definite
 };
 void launch_reduced(const ReducedDesc* d, int nitems, hipStream_t s);
 void launch_reduced_one(const ReducedDesc& d, hipStream_t s);

@@ -107,13 +107,16 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
     if (!rotated) break;
     __syncthreads();
   }
-  // descending order over all nc (original) indices, ties by index
+  // descending order over all nc (original) indices, ties by index. The sort
+  // key orders a NaN below everything, so the ranks stay a permutation (and
+  // every index read through `order` stays in range) whatever the data.
   auto val = [&](int i) -> double { const int p = kpos[i]; return p >= 0 ? A[p][p] : 0.0; };
+  auto key = [&](int i) -> double { const double v = val(i); return v == v ? v : -INFINITY; };
   if (tid < nc) {
-    const double li = val(tid);
+    const double li = key(tid);
     int rank = 0;
     for (int j = 0; j < nc; ++j) {
-      const double lj = val(j);
+      const double lj = key(j);
       if (lj > li || (lj == li && j < tid)) ++rank;
     }
     order[rank] = tid;
@@ -448,7 +451,9 @@ struct RedShared {
   int q, n_c, bad;
 };
 
-// Cholesky in place of sh.M (q x q, lower); sets bad on a non-positive pivot.
+// Cholesky in place of sh.M (q x q, lower); sets bad on a non-positive (or
+// NaN) pivot, which is then clamped only so the factorisation completes: the
+// callers turn bad into NaN coefficients.
 __device__ void red_cholesky(RedShared& sh, int q) {
   const int tid = threadIdx.x;
   for (int j = 0; j < q; ++j) {
@@ -652,6 +657,10 @@ __device__ void reduced_run(const ReducedDesc& d) {
   red_cholesky(sh, q);
   if (tid < d.n_in) red_solve(sh, q, sh.beta[tid], 1);
   __syncthreads();
+  // M_r not positive definite (a NaN or a breakdown): the coefficients become
+  // NaN, so the correction and its jump norm carry the failure to the host
+  if (sh.bad && tid < d.n_in * q) sh.beta[tid / q][tid % q] = NAN;
+  __syncthreads();
   if (d.forced) {
     red_forced_setup(sh, q, np, d.dT, d.n_c);
     red_advance_forced(sh, q, d.n_in, np, d.forced, d.w, d.t0, d.dT);
@@ -674,7 +683,6 @@ __device__ void reduced_run(const ReducedDesc& d) {
   }
   if (tid == 0) {
     if (d.n_c_out) *d.n_c_out = sh.n_c;
-    if (d.status) *d.status = sh.bad;
   }
 }
 
@@ -724,6 +732,8 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   __syncthreads();
   red_cholesky(sh, q);
   if (tid == 0) red_solve(sh, q, sh.beta[0], 1);
+  __syncthreads();
+  if (sh.bad && tid < q) sh.beta[0][tid] = NAN;   // as in reduced_run
   __syncthreads();
   if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c);
   else red_propagator(sh, q, d.dT, d.n_c);
