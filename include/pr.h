@@ -242,10 +242,15 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
 
 /* ---------------------------------------------------------------------------
  * The adaptive parareal solve (formula4, Algorithm 2).
- * [0, T] is split into N subintervals of DeltaT = T / N; subinterval 0 is the
- * warm-up window [0, T_0] (T_0 = DeltaT) whose fine solve gives G_0 (Case I);
- * the parareal partition of [T_0, T] has N - 1 subintervals. Subinterval i
- * of [0, T] starts at t = i DeltaT (the time the forced flows read).
+ * [0, T] is split into N subintervals of DeltaT = T / N; the first n_warm of
+ * them form the warm-up window [0, T_0], T_0 = n_warm DeltaT (the paper runs
+ * the adaptive method with T_0 = DeltaT and its Parareal-I comparison with
+ * T_0 = 2 DeltaT, Sec. 4), whose fine solve gives G_0 (Case I): snapshots
+ * every dM steps across the whole window, floor(n_warm n_f / dM) + 1 <= 64
+ * of them (POD modes only). The parareal partition of [T_0, T] has
+ * N' = N - n_warm subintervals; U_out rows 1 .. n_warm are fine states.
+ * Subinterval i of [0, T] starts at t = i DeltaT (the time the forced flows
+ * read).
  *   fine steps    n_f = ceil(DeltaT / dt - 1e-9), delta_t = DeltaT / n_f;
  *                 dt <= 0 requests min(2e-3, 1.3 / rho) with the bound
  *                 rho = 12 kappa / h^2 + sum_d max|v_d| / h (max|v_d| from
@@ -258,8 +263,8 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  *                 iterations; 0 <= m_l, 0 <= p <= 1), rank caps cap0 (stage
  *                 1 and k = 0 use cap) and cap
  *   stopping      e_k = max_n ||U^k_n - U^{k-1}_n||_M / ||U^k_n||_M <= tol,
- *                 or k = N - 1 (finite termination), or k = max_iter
- *                 (max_iter <= 0: N - 1)
+ *                 or k = N' (finite termination), or k = max_iter
+ *                 (max_iter <= 0: N')
  *   u0            device, N_g doubles (t = 0)
  *   U_out         device, (N + 1) x N_g doubles: U_out[j] = state at j DeltaT
  *   U_ref         NULL or device (N + 1) x N_g doubles (serial fine
@@ -290,15 +295,18 @@ pr_status pr_coarse_propagate(pr_ctx* ctx, int batch, const pr_coarse_item* item
  * 0 = even split) sizes the first part; PR_DEFER_POD1 (default 1; 0 = off)
  * moves the stage-1 POD into those preparations; PR_DEFER_CHOLQR (default
  * 1; 0 = off) folds the stage-1 CholQR into stage 2's block whitening;
- * PR_SMALL_CHOLQR (default 1; 0 = off) takes stage 2's CholQR factor from
- * C^T G C instead of a Gram pass over the formed modes;
+ * PR_SMALL_CHOLQR (default 1; 0 = off; PR_F64 only) takes stage 2's CholQR
+ * factor from C^T G C instead of a Gram pass over the formed modes (the
+ * modes then keep an M-orthogonality error of about eps lambda_1 /
+ * lambda_m, at most about 1e-3; the span and the Galerkin system, which
+ * keeps M_r explicitly, are unchanged);
  * PR_STAGE_UPLOAD (default 1; 0 = off, read once per process) writes small
  * descriptor blocks through kernel arguments. All keep the ranks; all but
  * the two CholQR switches keep every bit, and those the iterates up to
  * round-off.
  * The call synchronises `stream` once per iteration (8-byte jump read) and
  * before returning. Returns PR_ENOTCONV (outputs = last iterate) when
- * max_iter < N - 1 stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
+ * max_iter < N' stops it above tol, PR_ENUMERIC on a NaN/Inf jump. */
 typedef struct {
   double T;
   int N;
@@ -312,6 +320,7 @@ typedef struct {
   int max_iter;
   int mode;        /* PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD or PR_MODE_COARSE_GRID */
   int diag;        /* 1: coarse-gap diagnostics (see above)                   */
+  int n_warm;      /* warm-up window (see above): T_0 = n_warm DeltaT; 0 = 1 */
   const double* U_ref;
 } pr_parareal_opts;
 
@@ -319,7 +328,7 @@ typedef struct {
 typedef struct {
   int iters;          /* parareal iterations performed (k_max)            */
   int converged;      /* 1 if e_k <= tol or finite termination            */
-  int n_f, dM, n_s, n_c, n_sub; /* derived sizes (n_sub = N - 1)          */
+  int n_f, dM, n_s, n_c, n_sub; /* derived sizes (n_sub = N' = N - n_warm) */
   int m0;             /* rank of V^0_POD                                   */
   double* jump;       /* [max_iter + 1]: jump[k - 1] = e_k                 */
   double* err;        /* [max_iter + 1]: err[k] vs U_ref (k = 0..iters)    */
@@ -343,13 +352,13 @@ pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,
  * to (prob, opts). n_c is before the stability guard, which the device may
  * raise per coarse step. Errors as pr_parareal_solve's validation. */
 typedef struct {
-  int n_sub;      /* N - 1 parareal subintervals                             */
+  int n_sub;      /* N' = N - n_warm parareal subintervals                   */
   int n_f;        /* fine steps per subinterval                              */
   double dt;      /* fine step delta_t = DeltaT / n_f                        */
   int dM;         /* snapshot stride                                         */
   int n_s;        /* snapshots per subinterval, floor(n_f / dM) + 1          */
   int n_c;        /* coarse steps per subinterval                            */
-  int max_iter;   /* iteration limit after clamping to N - 1                 */
+  int max_iter;   /* iteration limit after clamping to N'                    */
 } pr_plan_info;
 pr_status pr_plan(const pr_grid_problem* prob, const pr_parareal_opts* opts, pr_plan_info* out);
 

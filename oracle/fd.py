@@ -276,6 +276,24 @@ def fine_propagate(op: Operator, u0: np.ndarray, dt: float, n_steps: int,
     return phi, None
 
 
+def fine_window(op: Operator, u0: np.ndarray, dt: float, n_f: int, n_sub: int, dM: int):
+    """The warm-up solve of Sec. 3.2 Case I over [0, T_0], T_0 = n_sub DeltaT
+    (n_sub subintervals of n_f steps, from t = 0): the snapshot matrix W_h of
+    the states at steps 0, dM, 2 dM, ... <= n_sub n_f (one contiguous
+    sequence over the window, n_s = floor(n_sub n_f / dM) + 1 columns) and the
+    states at the window's subinterval ends DeltaT, ..., n_sub DeltaT."""
+    phi = np.array(u0, dtype=np.float64, copy=True)
+    snaps = [phi.reshape(-1).copy()]
+    ends = []
+    for j in range(1, n_sub * n_f + 1):
+        phi = rk4_step(op, phi, dt, (j - 1) * dt)
+        if j % dM == 0:
+            snaps.append(phi.reshape(-1).copy())
+        if j % n_f == 0:
+            ends.append(phi.copy())
+    return ends, np.stack(snaps, axis=1)
+
+
 def serial_fine(op: Operator, u0: np.ndarray, dT_sub: float, N: int, dt_req: float):
     """Reference solution U_n of the error metric (eq. error): the fine
     propagator applied serially from the exact initial value, returned at

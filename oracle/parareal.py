@@ -1,13 +1,16 @@
 """Adaptive parareal iteration of the oracle (formula4, Algorithm 2).
 
 Numbering (reading of where T_0 sits): [0, T] is split into N subintervals of
-length DeltaT. The warm-up window [0, T_0] is subinterval 0 (T_0 = DeltaT, as
-in the paper's runs), so the parareal partition of [T_0, T] has N' = N - 1
-subintervals and states U_n at t_hat_n = (n + 1) DeltaT, n = 0..N'. U_0 is the
-fine solution at T_0 (u_hat_0 of Case I).
+length DeltaT. The warm-up window [0, T_0] is the first w = opts.n_warm of
+them (T_0 = w DeltaT; w = 1 in the paper's runs of the adaptive method, w = 2
+for its Parareal-I runs, Sec. 4), so the parareal partition of [T_0, T] has
+N' = N - w subintervals and states U_n at t_hat_n = (n + w) DeltaT,
+n = 0..N'. U_0 is the fine solution at T_0 (u_hat_0 of Case I); the states
+at DeltaT, ..., (w - 1) DeltaT inside the window are fine states too.
 
-k = 0 (Algorithm 2, initialisation): fine solve on [0, T_0] with snapshots,
-POD_Mode(W, gamma_1) gives G_0, and U^0_{n+1} = G_0(P U^0_n).
+k = 0 (Algorithm 2, initialisation): fine solve on [0, T_0] with snapshots
+(one sequence every dM steps over the whole window), POD_Mode(W, gamma_1)
+gives G_0, and U^0_{n+1} = G_0(P U^0_n).
 
 k >= 1 (Algorithm 2, the iteration):
   (i)   F(U^{k-1}_n) and the snapshots W^k_{n,0} for n = k-1..N'-1;
@@ -26,8 +29,8 @@ k >= 1 (Algorithm 2, the iteration):
 mode = 1 is the comparison method "Parareal-I" of Sec. 4: plain parareal
 (formula4 without augmentation) whose coarse propagator is the Galerkin POD
 propagator G_0 of the k = 0 step, kept for every iteration; steps (i) and
-(ii) build no bases. Its POD window is the same warm-up subinterval
-[0, T_0], T_0 = DeltaT.
+(ii) build no bases. Its POD window is the warm-up window [0, T_0] (the
+paper takes T_0 = 2 DeltaT there: n_warm = 2).
 
 mode = 2 is "Parareal-II" of Sec. 4: plain parareal whose coarse propagator
 solves the same equation on the coarse n/2 grid (gridcoarse.py); no POD at
@@ -43,7 +46,7 @@ with G_k the coarse propagator of that step (adaptive and fixed-POD modes).
 
 Time: subinterval i of [0, T] starts at i DeltaT, so the warm-up solve starts
 at t = 0 and the fine and coarse solves from U_n (n = 0..N'-1) start at
-t_hat_n = (n + 1) DeltaT; fine step j of a solve from t starts at t + j dt.
+t_hat_n = (n + w) DeltaT; fine step j of a solve from t starts at t + j dt.
 Only the forced time-dependent flows read the time.
 """
 from __future__ import annotations
@@ -64,6 +67,7 @@ from . import pod as P
 @dataclasses.dataclass
 class Result:
     U: List[np.ndarray]           # N + 1 states at t = j DeltaT (U[0] = u0)
+    # (history[k][n] and ranks are in parareal numbering: time index n + w)
     iters: int
     converged: bool
     jumps: List[float]            # e_k, k = 1..iters
@@ -91,7 +95,12 @@ def requested_dt(prob, opts) -> float:
 
 
 def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
-          tau_r: float = P.TAU_R_F64, keep_history: bool = False) -> Result:
+          tau_r: float = P.TAU_R_F64, keep_history: bool = False,
+          trace: Optional[dict] = None) -> Result:
+    """Algorithm 2 (see the module docstring). ``trace``, when a dict, receives
+    the intermediate POD data of the adaptive mode for tests:
+    trace[("R0", k, n)] = R^k_{n,0} (stage-1 basis of iteration k) and
+    trace[("W", k, n)] = W^k_n (the stage-2 input of the sweep step from n)."""
     op = fd.Operator.of(prob)
     n = prob.n
     h3 = op.h ** 3
@@ -99,33 +108,37 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
     dT_sub = opts.T / N
     n_f, dt = fd.steps_per_subinterval(dT_sub, requested_dt(prob, opts))
     dM = fd.snapshot_stride(n_f, opts.dM)
-    Np = N - 1
+    nw = int(getattr(opts, "n_warm", 1))
+    if not 1 <= nw <= N:
+        raise ValueError("n_warm must be in [1, N]")
+    Np = N - nw
     n_c0 = C.coarse_steps(n_f, opts.coarse_ratio)
     max_iter = opts.max_iter if opts.max_iter > 0 else Np
     t_phase = {"F": 0.0, "C": 0.0, "U": 0.0, "A": 0.0, "G": 0.0}
     u0v = np.asarray(u0, dtype=np.float64).reshape(-1)
 
     def t_hat(j):
-        return (j + 1) * dT_sub
+        return (j + nw) * dT_sub
 
     def err_of(states):
         if U_ref is None:
             return None
         e = 0.0
         for j in range(1, len(states)):
-            ref = np.asarray(U_ref[j + 1]).reshape(-1)
+            ref = np.asarray(U_ref[j + nw]).reshape(-1)
             e = max(e, _norm_m(states[j] - ref, h3) / _norm_m(ref, h3))
         return e
 
     # ---- k = 0: Case I ----------------------------------------------------
     t0 = time.perf_counter()
-    F0, W = fd.fine_propagate(op, u0v.reshape(n, n, n), dt, n_f, dM, t0=0.0)
+    ends, W = fd.fine_window(op, u0v.reshape(n, n, n), dt, n_f, nw, dM)
     t_phase["F"] += time.perf_counter() - t0
-    U0hat = F0.reshape(-1)
+    U0hat = ends[-1].reshape(-1)
+    warm = [u0v.copy()] + [e.reshape(-1) for e in ends[:-1]]   # time indices 0..w-1
     mode = getattr(opts, "mode", 0)
     if mode == 2:
-        return _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter,
-                                  err_of, keep_history, t_phase, h3)
+        return _solve_coarse_grid(prob, opts, op, warm, U0hat, n_f, dt, dM, n_c0, max_iter,
+                                  err_of, keep_history, t_phase, h3, nw)
     t0 = time.perf_counter()
     R0, m0, _ = P.pod_mode(W, opts.gamma1, h3, opts.cap, tau_r)
     t_phase["C"] += time.perf_counter() - t0
@@ -162,7 +175,7 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
         F = Fk[nn]
         gap_fine[kk].append(_norm_m(F - g_old, h3) / _norm_m(F, h3))
         if U_ref is not None:
-            ref = np.asarray(U_ref[nn + 2]).reshape(-1)
+            ref = np.asarray(U_ref[nn + 1 + nw]).reshape(-1)
             gap_ref[kk].append(_norm_m(ref - g_new, h3) / _norm_m(ref, h3))
 
     while not converged and k < max_iter:
@@ -190,6 +203,8 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
             t_phase["C"] += time.perf_counter() - t0
             hist[k][nn] = R
             ranks0[k].append(m)
+            if trace is not None:
+                trace[("R0", k, nn)] = R
 
         def latest(j):
             return hist[min(k, j + 1)][j]
@@ -216,6 +231,8 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
             blocks = [latest(j) for j in range(nn - opts.ml, nn + 1) if j >= 0]
             blocks += [hist[k - i][nn] for i in range(1, opts.p + 1) if k - i >= 1]
             Wkn = np.concatenate(blocks, axis=1)
+            if trace is not None:
+                trace[("W", k, nn)] = Wkn
             Rkn, mkn, _ = P.pod_mode(Wkn, opts.gamma3, h3, opts.cap, tau_r)
             t_phase["C"] += time.perf_counter() - t0
             ranks[k].append(mkn)
@@ -256,21 +273,21 @@ def solve(prob, opts, u0: np.ndarray, U_ref: Optional[List[np.ndarray]] = None,
         U_prev = U_cur
         converged = (e <= opts.tol) or (k == Np)
 
-    U_out = [u0v.copy()] + [u.copy() for u in U_prev]
+    U_out = [u.copy() for u in warm] + [u.copy() for u in U_prev]
     return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
                   ranks=ranks, ranks0=ranks0, m0=m0, n_f=n_f, dt=dt, dM=dM,
                   n_c=n_c, history=history, t_phase=t_phase,
                   gap_fine=gap_fine if diag else {}, gap_ref=gap_ref if diag else {})
 
 
-def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, err_of,
-                       keep_history, t_phase, h3) -> Result:
+def _solve_coarse_grid(prob, opts, op, warm, U0hat, n_f, dt, dM, n_c0, max_iter, err_of,
+                       keep_history, t_phase, h3, nw) -> Result:
     """Parareal-II: U^0_{n+1} = G(U^0_n) and, for k >= 1,
     U^k_{n+1} = G(U^k_n) + F(U^{k-1}_n) - G(U^{k-1}_n), G the coarse-grid
     propagator (formula4 with the coarse spatial discretisation)."""
     n = prob.n
     N = opts.N
-    Np = N - 1
+    Np = N - nw
     dT_sub = opts.T / N
     prob_c = GC.coarse_problem(prob)
     op_c = fd.Operator.of(prob_c)
@@ -278,7 +295,7 @@ def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, 
 
     def G(u, j):
         t0 = time.perf_counter()
-        v = GC.coarse_grid_propagate(op_c, u, dT_sub, n_g, t0=(j + 1) * dT_sub)
+        v = GC.coarse_grid_propagate(op_c, u, dT_sub, n_g, t0=(j + nw) * dT_sub)
         t_phase["G"] += time.perf_counter() - t0
         return v
 
@@ -299,7 +316,7 @@ def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, 
         for nn in range(k - 1, Np):
             t0 = time.perf_counter()
             Fn, _ = fd.fine_propagate(op, U_prev[nn].reshape(n, n, n), dt, n_f,
-                                      t0=(nn + 1) * dT_sub)
+                                      t0=(nn + nw) * dT_sub)
             t_phase["F"] += time.perf_counter() - t0
             Fk[nn] = Fn.reshape(-1)
         U_cur = [U_prev[j] for j in range(k)]
@@ -319,7 +336,7 @@ def _solve_coarse_grid(prob, opts, op, u0v, U0hat, n_f, dt, dM, n_c0, max_iter, 
             history.append(list(U_cur))
         U_prev = U_cur
         converged = (e <= opts.tol) or (k == Np)
-    U_out = [u0v.copy()] + [u.copy() for u in U_prev]
+    U_out = [u.copy() for u in warm] + [u.copy() for u in U_prev]
     return Result(U=U_out, iters=k, converged=converged, jumps=jumps, errors=errors,
                   ranks={}, ranks0={}, m0=0, n_f=n_f, dt=dt, dM=dM, n_c=n_g,
                   history=history, t_phase=t_phase)

@@ -285,6 +285,7 @@ def opts_struct(o, U_ref=None) -> L.pr_parareal_opts:
     s.max_iter = int(getattr(o, "max_iter", 0))
     s.mode = int(getattr(o, "mode", 0))
     s.diag = int(getattr(o, "diag", 0))
+    s.n_warm = int(getattr(o, "n_warm", 1))
     s.U_ref = _ptr(U_ref)
     return s
 
@@ -315,11 +316,12 @@ class Report:
 class _ReportBuffers:
     """Host arrays a pr_report points into, sized for at most kmax iterations."""
 
-    def __init__(self, N: int, max_iter: int):
+    def __init__(self, N: int, max_iter: int, n_warm: int = 1):
         self.N = N
-        self.n_sub = max(N - 1, 1)
-        kmax = max_iter if max_iter > 0 else N - 1
-        kmax = max(0, min(kmax, N - 1))
+        self.Np = N - max(1, n_warm)          # parareal subintervals N'
+        self.n_sub = max(self.Np, 1)
+        kmax = max_iter if max_iter > 0 else self.Np
+        kmax = max(0, min(kmax, self.Np))
         cap = kmax + 1
         self.jump = (ctypes.c_double * cap)()
         self.err = (ctypes.c_double * cap)()
@@ -342,7 +344,7 @@ class _ReportBuffers:
                       jump=[self.jump[i] for i in range(k)],
                       err=[self.err[i] for i in range(k + 1)] if has_ref else [],
                       t_iter=[self.t_iter[i] for i in range(k + 1)],
-                      ranks=[[self.ranks[kk * n_sub + n] for n in range(kk, N - 1)]
+                      ranks=[[self.ranks[kk * n_sub + n] for n in range(kk, self.Np)]
                              for kk in range(1, k + 1)],
                       t_phase=dict(zip("FCUAG", list(rep.t_phase))),
                       fine_updates=rep.fine_updates, seconds=rep.seconds,
@@ -351,7 +353,7 @@ class _ReportBuffers:
     def _gaps(self, arr, k):
         out = {}
         for kk in range(1, k + 1):
-            row = [arr[kk * self.n_sub + n] for n in range(kk, self.N - 1)]
+            row = [arr[kk * self.n_sub + n] for n in range(kk, self.Np)]
             if row and all(v >= 0 for v in row):
                 out[kk] = row
         return out
@@ -370,7 +372,7 @@ def pr_parareal_solve(ctx: Context, prob: L.pr_grid_problem, opts, u0, U_out=Non
     if U_ref is not None:
         _check_dev(U_ref, torch.float64, (N + 1) * ng, "U_ref")
     o = opts_struct(opts, U_ref)
-    rb = _ReportBuffers(N, int(getattr(opts, "max_iter", 0)))
+    rb = _ReportBuffers(N, int(getattr(opts, "max_iter", 0)), int(getattr(opts, "n_warm", 1)))
     st = ctx.lib.pr_parareal_solve(ctx.h, ctypes.byref(prob), ctypes.byref(o), _ptr(u0),
                                    _ptr(U_out), ctypes.byref(rb.rep), _stream(stream))
     if st != L.PR_OK and not (allow_notconv and st == -5):
@@ -462,7 +464,8 @@ def pr_solve_end(ctx: Context, handle: SolveHandle, U_out=None, stream=None,
         U_out = torch.empty((N + 1, ng), dtype=torch.float64, device="cuda")
     if U_out is not False:
         _check_dev(U_out, torch.float64, (N + 1) * ng, "U_out")
-    rb = _ReportBuffers(N, int(getattr(handle.opts, "max_iter", 0)))
+    rb = _ReportBuffers(N, int(getattr(handle.opts, "max_iter", 0)),
+                        int(getattr(handle.opts, "n_warm", 1)))
     h = handle.h
     handle.h = None
     st = ctx.lib.pr_solve_end(ctx.h, ctypes.c_void_p(h), None if U_out is False else _ptr(U_out),

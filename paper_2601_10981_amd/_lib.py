@@ -49,7 +49,7 @@ class pr_parareal_opts(Structure):
                 ("gamma1", c_double), ("gamma2", c_double), ("gamma3", c_double),
                 ("cap0", c_int), ("cap", c_int), ("ml", c_int), ("p", c_int),
                 ("coarse_ratio", c_int), ("tol", c_double), ("max_iter", c_int),
-                ("mode", c_int), ("diag", c_int), ("U_ref", c_void_p)]
+                ("mode", c_int), ("diag", c_int), ("n_warm", c_int), ("U_ref", c_void_p)]
 
 
 class pr_report(Structure):

@@ -943,8 +943,14 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
   stage_flush(c, s);
   launch_eig_select(edd, nitems, s);
   // whitened items: the CholQR factor from C^T G C (the modes' Gram in exact
-  // arithmetic) applied to the coefficients, so the modes are formed once
-  const bool small_cq = wdd && cq && small_cholqr();
+  // arithmetic) applied to the coefficients, so the modes are formed once.
+  // That factor cannot remove the rounding of G itself (about eps lambda_1
+  // absolute), so the modes keep an M-orthogonality error of about
+  // eps lambda_1 / lambda_m: at most about 1e-3 in FP64 with tau_r = 1e-13
+  // (harmless: the Galerkin system keeps M_r explicitly and the span is
+  // unchanged), but up to 1e-1 for the FP32 Gram of PR_MIXED, which
+  // therefore takes the Gram pass over the formed modes.
+  const bool small_cq = wdd && cq && small_cholqr() && !f32;
   if (small_cq) {
     std::vector<CoefGramDesc> gd;
     std::vector<CholDesc> cd;

@@ -36,6 +36,8 @@ struct Plan {
   pr_grid_problem prob;
   pr_parareal_opts o;
   int N, Np, n_f, dM, n_s, n_c, max_iter;
+  int nw;          // subintervals of the warm-up window [0, T_0] (T_0 = nw DeltaT)
+  int n_s0;        // snapshots of the warm-up solve, floor(nw n_f / dM) + 1
   double dTs, dt;
   long long ng;
   bool f32;
@@ -55,9 +57,9 @@ struct Plan {
   size_t cs;       // bytes per column of those blocks (ld x field size)
 };
 
-// Start time of parareal subinterval n (state U_n at t_hat_n = (n + 1) DeltaT;
-// subinterval 0 of [0, T] is the warm-up window).
-static double t_hat(const Plan& P, int n) { return (double)(n + 1) * P.dTs; }
+// Start time of parareal subinterval n (state U_n at t_hat_n = (n + nw) DeltaT;
+// subintervals 0 .. nw - 1 of [0, T] form the warm-up window).
+static double t_hat(const Plan& P, int n) { return (double)(n + P.nw) * P.dTs; }
 
 static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   check_problem(p);
@@ -90,7 +92,9 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   PR_CHECK(o->coarse_ratio >= 1, "coarse_ratio must be >= 1");
   PR_CHECK(std::isfinite(o->tol) && o->tol >= 0, "tol must be >= 0");
   P.N = o->N;
-  P.Np = o->N - 1;
+  P.nw = o->n_warm > 0 ? o->n_warm : 1;
+  PR_CHECK(P.nw <= o->N, "the warm-up window must lie inside [0, T] (n_warm <= N)");
+  P.Np = o->N - P.nw;
   P.dTs = o->T / o->N;
   // dt <= 0: half the RK4 stability radius over the spectral bound, at most 2e-3
   const double dt_req = o->dt > 0 ? o->dt : std::min(2e-3, 0.5 * kStabRK4 / spectral_bound(*p));
@@ -100,6 +104,9 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   P.dM = std::max(1, P.dM);
   P.n_s = P.n_f / P.dM + 1;
   PR_CHECK(P.n_s <= kMaxPodCols, "too many snapshots per subinterval (n_f / dM + 1 > 64)");
+  P.n_s0 = (int)(((long long)P.nw * P.n_f) / P.dM + 1);
+  PR_CHECK(P.n_s0 <= kMaxPodCols || o->mode == PR_MODE_COARSE_GRID,
+           "too many warm-up snapshots (n_warm n_f / dM + 1 > 64)");
   P.n_c = std::max(1, (int)std::ceil(P.n_f / (double)o->coarse_ratio));
   P.max_iter = o->max_iter > 0 ? std::min(o->max_iter, P.Np) : P.Np;
   P.ng = ngrid(*p);
@@ -129,11 +136,14 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
   // every basis separately, and the np forcing fields stay resident.
   P.np = flow_pieces(*p);
   P.forced = forced_flow(*p);
+  // the warm-up solve's snapshots beyond one subinterval's (n_warm > 1)
+  const size_t warm_snaps = (size_t)std::max(0, P.n_s0 - P.n_s) * cs;
   P.fixed_bytes = 2 * (size_t)(P.Np + 1) * f8 + Np1 * f8 +
                   (P.grid ? 0
-                          : (P.fixed ? (size_t)P.n_s * cs + (1 + (size_t)P.np) * o->cap * cs
-                                     : 2 * Np1 * o->cap0 * cs)) +
-                  (P.forced && !P.grid ? (size_t)P.np * cs : 0) + f8 + ((size_t)4 << 20) +
+                          : (P.fixed ? (size_t)P.n_s0 * cs + (1 + (size_t)P.np) * o->cap * cs
+                                     : 2 * Np1 * o->cap0 * cs + warm_snaps)) +
+                  (P.forced && !P.grid ? (size_t)P.np * cs : 0) + (size_t)P.nw * f8 +
+                  ((size_t)4 << 20) +
                   (P.diag ? (size_t)(P.max_iter + 1) * Np1 * 8 * 8 : 0);
   P.perF = plain ? 0 : (size_t)P.n_s * cs;        // snapshots of one subinterval
   // stage-2 basis and the pieces of L applied to it
@@ -326,20 +336,23 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     const size_t f8 = (size_t)ng * 8, fs = (size_t)ng * P.sf;
     const int Np = P.Np;
     const size_t Np1 = (size_t)std::max(Np, 1);
+    // S->u0: the warm-up window's states u0, F(DeltaT), ..., at t = j DeltaT,
+    // j < nw (the first nw rows of U_out)
     if (U_out) {
       S->ext_out = true;
-      S->U[0] = U_out + ng;
+      S->U[0] = U_out + (size_t)P.nw * ng;
       S->u0 = U_out;
     } else {
       S->U[0] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
-      S->u0 = (double*)owned_alloc(c, S, f8);
+      S->u0 = (double*)owned_alloc(c, S, (size_t)P.nw * f8);
     }
     S->U[1] = (double*)owned_alloc(c, S, (size_t)(Np + 1) * f8);
     S->Fn = (double*)owned_alloc(c, S, Np1 * f8);
     const size_t cs = P.cs;
     S->R0 = (P.fixed || P.grid) ? nullptr : (char*)owned_alloc(c, S, 2 * Np1 * P.o.cap0 * cs);
     if (!P.grid) {
-      S->snaps = (char*)owned_alloc(c, S, (size_t)(P.fixed ? 1 : P.waveF) * P.n_s * cs);
+      S->snaps = (char*)owned_alloc(
+          c, S, (size_t)std::max((P.fixed ? 1 : P.waveF) * P.n_s, P.n_s0) * cs);
       S->Psi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.o.cap * cs);
       S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * cs);
       if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * cs);
@@ -378,22 +391,29 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     ph.s = s;
     stage_begin(c, s);
     ph.begin(0);
-    enqueue_fine(c, {FineWork{&S->P.prob, P.dt, P.n_f, S->u0, Ua, P.grid ? 0 : P.dM,
-                              P.grid ? nullptr : S->snaps, 0.0, 0, P.ld}},
-                 s, "sol_fine");
-    S->fine_updates += (double)P.n_f * ng;
+    // the warm-up solve over [0, T_0] with its snapshots, and the window's
+    // inner subinterval ends (the same steps from u0, so bitwise the states
+    // the long solve passes through)
+    std::vector<FineWork> warm{FineWork{&S->P.prob, P.dt, P.nw * P.n_f, S->u0, Ua,
+                                        P.grid ? 0 : P.dM, P.grid ? nullptr : S->snaps, 0.0, 0,
+                                        P.ld}};
+    for (int j = 1; j < P.nw; ++j)
+      warm.push_back(FineWork{&S->P.prob, P.dt, j * P.n_f, S->u0, S->u0 + (size_t)j * ng, 0,
+                              nullptr, 0.0, 0, 0});
+    enqueue_fine(c, warm, s, "sol_fine");
+    S->fine_updates += (double)P.nw * P.n_f * ng;
     if (Np > 0 && P.grid) {
       // U^0_{n+1} = G(U^0_n) with the coarse-grid propagator
       ph.begin(4);
       for (int n = 0; n < Np; ++n)
         enqueue_grid_step(c, S, Ua + (size_t)n * ng, nullptr, nullptr, Ua + (size_t)(n + 1) * ng,
-                          nullptr, S->U_ref ? S->U_ref + (size_t)(n + 2) * ng : nullptr,
+                          nullptr, S->U_ref ? S->U_ref + (size_t)(n + 1 + P.nw) * ng : nullptr,
                           S->norms + 4 * (n + 1), t_hat(P, n), s);
     } else if (Np > 0) {
       ph.begin(1);
       PodWork pw;
       pw.prob = &S->P.prob;
-      for (int j = 0; j < P.n_s; ++j) pw.cols.push_back(colp(S->snaps, j, P.ld, P.f32, nullptr));
+      for (int j = 0; j < P.n_s0; ++j) pw.cols.push_back(colp(S->snaps, j, P.ld, P.f32, nullptr));
       pw.gamma = P.o.gamma1;
       pw.cap = cap;
       pw.force_m = -1;
@@ -442,6 +462,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       d.w = P.forced ? p.fp[2] : 0.0;
       d.dT = P.dTs;
       d.n_c = P.n_c;
+      d.n_warm = P.nw;
       d.count = Np;
       d.betas = S->betas0;
       d.ld_out = 32;
@@ -454,11 +475,11 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       for (int n = 0; n < Np; ++n)
         enqueue_correct(c, ng, psi, S->betas0 + (size_t)n * 32, nullptr, 0,
                         Ua + (size_t)(n + 1) * ng, nullptr,
-                        S->U_ref ? S->U_ref + (size_t)(n + 2) * ng : nullptr,
+                        S->U_ref ? S->U_ref + (size_t)(n + 1 + P.nw) * ng : nullptr,
                         S->norms + 4 * (n + 1), h3, s, "sol");
     }
     enqueue_correct(c, ng, {}, nullptr, Ua, 0, Ua, nullptr,
-                    S->U_ref ? S->U_ref + (size_t)1 * ng : nullptr, S->norms, h3, s, "sol");
+                    S->U_ref ? S->U_ref + (size_t)P.nw * ng : nullptr, S->norms, h3, s, "sol");
     ph.end();
     PR_HIP(hipMemcpyAsync(S->U[1], Ua, f8, hipMemcpyDeviceToDevice, s));
     launch_jump_max(S->norms, Np + 1, S->dscal, s);
@@ -697,7 +718,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         enqueue_grid_step(c, S, Ucur + (size_t)n * ng, Uprev + (size_t)n * ng,
                           S->Fn + (size_t)n * ng, Ucur + (size_t)(n + 1) * ng,
                           Uprev + (size_t)(n + 1) * ng,
-                          Uref ? Uref + (size_t)(n + 2) * ng : nullptr, S->norms + 4 * (n + 1),
+                          Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr, S->norms + 4 * (n + 1),
                           t_hat(P, n), s);
     }
     // (iv) for the fixed-POD mode: the k = 0 basis (wave slot 0 of the stage-2
@@ -722,12 +743,12 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.forcing = S->forcing;
         if (P.diag) {
           w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
-          w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+          w.diag_ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
         }
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
         w.fine = S->Fn + (size_t)n * ng;
         w.prev = Uprev + (size_t)(n + 1) * ng;
-        w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+        w.ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
         w.norms4 = S->norms + 4 * (n + 1);
         enqueue_coarse(c, w, s, &ph);
       }
@@ -840,12 +861,12 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           w.forcing = S->forcing;
           if (P.diag) {
             w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
-            w.diag_ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+            w.diag_ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
           }
           w.corr_out = Ucur + (size_t)(n + 1) * ng;
           w.fine = S->Fn + (size_t)n * ng;
           w.prev = Uprev + (size_t)(n + 1) * ng;
-          w.ref = Uref ? Uref + (size_t)(n + 2) * ng : nullptr;
+          w.ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
           w.norms4 = S->norms + 4 * (n + 1);
           enqueue_coarse(c, w, s, &ph);
         }
@@ -904,9 +925,10 @@ static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* 
   const size_t f8 = (size_t)ng * 8;
   const int Np = P.Np;
   if (U_out) {
-    if (U_out != S->u0) PR_HIP(hipMemcpyAsync(U_out, S->u0, f8, hipMemcpyDeviceToDevice, s));
-    if (U_out + ng != S->U[S->prev])
-      PR_HIP(hipMemcpyAsync(U_out + ng, S->U[S->prev], (size_t)(Np + 1) * f8,
+    if (U_out != S->u0)
+      PR_HIP(hipMemcpyAsync(U_out, S->u0, (size_t)P.nw * f8, hipMemcpyDeviceToDevice, s));
+    if (U_out + (size_t)P.nw * ng != S->U[S->prev])
+      PR_HIP(hipMemcpyAsync(U_out + (size_t)P.nw * ng, S->U[S->prev], (size_t)(Np + 1) * f8,
                             hipMemcpyDeviceToDevice, s));
   }
   if (rep) {
@@ -1035,7 +1057,9 @@ pr_status pr_solve_state(pr_ctx* c, const pr_solve* S, int j, double* out, void*
     PR_CHECK(S != nullptr && out != nullptr, "null handle or output");
     PR_CHECK(j >= 0 && j <= S->P.N, "state index out of range");
     PR_HIP(hipSetDevice(c->device));
-    const double* src = j == 0 ? S->u0 : S->U[S->prev] + (size_t)(j - 1) * S->P.ng;
+    const int nw = S->P.nw;
+    const double* src = j < nw ? S->u0 + (size_t)j * S->P.ng
+                               : S->U[S->prev] + (size_t)(j - nw) * S->P.ng;
     PR_HIP(hipMemcpyAsync(out, src, (size_t)S->P.ng * 8, hipMemcpyDeviceToDevice,
                           (hipStream_t)stream));
     return PR_OK;

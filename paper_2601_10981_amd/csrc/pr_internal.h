@@ -409,7 +409,8 @@ struct Reduced0Desc {
   double dT;
   int n_c;
   int forced, npieces, off_F;
-  double w;          // subinterval n starts at (n + 1) dT
+  double w;          // subinterval n starts at (n + n_warm) dT
+  int n_warm;        // subintervals of the warm-up window
   int count;
   double* betas;     // count x ld_out
   int ld_out;

@@ -738,8 +738,9 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c);
   else red_propagator(sh, q, d.dT, d.n_c);
   for (int n = 0; n < d.count; ++n) {
-    // subinterval n runs over [(n + 1) dT, (n + 2) dT]
-    if (d.forced) red_advance_forced(sh, q, 1, np, d.forced, d.w, (double)(n + 1) * d.dT, d.dT);
+    // subinterval n runs over [(n + n_warm) dT, (n + n_warm + 1) dT]
+    if (d.forced)
+      red_advance_forced(sh, q, 1, np, d.forced, d.w, (double)(n + d.n_warm) * d.dT, d.dT);
     else red_advance(sh, q, 1);
     for (int e = tid; e < d.ld_out; e += 256)
       d.betas[(long long)n * d.ld_out + e] = (e < q) ? sh.beta[0][e] : 0.0;

@@ -64,16 +64,40 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
 // ---------------------------------------------------------------------------
 // Fused RK4 step.
 
+template <int P>
+using Phase = std::integral_constant<int, P>;
+
+// Steady march steps of phases P, P + 1, ..., END - 1 (all of them), or only
+// the first `left` of them.
+template <int P, int END, typename F>
+__device__ __forceinline__ void march_all(F& f) {
+  if constexpr (P < END) {
+    f(Phase<P>{}, std::false_type{});
+    march_all<P + 1, END>(f);
+  }
+}
+template <int P, int END, typename F>
+__device__ __forceinline__ void march_upto(F& f, int left) {
+  if constexpr (P < END) {
+    if (left > 0) {
+      f(Phase<P>{}, std::false_type{});
+      march_upto<P + 1, END>(f, left - 1);
+    }
+  }
+}
+
 // One fused RK4 step of one workgroup tile. The stages form a skewed
 // pipeline along x: at march step tt, w1 at plane tt + 3, w2 at tt + 2, w3 at
 // tt + 1 and y_new at tt. Each thread holds SL columns (slots); for each it
 // keeps the planes every stage still needs in registers and exchanges the
 // current plane of every stage through LDS for the y and z neighbours.
-// The per-slot plane windows are rings of six registers indexed by the
-// march step modulo 6, and the march is unrolled by 6 so every ring index
-// is a compile-time constant (no register shuffling per step). Slots wholly
-// inside the interior are known at compile time and skip the ring tests.
-template <typename T, int TY, int TZ, int NT, bool XONLY>
+// The per-slot plane windows are rings of registers indexed by the march
+// step modulo their length (RING for y, whose last entries are loads in
+// flight, 3 for the stages), and the march is unrolled by RING so every ring
+// index is a compile-time constant (no register shuffling per step). Slots
+// wholly inside the interior are known at compile time and skip the ring
+// tests.
+template <typename T, int TY, int TZ, int NT, bool XONLY, int RING>
 __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long long lt,
                                          T (*lds)[4][(TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo)],
                                          T (*vxt)[kMaxChunk + 10]) {
@@ -83,7 +107,7 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
   constexpr int NR = RY * RZ;
   constexpr int SL = (NR + NT - 1) / NT;
   constexpr int NI = TY * TZ;
-  constexpr int RING = 6;
+  static_assert(RING % 6 == 0, "the y ring is a whole number of W-ring periods and even");
   const int tz = (int)(lt % d.tiles_z);
   const long long rest = lt / d.tiles_z;
   const int ty = (int)(rest % d.tiles_y);
@@ -132,10 +156,11 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
       vxt[1][i] = tab[4 * n + x];
     }
 
-  // Rings, at march step tt with phase ph = (tt - x0 + 6) % 6, logical index
-  // k at physical (k + ph) % 6: Y: y(tt + k), k = 0..5 (k = 5 is loaded
-  // during the step, one step ahead of use); W1: w1(tt + 1 + k), W2:
-  // w2(tt + k), W3: w3(tt - 1 + k), k = 0..2.
+  // Rings, at march step tt with phase ph = (tt - x0 + 6) % RING, logical
+  // index k at physical (k + ph) % RING: Y: y(tt + k), k = 0..RING-1 (k =
+  // RING - 1 is loaded during the step, RING - 5 steps ahead of use); W1:
+  // w1(tt + 1 + k), W2: w2(tt + k), W3: w3(tt - 1 + k), k = 0..2 at physical
+  // (k + ph) % 3.
   T Y[SL][RING], W1[SL][3], W2[SL][3], W3[SL][3];
 #pragma unroll
   for (int s = 0; s < SL; ++s) {
@@ -144,27 +169,24 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
 #pragma unroll
     for (int k = 0; k < 3; ++k) W1[s][k] = W2[s][k] = W3[s][k] = (T)0;
   }
-  {
-    const long long pa = (long long)wrapi(x0 - 4, n) * plane;
-    const long long pb = (long long)wrapi(x0 - 3, n) * plane;
-    const long long pc = (long long)wrapi(x0 - 2, n) * plane;
-    // unconditional loads (slots without a column read offset 0): a
-    // conditional load would merge values across lanes and wait at once
+  // y(tt + k) for k = 2 .. RING - 2 before the first step (tt = x0 - 6);
+  // each step then loads y(tt + RING - 1), RING - 5 steps ahead of its
+  // first use. Unconditional loads (slots without a column read offset 0):
+  // a conditional load would merge values across lanes and wait at once.
 #pragma unroll
-    for (int s = 0; s < SL; ++s) {
-      Y[s][2] = src[pa + off[s]];
-      Y[s][3] = src[pb + off[s]];
-      Y[s][4] = src[pc + off[s]];
-    }
+  for (int k = 2; k <= RING - 2; ++k) {
+    const long long pk = (long long)wrapi(x0 - 6 + k, n) * plane;
+#pragma unroll
+    for (int s = 0; s < SL; ++s) Y[s][k] = src[pk + off[s]];
   }
-  // plane offsets of x = tt + 5 (load) and x = tt (store), wrapped by
+  // plane offsets of x = tt + RING - 1 (load) and x = tt (store), wrapped by
   // stepping instead of dividing
-  long long o5 = (long long)wrapi(x0 - 1, n) * plane;
+  long long o5 = (long long)wrapi(x0 - 7 + RING, n) * plane;
   long long od = (long long)wrapi(x0 - 6, n) * plane;
   const long long ng = plane * n;
   int tt = x0 - 6;
 
-  // phase: march step modulo 6; warm: the first six steps of the chunk,
+  // phase: march step modulo RING; warm: the first six steps of the chunk,
   // where stage s only starts once its input planes exist (w2 from the third
   // step, w3 from the fifth, y_new after the sixth)
   auto march = [&](auto phase, auto warm) {
@@ -176,13 +198,13 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
     __builtin_amdgcn_sched_barrier(0);
     // Y ring positions (period 6) and W ring positions (period 3)
     constexpr int k0 = PH % RING, k1 = (1 + PH) % RING, k2 = (2 + PH) % RING,
-                  k3 = (3 + PH) % RING, k4 = (4 + PH) % RING, k5 = (5 + PH) % RING;
+                  k3 = (3 + PH) % RING, k4 = (4 + PH) % RING, kl = (RING - 1 + PH) % RING;
     constexpr int j0 = PH % 3, j1 = (1 + PH) % 3, j2 = (2 + PH) % 3;
     T (*pl)[NR] = lds[PH & 1];
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
       const bool inner = (s + 1) * NT <= NI;
-      Y[s][k5] = src[o5 + off[s]];   // y(tt + 5), used from the next step on
+      Y[s][kl] = src[o5 + off[s]];   // y(tt + RING - 1), used RING - 5 steps later
       if (inner || lev[s] <= H) pl[0][ci[s]] = Y[s][k3];
       if (inner || lev[s] <= H - 1) pl[1][ci[s]] = W1[s][j1];
       if (inner || lev[s] <= H - 2) pl[2][ci[s]] = W2[s][j1];
@@ -245,32 +267,19 @@ __device__ __forceinline__ void rk4_tile(const FineDesc<T>& d, int step, long lo
     if (od == ng) od = 0;
     ++tt;
   };
-  using I0 = std::integral_constant<int, 0>;
-  using I1 = std::integral_constant<int, 1>;
-  using I2 = std::integral_constant<int, 2>;
-  using I3 = std::integral_constant<int, 3>;
-  using I4 = std::integral_constant<int, 4>;
-  using I5 = std::integral_constant<int, 5>;
-
   using W = std::true_type;
-  using S = std::false_type;
 
   __syncthreads();   // vxt visible
-  // (x1 - x0) + 6 march steps: the six warm-up steps, whole rounds of six,
-  // then the rest (phases continue from 0, the phase after a whole round)
-  march(I0{}, W{}); march(I1{}, W{}); march(I2{}, W{});
-  march(I3{}, W{}); march(I4{}, W{}); march(I5{}, W{});
-  const int nstep = x1 - x0;
-  for (int r = 0; r + RING <= nstep; r += RING) {
-    march(I0{}, S{}); march(I1{}, S{}); march(I2{}, S{});
-    march(I3{}, S{}); march(I4{}, S{}); march(I5{}, S{});
-  }
-  const int rem = nstep % RING;
-  if (rem > 0) march(I0{}, S{});
-  if (rem > 1) march(I1{}, S{});
-  if (rem > 2) march(I2{}, S{});
-  if (rem > 3) march(I3{}, S{});
-  if (rem > 4) march(I4{}, S{});
+  // (x1 - x0) + 6 march steps: the six warm-up steps (phases 0..5), the rest
+  // of the first round of RING phases, whole rounds, then the remainder
+  // (phases continue from 0, the phase after a whole round)
+  march(Phase<0>{}, W{}); march(Phase<1>{}, W{}); march(Phase<2>{}, W{});
+  march(Phase<3>{}, W{}); march(Phase<4>{}, W{}); march(Phase<5>{}, W{});
+  int left = x1 - x0;
+  march_upto<6, RING>(march, left);
+  left -= min(left, RING - 6);
+  for (; left >= RING; left -= RING) march_all<0, RING>(march);
+  march_upto<0, RING>(march, left);
 }
 
 // Waves per SIMD that the tiling's LDS allows on a CU (160 KiB of LDS, four
@@ -286,7 +295,7 @@ constexpr int fused_waves_per_simd() {
 
 // TY x TZ output tile per workgroup of NT threads; the region with the
 // 4-layer halo has (TY + 8) x (TZ + 8) columns.
-template <typename T, int TY, int TZ, int NT>
+template <typename T, int TY, int TZ, int NT, int RING>
 __global__ __launch_bounds__(NT, (fused_waves_per_simd<T, TY, TZ, NT>())) void k_rk4_fused(const FineDesc<T>* __restrict__ descs, int nd,
                                                   int step, long long total, long long per_xcd) {
   constexpr int NR = (TY + 2 * kFusedHalo) * (TZ + 2 * kFusedHalo);
@@ -306,17 +315,22 @@ __global__ __launch_bounds__(NT, (fused_waves_per_simd<T, TY, TZ, NT>())) void k
   const FineDesc<T>& d = descs[f];
   if (step >= d.n_steps) return;
   if (d.g.xonly)
-    rk4_tile<T, TY, TZ, NT, true>(d, step, t - d.tile_begin, lds, vxt);
+    rk4_tile<T, TY, TZ, NT, true, RING>(d, step, t - d.tile_begin, lds, vxt);
   else
-    rk4_tile<T, TY, TZ, NT, false>(d, step, t - d.tile_begin, lds, vxt);
+    rk4_tile<T, TY, TZ, NT, false, RING>(d, step, t - d.tile_begin, lds, vxt);
 }
 
 // Launch of one fused step in tile configuration cfg (kFusedCfgs).
+// The y ring of six planes (one step of prefetch): a ring of twelve measured
+// 5 % slower on 63 x 128^3 FP64 in the tiling with two columns per thread
+// (spills) and 13 % faster only in the one-column tiling.
+constexpr int kFusedRing = 6;
+
 template <typename T, int TY, int TZ, int NT>
 static void launch_cfg(const FineDesc<T>* d, int nd, long long total, int step, hipStream_t s) {
   const long long g8 = (total + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_rk4_fused<T, TY, TZ, NT>), dim3((unsigned)g8), dim3(NT), 0, s, d, nd, step,
-                     total, g8 / 8);
+  hipLaunchKernelGGL((k_rk4_fused<T, TY, TZ, NT, kFusedRing>), dim3((unsigned)g8), dim3(NT), 0, s,
+                     d, nd, step, total, g8 / 8);
 }
 
 template <typename T>
@@ -340,7 +354,8 @@ static void launch_step_impl(const FineDesc<T>* d, int nd, long long total, int 
 template <typename T, int TY, int TZ, int NT>
 static int occ_cfg() {
   int n = 0;
-  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rk4_fused<T, TY, TZ, NT>, NT, 0));
+  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_rk4_fused<T, TY, TZ, NT, kFusedRing>,
+                                                       NT, 0));
   return n;
 }
 

@@ -91,3 +91,17 @@ def test_plan_forced_flows_automatic_step(flow, fp, kappa):
     assert plan["n_f"] == n_f
     assert plan["dt"] == pytest.approx(dt, rel=1e-15)
     assert fd.velocity_bound(flow, fp) == 6.0 * abs(fp[0])
+
+def test_plan_warm_up_window():
+    """n_warm subintervals of warm-up leave N - n_warm parareal subintervals
+    (host only); a window longer than [0, T] is rejected."""
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    prob = W.Problem(n=32, kappa=0.05, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0))
+    for nw in (1, 2, 5):
+        opts = W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=nw)
+        plan = pr.pr_plan(pr.problem_of(prob), opts)
+        assert plan["n_sub"] == 8 - nw and plan["max_iter"] == 8 - nw
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_plan(pr.problem_of(prob), W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=9))
+    assert e.value.name == "PR_EINVAL"

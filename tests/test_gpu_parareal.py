@@ -95,6 +95,34 @@ def test_parareal_prefix_and_iterates_match_oracle(ctx, ml, p):
         assert worst <= 10.0 * env[k] + 1e-12
 
 
+def test_parareal_iterates_at_1e12_on_a_well_separated_spectrum(ctx):
+    """Iterates k = 1..3 of (m_l, p) = (1, 1) in FP64 held to 1e-12 against
+    the oracle. The rank caps cut every POD spectrum of this case at a wide
+    gap (lambda_{m+1} / lambda_m <= 0.32), so the kept subspaces are fixed by
+    the data to round-off: the oracle's own one-ulp perturbation envelope
+    stays below 1e-13, and the GPU must agree to 1e-12."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0),
+                       cap0=3, cap=4)
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    o3 = W.PararealOpts(**{**opts.__dict__, "max_iter": 3})
+    ores = parareal.solve(prob, o3, u0, keep_history=True)
+    env = _roundoff_envelope(prob, o3, u0, ores, 3)
+    say(f"well-separated case: oracle round-off envelope {['%.1e' % e for e in env[1:]]}")
+    assert max(env[1:]) <= 1e-13
+    for k in range(1, 4):
+        o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
+        U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+        assert rep.iters == k
+        assert rep.ranks[k - 1] == ores.ranks[k]
+        Un = to_np(U)
+        worst = max(rel_l2(Un[j + 1], ores.history[k][j]) for j in range(len(ores.history[k])))
+        say(f"  k={k} worst iterate rel L2 vs oracle {worst:.3e}")
+        assert worst <= 1e-12
+
+
 def test_parareal_abc32_workload(ctx):
     """The 32^3 ABC FP64 workload end to end against the oracle."""
     import paper_2601_10981_amd as pr
@@ -383,3 +411,81 @@ def test_parareal_zero_initial_state(ctx):
     assert rep.converged and rep.iters == 1 and rep.m0 == 0
     assert np.all(to_np(U) == 0.0)
     assert rep.jump == [0.0]
+
+
+def test_nan_in_the_iterate_returns_enumeric(ctx):
+    """A NaN in the state reaches the jump norms (formula4's correction
+    carries it) and the solve stops with PR_ENUMERIC instead of reading it as
+    a zero jump; the incremental (serving) path reports the same."""
+    import torch
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=6, T=0.6, max_iter=3)
+    p = pr.problem_of(prob)
+    u0 = W.blob_field(prob.n, 7)
+    u0[5] = float("nan")
+    say("NaN initial state: pr_parareal_solve")
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    assert e.value.name == "PR_ENUMERIC"
+    say("NaN initial state: pr_solve_begin / step / end")
+    h = pr.pr_solve_begin(ctx, p, opts, to_dev(u0))
+    for _ in range(opts.N):
+        if pr.pr_solve_step_batch(ctx, [h])[0]:
+            break
+    assert pr.pr_solve_done(h)
+    with pytest.raises(pr.PrError) as e:
+        pr.pr_solve_end(ctx, h)
+    assert e.value.name == "PR_ENUMERIC"
+    torch.cuda.synchronize()
+
+
+def test_nan_in_the_reference_shows_in_the_error_only(ctx):
+    """A NaN in U_ref makes the reported error NaN (the error maximum keeps
+    it) while the jumps, the iterate and the status are unaffected."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=6, T=0.6, max_iter=2)
+    p = pr.problem_of(prob)
+    u0 = W.blob_field(prob.n, 7)
+    ref = gpu_serial(ctx, p, opts, u0)
+    U1, rep1 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    bad = ref.clone()
+    bad[3, 17] = float("nan")
+    U2, rep2 = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=bad)
+    assert rep2.status == rep1.status
+    assert rep2.jump == rep1.jump
+    assert np.array_equal(to_np(U1), to_np(U2))
+    assert all(math.isnan(e) for e in rep2.err)
+    assert all(math.isfinite(e) for e in rep1.err)
+
+
+@pytest.mark.parametrize("mode", [W.MODE_FIXED_POD, W.MODE_ADAPTIVE, W.MODE_COARSE_GRID],
+                         ids=["fixed_pod", "adaptive", "coarse_grid"])
+def test_warm_up_window_of_two_subintervals(ctx, mode):
+    """T_0 = 2 DeltaT, the paper's Parareal-I window (Sec. 4): the window's
+    states and the converged prefix bitwise equal the GPU serial solve, the
+    iterates match the oracle (POD modes within its round-off envelope), and
+    finite termination comes after N - 2 iterations."""
+    import paper_2601_10981_amd as pr
+    prob, opts = _tiny(n=12, N=8, T=0.8, kappa=0.1, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 2.0, 0.0))
+    opts = W.PararealOpts(**{**opts.__dict__, "mode": mode, "n_warm": 2})
+    u0 = W.fourier_field(prob.n, 9, n_modes=6, kmax=3.0)
+    p = pr.problem_of(prob)
+    ref = gpu_serial(ctx, p, opts, u0)
+    ores = parareal.solve(prob, opts, u0, keep_history=True)
+    env = _roundoff_envelope(prob, opts, u0, ores, 2)
+    for k in (1, 2):
+        say(f"warm-up window 2 DeltaT, mode {mode}, iterate k={k}")
+        o = W.PararealOpts(**{**opts.__dict__, "max_iter": k})
+        U, rep = pr.pr_parareal_solve(ctx, p, o, to_dev(u0), U_ref=ref)
+        assert rep.iters == k and rep.n_sub == opts.N - 2 and rep.m0 == ores.m0
+        Un = to_np(U)
+        for j in range(0, k + 3):
+            assert np.array_equal(Un[j], to_np(ref[j])), (k, j)
+        worst = max(rel_l2(Un[j + 2], h) for j, h in enumerate(ores.history[k]))
+        say(f"  worst rel L2 vs oracle {worst:.3e} (envelope {env[k]:.3e})")
+        assert worst <= 10.0 * env[k] + 1e-12
+        if mode == W.MODE_ADAPTIVE:
+            assert rep.ranks[k - 1] == ores.ranks[k]
+    U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
+    assert rep.iters == opts.N - 2 and rep.converged
+    assert np.array_equal(to_np(U), to_np(ref))

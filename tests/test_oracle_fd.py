@@ -179,3 +179,73 @@ def test_rk4_is_fourth_order_polynomial_of_L():
         terms.append(op.apply(terms[-1]))
     poly = phi + dt * terms[1] + dt ** 2 / 2 * terms[2] + dt ** 3 / 6 * terms[3] + dt ** 4 / 24 * terms[4]
     assert np.max(np.abs(fd.rk4_step(op, phi, dt) - poly)) <= 1e-13
+
+
+def _spectral_derivative(f, axis, L=2 * math.pi):
+    """Exact derivative of a band-limited periodic field (FFT along axis)."""
+    n = f.shape[axis]
+    k = np.fft.fftfreq(n, d=L / n) * 2 * math.pi
+    shape = [1, 1, 1]
+    shape[axis] = n
+    return np.real(np.fft.ifft(1j * k.reshape(shape) * np.fft.fft(f, axis=axis), axis=axis))
+
+
+def test_abc_velocity_is_a_beltrami_field_with_its_amplitudes():
+    """The ABC velocity (unequal A, B, C) is fixed without retyping it: it is
+    divergence free, equals its own curl (a Beltrami field: curl u = u),
+    each component's mean square is half the sum of the squares of its two
+    amplitudes, and u(0, 0, 0) = (C, A, B). A sin <-> cos swap, a swapped
+    amplitude or a sign slip in any component breaks one of these."""
+    n, (A, B, C) = 16, (0.7, 1.3, 2.1)
+    ux, uy, uz = fd.velocity(n, fd.FLOW_ABC, (A, B, C), 2 * math.pi)
+    d = _spectral_derivative
+    div = d(ux, 0) + d(uy, 1) + d(uz, 2)
+    assert np.max(np.abs(div)) <= 1e-12
+    curl = (d(uz, 1) - d(uy, 2), d(ux, 2) - d(uz, 0), d(uy, 0) - d(ux, 1))
+    for c, u in zip(curl, (ux, uy, uz)):
+        assert np.max(np.abs(c - u)) <= 1e-12
+    for u, (a, b) in zip((ux, uy, uz), ((A, C), (B, A), (C, B))):
+        assert abs(float(np.mean(u * u)) - 0.5 * (a * a + b * b)) <= 1e-12
+    assert np.allclose([ux[0, 0, 0], uy[0, 0, 0], uz[0, 0, 0]], [C, A, B], rtol=0, atol=1e-15)
+
+
+def test_kolmogorov_velocity_spectrum():
+    """u = (a sin(k_f y), 0, 0): the x component depends on y alone, and its
+    discrete Fourier transform along y is exactly -i a n / 2 at k_f and
+    +i a n / 2 at -k_f (the transform of a sine), zero elsewhere."""
+    n, a, kf = 16, 1.7, 3
+    ux, uy, uz = fd.velocity(n, fd.FLOW_KOLMOGOROV, (a, float(kf), 0.0), 2 * math.pi)
+    assert np.all(uy == 0.0) and np.all(uz == 0.0)
+    assert np.all(ux == ux[:1, :, :1])          # a function of y only
+    spec = np.fft.fft(ux[0, :, 0])
+    expect = np.zeros(n, dtype=complex)
+    expect[kf] = -0.5j * a * n
+    expect[n - kf] = 0.5j * a * n
+    assert np.max(np.abs(spec - expect)) <= 1e-12
+
+
+@pytest.mark.parametrize("flow,fp", [(fd.FLOW_ABC, (0.7, 1.3, 2.1)),
+                                     (fd.FLOW_KOLMOGOROV, (1.7, 3.0, 0.0))])
+def test_steady_stencil_on_sinusoids_closed_form(flow, fp):
+    """L on sin(x_d + c): the discrete Laplacian and central difference of a
+    sinusoid are -(2 - 2 cos h) / h^2 and sin(h) / h times the sinusoid and
+    its cosine, so L phi = kappa lap_f phi - u_d grad_f cos(x_d + c) with the
+    velocity component u_d typed from the problem statement (unequal ABC
+    amplitudes; Kolmogorov amplitude and wavenumber)."""
+    n, kappa = 10, 0.3
+    h = 2 * math.pi / n
+    op = fd.Operator(n, kappa, flow, fp)
+    X, Y, Z = _grid(n)
+    if flow == fd.FLOW_ABC:
+        A, B, C = fp
+        U = (A * np.sin(Z) + C * np.cos(Y), B * np.sin(X) + A * np.cos(Z),
+             C * np.sin(Y) + B * np.cos(X))
+    else:
+        a, kf = fp[0], fp[1]
+        U = (a * np.sin(kf * Y), 0.0 * X, 0.0 * X)
+    lap_f = -(2.0 - 2.0 * math.cos(h)) / h ** 2
+    grad_f = math.sin(h) / h
+    for d, (coord, c) in enumerate(((X, 0.3), (Y, -1.1), (Z, 2.0))):
+        phi = np.sin(coord + c)
+        expect = kappa * lap_f * phi - U[d] * grad_f * np.cos(coord + c)
+        assert np.max(np.abs(op.apply(phi) - expect)) <= 1e-12

@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import parareal
+from oracle import fd, parareal
 
 
 def _tiny(flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0), n=12, kappa=0.05, N=6, T=0.6,
@@ -169,3 +169,84 @@ def test_coarse_gap_diagnostics_closed_form(ratio):
         assert expect <= 1e-13
     else:
         assert expect > 1e-9
+
+
+@pytest.mark.parametrize("ml,p", [(1, 1), (2, 1), (0, 1), (1, 0)])
+def test_stage2_collection_is_the_papers_concatenation(ml, p):
+    """W^k_n (Sec. 3.2 Case II, eq. W^k_n) is the column concatenation
+    [R^k_{n-m_l,0}, ..., R^k_{n,0}, R^{k-1}_{n,0}, ..., R^{k-p}_{n,0}] of the
+    stage-1 bases, built here by hand from the recorded bases with explicit
+    indices. A block R^k_{j,0} that iteration k did not compute (j < k - 1:
+    that subinterval had converged) is the latest one, from iteration j + 1;
+    blocks with j < 0 or iteration < 1 are left out."""
+    prob, opts = _tiny(N=7, T=0.7, ml=ml, p=p, cap0=4, cap=6)
+    opts = W.PararealOpts(**{**opts.__dict__, "max_iter": 4})
+    u0 = W.fourier_field(prob.n, 8, n_modes=6, kmax=3.0)
+    tr = {}
+    parareal.solve(prob, opts, u0, trace=tr)
+    Np = opts.N - 1
+    seen = 0
+    for k in range(1, 5):
+        for n in range(k, Np):
+            R = lambda it, j: tr[("R0", it, j)]
+            if (ml, p) == (1, 1):
+                blocks = [R(k, n - 1), R(k, n)] + ([R(k - 1, n)] if k >= 2 else [])
+            elif (ml, p) == (2, 1):
+                blocks = []
+                if n - 2 >= 0:
+                    blocks.append(R(k - 1, n - 2) if n - 2 == k - 2 else R(k, n - 2))
+                blocks += [R(k, n - 1), R(k, n)]
+                blocks += [R(k - 1, n)] if k >= 2 else []
+            elif (ml, p) == (0, 1):
+                blocks = [R(k, n)] + ([R(k - 1, n)] if k >= 2 else [])
+            else:
+                blocks = [R(k, n - 1), R(k, n)]
+            assert np.array_equal(tr[("W", k, n)], np.concatenate(blocks, axis=1)), (k, n)
+            seen += 1
+    assert seen == sum(Np - k for k in range(1, 5))
+    # the n - 2 = k - 2 case of m_l = 2 takes the basis of iteration k - 1
+    if ml == 2:
+        assert ("R0", 3, 0) not in tr and ("R0", 2, 0) not in tr and ("R0", 1, 0) in tr
+
+
+@pytest.mark.parametrize("mode", [W.MODE_FIXED_POD, W.MODE_ADAPTIVE, W.MODE_COARSE_GRID])
+def test_warm_up_window_of_two_subintervals(mode):
+    """T_0 = 2 DeltaT (the paper's Parareal-I set-up, Sec. 4): the window's
+    states are the serial fine ones, the parareal partition of [T_0, T] has
+    N - 2 subintervals and terminates after N - 2 iterations with the serial
+    fine solution, and the k = 0 snapshots are the fine states at every dM
+    steps across the whole window (checked against separate fine solves from
+    u0 of j dM steps)."""
+    prob, opts = _tiny(N=6, T=0.6, mode=mode, n=12)
+    opts = W.PararealOpts(**{**opts.__dict__, "n_warm": 2, "dM": 3})
+    u0 = W.fourier_field(prob.n, 8, n_modes=6, kmax=3.0)
+    ref = parareal.reference(prob, opts, u0)
+    r = parareal.solve(prob, opts, u0, U_ref=ref, keep_history=True)
+    assert r.iters == opts.N - 2 and r.converged
+    assert len(r.U) == opts.N + 1
+    for j in range(opts.N + 1):
+        assert np.array_equal(r.U[j], ref[j].reshape(-1)), j
+    # the k = 0 iterate: U^0_0 is the fine state at T_0 = 2 DeltaT
+    assert np.array_equal(r.history[0][0], ref[2].reshape(-1))
+    assert len(r.history[0]) == opts.N - 1
+    if mode == W.MODE_COARSE_GRID:
+        return
+    op = fd.Operator.of(prob)
+    n_f, dt = fd.steps_per_subinterval(opts.T / opts.N, opts.dt)
+    ends, Wh = fd.fine_window(op, u0, dt, n_f, 2, opts.dM)
+    assert Wh.shape[1] == (2 * n_f) // opts.dM + 1
+    for j in range(Wh.shape[1]):
+        expect, _ = fd.fine_propagate(op, u0, dt, j * opts.dM)
+        assert np.array_equal(Wh[:, j], expect.reshape(-1)), j
+    assert np.array_equal(ends[0].reshape(-1), ref[1].reshape(-1))
+
+
+def test_warm_up_window_one_is_the_default():
+    prob, opts = _tiny(N=5, T=0.5)
+    u0 = W.fourier_field(prob.n, 8, n_modes=6, kmax=3.0)
+    a = parareal.solve(prob, opts, u0, keep_history=True)
+    b = parareal.solve(prob, W.PararealOpts(**{**opts.__dict__, "n_warm": 1}), u0,
+                       keep_history=True)
+    assert a.iters == b.iters == opts.N - 1
+    for x, y in zip(a.history[-1], b.history[-1]):
+        assert np.array_equal(x, y)

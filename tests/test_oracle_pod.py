@@ -120,3 +120,25 @@ def test_eigenvector_sign_convention():
     for j in range(3):
         i = int(np.argmax(np.abs(Y[:, j])))
         assert Y[i, j] > 0
+
+
+def test_drop_pivot_rule_by_hand():
+    """The re-orthonormalisation drops a mode whose M-norm squared residual
+    against the earlier modes is <= 1e-8, together with every later one.
+    Columns built from M-orthonormal vectors e_i with a known residual."""
+    n3, h3 = 64, 0.1
+    E = np.eye(n3)[:, :4] / math.sqrt(h3)         # M-orthonormal: h3 E^T E = I
+    # third column: e_0 + eps e_2, residual M-norm^2 = eps^2
+    for eps, kept in ((1e-5, 2), (1e-3, 4)):
+        R = np.stack([E[:, 0], E[:, 1], E[:, 0] + eps * E[:, 2], E[:, 3]], axis=1)
+        Q, m = pod.m_orthonormalise(R, h3)
+        assert m == kept, (eps, m)
+        assert Q.shape[1] == kept
+        assert np.allclose(h3 * Q.T @ Q, np.eye(kept), atol=1e-12)
+    # a repeated first column drops it and both later columns
+    R = np.stack([E[:, 0], E[:, 0], E[:, 1]], axis=1)
+    assert pod.m_orthonormalise(R, h3)[1] == 1
+    # either side of the threshold: residual^2 below 1e-8 drops, above keeps
+    for r2, kept in ((0.9e-8, 1), (1.1e-8, 2)):
+        R = np.stack([E[:, 0], E[:, 0] + math.sqrt(r2) * E[:, 1]], axis=1)
+        assert pod.m_orthonormalise(R, h3)[1] == kept, r2

@@ -76,6 +76,7 @@ class PararealOpts:
     max_iter: int = 0        # 0: N - 1
     mode: int = MODE_ADAPTIVE
     diag: int = 0            # 1: record the coarse-gap diagnostics (Sec. 4, dT = delta t runs)
+    n_warm: int = 1          # subintervals in the warm-up window [0, T_0]: T_0 = n_warm DeltaT
 
 
 @dataclasses.dataclass(frozen=True)
