@@ -98,10 +98,15 @@ def test_plan_warm_up_window():
     import paper_2601_10981_amd as pr
     import workloads as W
     prob = W.Problem(n=32, kappa=0.05, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0))
-    for nw in (1, 2, 5):
+    for nw in (1, 2, 3):
         opts = W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=nw)
         plan = pr.pr_plan(pr.problem_of(prob), opts)
         assert plan["n_sub"] == 8 - nw and plan["max_iter"] == 8 - nw
-    with pytest.raises(pr.PrError) as e:
-        pr.pr_plan(pr.problem_of(prob), W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=9))
-    assert e.value.name == "PR_EINVAL"
+    # beyond [0, T], and a window whose snapshots (5 x 63 steps every 4) exceed 64
+    for nw in (9, 5):
+        with pytest.raises(pr.PrError) as e:
+            pr.pr_plan(pr.problem_of(prob), W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=nw))
+        assert e.value.name == "PR_EINVAL"
+    # the coarse-grid mode takes no snapshots: any window inside [0, T]
+    opts = W.PararealOpts(T=1.0, N=8, dt=2e-3, n_warm=5, mode=W.MODE_COARSE_GRID)
+    assert pr.pr_plan(pr.problem_of(prob), opts)["n_sub"] == 3
