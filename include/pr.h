@@ -199,6 +199,21 @@ pr_status pr_pod_build(pr_ctx* ctx, int batch, const pr_pod_item* items, void* s
 pr_status pr_gram(pr_ctx* ctx, const pr_grid_problem* prob, const void* W, int ncols,
                   double* G_out, void* stream);
 
+/* pr_gram for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels and chunking as pr_gram, so G_out is bitwise the
+ * same, but the call allocates nothing and uses no context scratch. Its
+ * device scratch (descriptors, the padded Gram and the per-chunk partials)
+ * is one file-scope array of 10.5 MiB per device, set up by pr_ctx_create
+ * and held until the process ends. That size covers every Gram pr_gram
+ * accepts (1 <= ncols <= 64, any N_g): larger ncols is PR_EINVAL. Every call
+ * on a device shares the array and it keeps the last call's contents: calls
+ * on one stream are ordered, calls that overlap on one device (several
+ * streams or host threads, or several contexts) race.
+ * Errors: PR_EINVAL for a bad problem or ncols, PR_EDEVICE on a HIP failure. */
+pr_status pr_gram_noalloc(pr_ctx* ctx, const pr_grid_problem* prob, const void* W, int ncols,
+                          double* G_out, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Coarse propagator G_{k,n} (eq. 8 / eq00; with augmentation eqaug, eq12,
  * eq13; formula4): Galerkin projection of each input state onto span(Psi),

@@ -19,7 +19,7 @@ from ._lib import PR_F64, PR_MIXED, PR_FLOW_ABC, PR_FLOW_KOLMOGOROV, PR_FLOW_UNI
 from ._lib import PR_FLOW_ABC_T, PR_FLOW_KOLMOGOROV_T  # noqa: F401
 from ._lib import PR_MODE_ADAPTIVE, PR_MODE_FIXED_POD, PR_MODE_COARSE_GRID  # noqa: F401
 
-__all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build",
+__all__ = ["Context", "PrError", "problem", "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_gram_noalloc", "pr_pod_build",
            "pr_coarse_propagate", "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin",
            "pr_solve_step_batch", "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end",
            "SolveHandle", "costmodel"]
@@ -174,6 +174,20 @@ def pr_gram(ctx: Context, prob: L.pr_grid_problem, W, ncols: int, G_out=None, st
     _check_dev(G_out, torch.float64, ncols * ncols, "G_out")
     ctx.check(ctx.lib.pr_gram(ctx.h, ctypes.byref(prob), _ptr(W), int(ncols), _ptr(G_out),
                               _stream(stream)))
+    return G_out
+
+
+def pr_gram_noalloc(ctx: Context, prob: L.pr_grid_problem, W, G_out, stream=None, ncols=None):
+    """pr_gram into a caller-provided (ncols, ncols) FP64 G_out, allocating
+    nothing (the library's static device scratch)."""
+    torch = _torch()
+    ng = prob.n ** 3
+    if ncols is None:
+        ncols = G_out.shape[0]
+    _check_dev(W, _fdtype(prob), ncols * ng, "W")
+    _check_dev(G_out, torch.float64, ncols * ncols, "G_out")
+    ctx.check(ctx.lib.pr_gram_noalloc(ctx.h, ctypes.byref(prob), _ptr(W), int(ncols),
+                                      _ptr(G_out), _stream(stream)))
     return G_out
 
 

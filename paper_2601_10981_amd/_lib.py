@@ -67,7 +67,7 @@ class pr_plan_info(Structure):
 
 
 EXPORTS = ["pr_ctx_create", "pr_ctx_destroy", "pr_last_error", "pr_ctx_scratch_bytes",
-           "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_pod_build", "pr_coarse_propagate",
+           "pr_fine_propagate", "pr_fine_tuned", "pr_gram", "pr_gram_noalloc", "pr_pod_build", "pr_coarse_propagate",
            "pr_parareal_solve", "pr_plan", "pr_footprint", "pr_solve_begin", "pr_solve_step_batch",
            "pr_solve_state", "pr_solve_done", "pr_solve_bytes", "pr_solve_end"]
 
@@ -107,6 +107,9 @@ def load(path: str = LIB_PATH):
     lib.pr_gram.argtypes = [c_void_p, POINTER(pr_grid_problem), c_void_p, c_int, c_void_p,
                             c_void_p]
     lib.pr_gram.restype = c_int
+    lib.pr_gram_noalloc.argtypes = [c_void_p, POINTER(pr_grid_problem), c_void_p, c_int, c_void_p,
+                                    c_void_p]
+    lib.pr_gram_noalloc.restype = c_int
     lib.pr_pod_build.argtypes = [c_void_p, c_int, POINTER(pr_pod_item), c_void_p]
     lib.pr_pod_build.restype = c_int
     lib.pr_coarse_propagate.argtypes = [c_void_p, c_int, POINTER(pr_coarse_item), c_void_p]

@@ -1303,6 +1303,11 @@ pr_status pr_ctx_create(int device, size_t hbm_budget_bytes, pr_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return PR_EDEVICE;
   if (device < 0 || device >= ndev) return PR_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return PR_EDEVICE;
+  try {
+    noalloc_scratch_init(device);   // pr_gram_noalloc's scratch on this device
+  } catch (const pr::Error&) {
+    return PR_EDEVICE;
+  }
   pr_ctx* c = new pr_ctx();
   c->device = device;
   size_t fr = 0, tot = 0;
@@ -1460,6 +1465,59 @@ pr_status pr_gram(pr_ctx* c, const pr_grid_problem* prob, const void* W, int nco
   PR_HIP(hipMemcpy2DAsync(G_out, (size_t)ncols * 8, G, (size_t)ldg * 8, (size_t)ncols * 8, ncols,
                           hipMemcpyDeviceToDevice, s));
   stage_end(c, s);
+  return PR_OK;
+  PR_API_END(c)
+}
+
+pr_status pr_gram_noalloc(pr_ctx* c, const pr_grid_problem* prob, const void* W, int ncols,
+                          double* G_out, void* stream) {
+  PR_API_BEGIN(c)
+  check_problem(prob);
+  PR_CHECK(W && G_out, "null Gram buffer");
+  PR_CHECK(ncols >= 1 && ncols <= kMaxPodCols, "ncols must be in [1, 64] (the no-alloc maximum)");
+  PR_HIP(hipSetDevice(c->device));
+  char* area = (char*)noalloc_scratch(c->device);
+  if (!area) fail(PR_EDEVICE, "no-alloc scratch not set up on this device");
+  hipStream_t s = (hipStream_t)stream;
+  const bool f32 = prob->precision == PR_MIXED;
+  const long long ng = ngrid(*prob);
+  const int na = (ncols + 15) / 16, ldg = na * 16;
+  GemmDesc d{};
+  d.nrows = ng;
+  d.chunk_rows = gram_chunk_rows(ng);
+  d.nchunks = (int)((ng + d.chunk_rows - 1) / d.chunk_rows);
+  const size_t part = (size_t)d.nchunks * (na * (na + 1) / 2) * 256;
+  if (d.nchunks > kGramMaxChunks || part > kNoAllocPartialDoubles)
+    fail(PR_EINVAL, "Gram partials exceed the no-alloc scratch");
+  // layout of the area: GemmDesc at 0, column descriptors at 256, the
+  // padded Gram at kNoAllocDescBytes, the partials after it
+  static_assert(sizeof(GemmDesc) <= 256, "descriptor slot");
+  static_assert(256 + kMaxPodCols * sizeof(ColDesc) <= sizeof(UploadBlob), "upload blob");
+  static_assert(256 + kMaxPodCols * sizeof(ColDesc) <= kNoAllocDescBytes, "descriptor area");
+  ColDesc* cols_dev = (ColDesc*)(area + 256);
+  double* G = (double*)(area + kNoAllocDescBytes);
+  d.wg_begin = 0;
+  d.cols = cols_dev;
+  d.partial = G + kNoAllocGramDoubles;
+  d.out = G;
+  d.ld = ldg;
+  const double h = spacing(*prob);
+  d.scale = h * h * h;
+  d.a_in_b = 0;
+  // the descriptors travel in the arguments of an upload kernel
+  UploadBlob b;
+  memset(&b, 0, sizeof b);
+  memcpy(b.w, &d, sizeof d);
+  for (int j = 0; j < ldg; ++j) {
+    const ColDesc cd = j < ncols ? col_of(W, j, ng, f32, nullptr) : col_null();
+    memcpy((char*)b.w + 256 + (size_t)j * sizeof(ColDesc), &cd, sizeof cd);
+  }
+  const int nw = (int)((256 + (size_t)ldg * sizeof(ColDesc) + 3) / 4);
+  launch_upload(b, (unsigned int*)area, nw, s);
+  launch_gemm_tn((const GemmDesc*)area, 1, d.nchunks, na, 0, f32, s);
+  launch_gemm_reduce((const GemmDesc*)area, 1, na, 0, s);
+  PR_HIP(hipMemcpy2DAsync(G_out, (size_t)ncols * 8, G, (size_t)ldg * 8, (size_t)ncols * 8, ncols,
+                          hipMemcpyDeviceToDevice, s));
   return PR_OK;
   PR_API_END(c)
 }

@@ -7,9 +7,40 @@
 //     re-orthonormalisation, projection residual and lift;
 //   * the parareal correction U^k_{n+1} = Psi (beta_new - beta_old) + F_n
 //     (formula4) with wave-shuffle partial sums of the jump norms.
+#include <mutex>
+
 #include "pr_internal.h"
 
 namespace pr {
+
+// ---------------------------------------------------------------------------
+// Device scratch of pr_gram_noalloc, for callers that cannot allocate device
+// memory: kNoAllocDescBytes of descriptors, the padded 64 x 64 Gram, then the
+// per-chunk partials. In host code the array's name only stands in for the
+// symbol; its device address on each device is looked up once (at context
+// creation) and only that address is passed to kernels and copies.
+static __device__ __align__(256) double noalloc_area[kNoAllocBytes / 8];
+
+constexpr int kMaxDevices = 64;
+static std::mutex noalloc_mu;
+static void* noalloc_ptr[kMaxDevices];
+
+void noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) fail(PR_EDEVICE, "device index beyond 64");
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_area));
+  if (e != hipSuccess || p == nullptr)
+    fail(PR_EDEVICE, std::string("hipGetSymbolAddress(noalloc_area): ") + hipGetErrorString(e));
+  noalloc_ptr[device] = p;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  return noalloc_ptr[device];
+}
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));

@@ -272,6 +272,23 @@ void launch_gemm_tn(const GemmDesc* d, int nitems, long long total_wg, int na, i
                     bool f32, hipStream_t s);
 void launch_gemm_reduce(const GemmDesc* d, int nitems, int na, int nb, hipStream_t s);
 
+// ---- the Gram without device allocation (pr_gram_noalloc) -------------------
+// A file-scope device array (gemm.hip), one per device, holds the
+// descriptors, the padded Gram and the per-chunk partials of one Gram of up
+// to 64 columns of any row count (gram_chunk_rows gives at most
+// kGramMaxChunks chunks, and four column tiles have 10 tile pairs).
+constexpr int kGramMaxChunks = 512;
+constexpr size_t kNoAllocDescBytes = 4096;
+constexpr size_t kNoAllocGramDoubles = 64 * 64;
+constexpr size_t kNoAllocPartialDoubles = (size_t)kGramMaxChunks * 10 * 256;
+constexpr size_t kNoAllocBytes =
+    kNoAllocDescBytes + 8 * (kNoAllocGramDoubles + kNoAllocPartialDoubles);
+// Look up the array's device address on `device` (which must be current);
+// does the lookup once per device. Throws PR_EDEVICE on failure.
+void noalloc_scratch_init(int device);
+// The address looked up for `device`, or nullptr before noalloc_scratch_init.
+void* noalloc_scratch(int device);
+
 // ---- one Gram-Schmidt pass of the augmentation (eqaug) ----------------------
 // Over the rows of one field: z = y - sum_{j < m} c[j] X_j (or z = y without
 // coefficients), then dots[j] = scale * X_j^T z (j < n, zero for j >= m) and
