@@ -25,6 +25,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FUSED_TILINGS = 11   # steady-flow stencil tilings (PR_FUSED_CFG indices)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -41,6 +42,14 @@ def parse():
                     help="skip the serial fine reference (no error history; profiling runs)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the fine step in every stencil tiling (stderr and JSON)")
+    ap.add_argument("--gram-only", action="store_true",
+                    help="time the snapshot Gram (pr_gram) of the 128^3 workload")
+    ap.add_argument("--serve-study", action="store_true",
+                    help="serving stream at scale: capacity, then Poisson phases at --serve-rates")
+    ap.add_argument("--serve-rates", default="0.5,0.7,0.9")
+    ap.add_argument("--serve-skip", type=int, default=8)
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="solves/s; 0 measures it with a closed loop first")
     ap.add_argument("--serve-requests", type=int, default=6,
                     help="requests per serving phase (closed loop, then Poisson); 0 = skip")
     ap.add_argument("--mixed256", action="store_true",
@@ -71,6 +80,18 @@ def log(msg):
 CSRC = os.path.join(ROOT, "paper_2601_10981_amd", "csrc")
 STENCIL_SRC = os.path.join(CSRC, "stencil.hip")
 STENCIL_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_fused_f64_kolmogorov128_batch63.md")
+B22_SRC = os.path.join(CSRC, "stencil22.hip")
+B22_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_b22_f64_kolmogorov128_batch63.md")
+
+
+def stencil_src_of(kname):
+    return B22_SRC if kname.startswith("k_rk4_b22") else STENCIL_SRC
+
+
+def stencil_profile_of(kname):
+    return B22_PROFILE if kname.startswith("k_rk4_b22") else STENCIL_PROFILE
+
+
 FORCED_SRC = os.path.join(CSRC, "forced.hip")
 FORCED_PROFILE = os.path.join(ROOT, "profiles", "k_rk4_forced_f64_paperkolmogorov128_batch40.md")
 
@@ -101,27 +122,99 @@ def profiled_traffic(kernel, src=None, profile=STENCIL_PROFILE):
     return None
 
 
-def cpu_baseline(w, budget_s):
-    """Oracle fine propagator (numpy FP64, classical RK4) on one field of the
-    workload, as many RK4 steps as fit the time budget."""
-    import numpy as np
+def _oracle_steps(args):
+    """One worker of the CPU baseline: the oracle's RK4 steps on one field
+    (subinterval i's copy of the workload's initial field) until the
+    deadline; returns the steps taken."""
+    wname, i, deadline = args
     import workloads as W
     from oracle import fd
+    w = W.BY_NAME[wname]
     op = fd.Operator.of(w.problem)
-    u = W.initial_field(w)
+    u = W.initial_field(w) * (1.0 + 0.01 * i)
     n_f, dt = fd.steps_per_subinterval(w.opts.T / w.opts.N, w.opts.dt)
-    t0 = time.perf_counter()
     steps = 0
     while True:
         u = fd.rk4_step(op, u, dt)
         steps += 1
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    el = time.perf_counter() - t0
+        if time.time() >= deadline:
+            return steps
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle's fine propagator (numpy FP64, classical RK4) on the host's
+    cores: one process per core, each stepping its own subinterval field of
+    the workload (the batched fine solve's independent fields) until a common
+    deadline; throughput = all steps x N_g / wall time. The core count is the
+    host's usable CPU set, capped at 16 (the CPU share of one GPU here); each
+    worker runs numpy single-threaded."""
+    import multiprocessing as mp
+    cores = min(16, len(os.sched_getaffinity(0)))
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_steps, [(w.name, i, time.time() + 0.5) for i in range(cores)])  # warm
+        t0 = time.time()
+        steps = pool.map(_oracle_steps, [(w.name, i, t0 + budget_s) for i in range(cores)])
+        el = time.time() - t0
     ng = w.problem.n ** 3
-    return {"value": steps * ng / el / 1e9, "unit": "GPts/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} RK4 steps of one {w.problem.n}^3 field of the workload "
-                      f"(oracle fine propagator, numpy FP64, {el:.1f} s)"}
+    tot = sum(steps)
+    return {"value": tot * ng / el / 1e9, "unit": "GPts/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
+            "sample": f"{tot} RK4 steps on {cores} independent {w.problem.n}^3 fields of the "
+                      f"workload, one process each (oracle fine propagator, numpy FP64, "
+                      f"{el:.1f} s)"}
+
+
+def copy_bandwidth(stream, nbytes=1 << 30, reps=10):
+    """Achieved HBM bandwidth of a plain device copy (torch's copy kernel):
+    nbytes read and nbytes written per copy, timed with HIP events on the
+    current stream; the best of reps."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        b.copy_(a)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s = e0.elapsed_time(e1) * 1e-3
+        best = s if best is None else min(best, s)
+    del a, b
+    return round(2 * nbytes / best / 1e9, 1)
+
+
+def oracle_c1_phases():
+    """The oracle's whole adaptive solve of the 32^3 ABC workload (T = 1 over
+    8 subintervals) on one host core, with its per-phase times in the paper's
+    breakdown (F, C, U, A, G) and its iteration count."""
+    import workloads as W
+    from oracle import parareal
+    w = W.ABC_32_F64
+    u0 = W.initial_field(w)
+    t0 = time.perf_counter()
+    r = parareal.solve(w.problem, w.opts, u0)
+    el = time.perf_counter() - t0
+    return {"workload": w.name, "seconds": round(el, 2), "iters": r.iters,
+            "t_phase_s": {k: round(v, 3) for k, v in r.t_phase.items()},
+            "gpts": round(r.iters and (sum((w.opts.N - 1 - k + 1) for k in range(1, r.iters + 1))
+                                       + 1) * r.n_f * w.problem.n ** 3 / max(r.t_phase["F"], 1e-9)
+                          / 1e9, 5)}
 
 
 def serving_sample(pr, ctx, budget, k):
@@ -156,6 +249,120 @@ def serving_sample(pr, ctx, budget, k):
             "iters": [c.iters for c in sorted(openl.completed, key=lambda c: c.rid)],
             "sample": f"{k} closed-loop then {k} Poisson requests of the serving stream "
                       f"(seeds 5000..{5000 + 2 * k - 1}); no warm-up exclusion"}
+
+
+def serving_study(args):
+    """The serving stream at scale: a closed loop of K requests (all at
+    t = 0) measures the capacity (solves/s), unless --serve-capacity gives
+    it; then, for each load factor, K further requests arrive as a Poisson
+    stream at that fraction of the capacity. Latency is arrival to result;
+    the first --serve-skip requests of each phase are warm-up and left out
+    of the percentiles. Every request has its own seed."""
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    from paper_2601_10981_amd import serving
+    k = args.serve_requests
+    rates = [float(x) for x in args.serve_rates.split(",") if x]
+    ws = W.serving_requests(k * (len(rates) + 1))
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.85 * free)
+    ctx = pr.Context(0, budget_bytes=budget)
+
+    def req(i, arrival):
+        w = ws[i]
+        return serving.Request(i, float(arrival), pr.problem_of(w.problem), w.opts,
+                               lambda w=w: W.fourier_field_device(w.problem.n, w.seed,
+                                                                  "cuda").reshape(-1))
+    P = serving.ServeStats.percentile
+    out = {"mode": "serving", "requests_per_phase": k, "skip": args.serve_skip,
+           "budget_bytes": budget, "phases": []}
+
+    def phase(name, st, offered):
+        lat = st.latencies(skip=args.serve_skip)
+        done = sorted(st.completed, key=lambda c: c.rid)
+        out["phases"].append({
+            "phase": name, "offered_per_s": offered, "n_latencies": len(lat),
+            "p50_latency_s": round(P(lat, 50), 3), "p99_latency_s": round(P(lat, 99), 3),
+            "mean_latency_s": round(sum(lat) / len(lat), 3),
+            "solves_per_s": round(len(done) / st.wall, 4), "wall_s": round(st.wall, 1),
+            "mean_live": round(st.mean_live, 2), "max_live": st.max_live,
+            "iters_mean": round(sum(c.iters for c in done) / len(done), 1),
+            "not_converged": sum(1 for c in done if c.status != 0)})
+        log(f"serving {name}: {out['phases'][-1]}")
+
+    if args.serve_capacity > 0:
+        capacity = args.serve_capacity
+        out["capacity_given"] = capacity
+    else:
+        log(f"serving: closed loop, {k} requests")
+        closed = serving.serve(ctx, [req(i, 0.0) for i in range(k)], budget,
+                               log=lambda m: log("  " + m))
+        capacity = k / closed.wall
+        phase("closed_loop", closed, None)
+    out["closed_loop_solves_per_s"] = round(capacity, 4)
+    for j, f in enumerate(rates):
+        rate = f * capacity
+        arrivals = W.poisson_arrivals(k, rate, seed=5 + j)
+        base = k * (j + 1)
+        log(f"serving: Poisson at {f} x capacity = {rate:.4f}/s, {k} requests")
+        st = serving.serve(ctx, [req(base + i, arrivals[i]) for i in range(k)], budget,
+                           log=lambda m: log("  " + m))
+        phase(f"poisson_{f}", st, round(rate, 4))
+    out["sample"] = (f"{k} requests per phase (seeds 5000..{5000 + len(ws) - 1}), the first "
+                     f"{args.serve_skip} of each phase excluded from the percentiles")
+    ctx.close()
+    print(json.dumps(out))
+
+
+def gram_run(args):
+    """The snapshot Gram G = h^3 W^T W (Algorithm 1, step 1) of the 128^3
+    workload through pr_gram: a stage-1 block of n_s = 16 snapshot columns
+    and a stage-2 collection of 48 columns, FP64 (FP64 MFMA) and FP32 data
+    (FP32 MFMA products, FP64 sums). Reports the time per call (HIP events
+    on the stream the library launches on), the algorithmic bytes (every
+    column read once) and flops (2 N_g per entry of the upper block
+    triangle of 16 x 16 tiles the kernel forms)."""
+    import torch
+    import paper_2601_10981_amd as pr
+    import workloads as W
+    n = 128
+    ng = n ** 3
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    ctx = pr.Context(0)
+    out = {"mode": "gram", "n": n, "cases": []}
+    for prec, dt, vb in ((W.PREC_F64, torch.float64, 8), (W.PREC_MIXED, torch.float32, 4)):
+        prob = pr.problem_of(W.Problem(n=n, kappa=0.01, flow=W.FLOW_KOLMOGOROV, fp=(1.0, 4.0, 0.0),
+                                       precision=prec))
+        for ncols in (16, 48):
+            Wt = torch.randn((ncols, ng), dtype=torch.float64, device="cuda").to(dt)
+            G = torch.empty((ncols, ncols), dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                pr.pr_gram(ctx, prob, Wt, ncols, G)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record(stream)
+            for _ in range(reps):
+                pr.pr_gram(ctx, prob, Wt, ncols, G)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            s = e0.elapsed_time(e1) * 1e-3 / reps
+            na = (ncols + 15) // 16
+            flops = 2.0 * (na * (na + 1) // 2) * 256 * ng
+            bytes_ = ncols * ng * vb
+            out["cases"].append({"precision": "f64" if vb == 8 else "f32 data", "ncols": ncols,
+                                 "us_per_call": round(s * 1e6, 1),
+                                 "gb_s": round(bytes_ / s / 1e9, 1),
+                                 "tflop_s": round(flops / s / 1e12, 2),
+                                 "flop_per_byte": round(flops / bytes_, 2)})
+            log(f"gram {out['cases'][-1]}")
+            del Wt
+    ctx.close()
+    print(json.dumps(out))
 
 
 def paper_projection(rep, serial_s, N):
@@ -218,7 +425,15 @@ def mixed256_run(args):
     log(f"mixed256: solve, max_iter {opts.max_iter}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, rep = pr.pr_parareal_solve(ctx, p32, opts, U_ref[0], U_out=U_out, U_ref=U_ref)
+    # the incremental form of the solve (bitwise the same iterates as
+    # pr_parareal_solve), so that every iteration reports progress
+    h = pr.pr_solve_begin(ctx, p32, opts, U_ref[0], U_ref=U_ref)
+    k = 0
+    while not pr.pr_solve_done(h):
+        pr.pr_solve_step_batch(ctx, [h])
+        k += 1
+        log(f"  iteration {k} done at {time.perf_counter() - t0:.1f} s")
+    _, rep = pr.pr_solve_end(ctx, h, U_out=U_out)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     # the converged prefix U_j, j <= k + 1, is the FP32-stencil serial fine
@@ -268,12 +483,31 @@ def ensemble_run(args):
     st = serving.serve(ctx, reqs, budget, max_live=len(reqs),
                        log=lambda m: log("  " + m))
     done = sorted(st.completed, key=lambda c: c.rid)
+    # each instance's state at T against its own serial fine solution with
+    # the FP64 stencil (after the timed loop)
+    log("ensemble: FP64 serial references")
+    errs = []
+    for r, w in zip(reqs, ws):
+        import dataclasses
+        p64 = pr.problem_of(dataclasses.replace(w.problem, precision=W.PREC_F64))
+        plan = pr.pr_plan(p64, w.opts)
+        u = W.fourier_field_device(w.problem.n, w.seed, "cuda").reshape(-1).clone()
+        v = torch.empty_like(u)
+        for j in range(w.opts.N):
+            pr.pr_fine_propagate(ctx, [dict(prob=p64, dt=plan["dt"], n_steps=plan["n_f"],
+                                            u_in=u, u_out=v, t0=j * w.opts.T / w.opts.N)])
+            u, v = v, u
+        torch.cuda.synchronize()
+        errs.append(float((torch.linalg.vector_norm(r.result - u) /
+                           torch.linalg.vector_norm(u)).item()))
     out = {"mode": "ensemble", "instances": len(done), "wall_s": round(st.wall, 2),
            "solves_per_s": round(len(done) / st.wall, 4), "steps": st.steps,
            "fine_gpts": round(sum(c.fine_updates for c in done) / st.wall / 1e9, 1),
            "mean_live": round(st.mean_live, 2), "max_live": st.max_live,
            "grids": [c.n for c in done], "N": [c.N for c in done],
            "iters": [c.iters for c in done], "status": [c.status for c in done],
+           "err_at_T_vs_fp64_serial": [float("%.2e" % e) for e in errs],
+           "max_err_at_T": float("%.3e" % max(errs)),
            "seeds": f"4000..{4000 + len(done) - 1}"}
     ctx.close()
     print(json.dumps(out))
@@ -524,6 +758,10 @@ def main():
         return paper_flow_run(args)
     if args.gap:
         return gap_run(args)
+    if args.serve_study:
+        return serving_study(args)
+    if args.gram_only:
+        return gram_run(args)
     import numpy as np
     import torch
     import paper_2601_10981_amd as pr
@@ -589,18 +827,21 @@ def main():
     bytes_per_launch = 16 * ng * B
     achieved = bytes_per_launch / avg_launch_s / 1e9
     stencil_gpts = B * ng * n_f / (fine_ms * 1e-3) / 1e9
-    tiling = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, planes=True)
-    kname = ("k_rk4_fused<double,%d,%d,%d>/x%d" % tiling) if tiling else "k_rk4_fused<double>"
+    kname = pr.fine_kernel_name(ctx, pr.PR_F64, n, B) or "k_rk4_fused<double>"
+    copy_gbs = copy_bandwidth(stream)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": profiled_traffic(kname),
+                "traffic": profiled_traffic(kname, src=stencil_src_of(kname),
+                                            profile=stencil_profile_of(kname)),
                 "kernel": kname, "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "bytes_per_launch": bytes_per_launch}
+                "bytes_per_launch": bytes_per_launch,
+                "copy_kernel_gbs": copy_gbs,
+                "frac_of_copy": round(achieved / copy_gbs, 4)}
     if args.sweep:
         sweep = {}
         for pol in range(3):
             os.environ["PR_FUSED_CHUNK"] = str(pol)
-            for cfg in range(8):
+            for cfg in range(FUSED_TILINGS):
                 os.environ["PR_FUSED_CFG"] = str(cfg)
                 pr.pr_fine_propagate(ctx, items)
                 e0.record(stream)
@@ -608,8 +849,8 @@ def main():
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
-                t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B)
-                key = "%dx%dx%d/chunks%d" % (t + (pol,))
+                t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, blocked=True)
+                key = "%dx%dx%d%s/chunks%d" % (t[:3] + ("b22" if t[3] else "", pol))
                 sweep[key] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
                 log(f"  tiling {key}: {sweep[key]} GPts/s")
         del os.environ["PR_FUSED_CFG"]
@@ -707,6 +948,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        log("oracle phase times, 32^3 workload")
+        out["cpu_baseline"]["oracle_abc32_solve"] = oracle_c1_phases()
     ctx.close()
     print(json.dumps(out))
 

@@ -143,13 +143,16 @@ pr_status pr_fine_propagate(pr_ctx* ctx, int batch, const pr_fine_item* items, v
  * flows), PR_FORCED_CFG=<index> (forced flows) and PR_FUSED_CHUNK=<policy>
  * force one; PR_TUNE_LOG=1 prints each tuning's timings (us per launch, by
  * code = tiling + 8 x policy) to stderr.
+ * The steady-flow tilings include 2 x 2 register-blocked ones (each thread
+ * holds four columns; tried for batches whose grids are even and whose
+ * fields are aligned to two values).
  * pr_fine_tuned reports, for a key (forced = 1: the forced-flow stencil), the
  * workgroup's output tile (tile_y x tile_z points of the (y, z) plane), its
- * thread count and the x planes it marches through (for `batch` fields of
- * n^3); every output pointer may be NULL. PR_EINVAL if no batch of that key
- * ran yet. */
+ * thread count, the x planes it marches through (for `batch` fields of n^3)
+ * and whether it is a blocked tiling; every output pointer may be NULL.
+ * PR_EINVAL if no batch of that key ran yet. */
 pr_status pr_fine_tuned(const pr_ctx* ctx, int precision, int forced, int n, int batch,
-                        int* tile_y, int* tile_z, int* threads, int* planes);
+                        int* tile_y, int* tile_z, int* threads, int* planes, int* blocked);
 
 /* ---------------------------------------------------------------------------
  * POD_Mode (Algorithm 1; Sec. 3.2 Case I and Case II, eq. W^k_n): modes of

@@ -151,17 +151,30 @@ def pr_fine_propagate(ctx: Context, items: Sequence[dict], stream=None):
 
 
 def pr_fine_tuned(ctx: Context, precision: int, n: int, batch: int, planes: bool = False,
-                  forced: bool = False):
-    """(tile_y, tile_z, threads[, x planes per workgroup]) of the fused
-    stencil launch shape chosen for a batch key (forced: the forced-flow
-    stencil), or None if no such batch ran yet."""
-    ty, tz, nt, xp = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+                  forced: bool = False, blocked: bool = False):
+    """(tile_y, tile_z, threads[, x planes per workgroup][, blocked]) of the
+    fused stencil launch shape chosen for a batch key (forced: the
+    forced-flow stencil; blocked: 1 for a 2 x 2 register-blocked tiling), or
+    None if no such batch ran yet."""
+    ty, tz, nt, xp, bl = (ctypes.c_int() for _ in range(5))
     st = ctx.lib.pr_fine_tuned(ctx.h, int(precision), 1 if forced else 0, int(n), int(batch),
-                               ctypes.byref(ty),
-                               ctypes.byref(tz), ctypes.byref(nt), ctypes.byref(xp))
+                               ctypes.byref(ty), ctypes.byref(tz), ctypes.byref(nt),
+                               ctypes.byref(xp), ctypes.byref(bl))
     if st != L.PR_OK:
         return None
-    return (ty.value, tz.value, nt.value, xp.value) if planes else (ty.value, tz.value, nt.value)
+    out = (ty.value, tz.value, nt.value) + ((xp.value,) if planes else ())
+    return out + ((bl.value,) if blocked else ())
+
+
+def fine_kernel_name(ctx: Context, precision: int, n: int, batch: int) -> Optional[str]:
+    """Name of the steady-flow stencil kernel and x chunk chosen for a batch
+    key, as the profiler lists it (template arguments abbreviated)."""
+    t = pr_fine_tuned(ctx, precision, n, batch, planes=True, blocked=True)
+    if t is None:
+        return None
+    ty, tz, nt, xp, bl = t
+    v = "double" if precision == L.PR_F64 else "float"
+    return "%s<%s,%d,%d,%d>/x%d" % ("k_rk4_b22" if bl else "k_rk4_fused", v, ty, tz, nt, xp)
 
 
 def pr_gram(ctx: Context, prob: L.pr_grid_problem, W, ncols: int, G_out=None, stream=None):

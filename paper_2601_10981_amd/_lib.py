@@ -102,7 +102,7 @@ def load(path: str = LIB_PATH):
     lib.pr_fine_propagate.argtypes = [c_void_p, c_int, POINTER(pr_fine_item), c_void_p]
     lib.pr_fine_propagate.restype = c_int
     lib.pr_fine_tuned.argtypes = [c_void_p, c_int, c_int, c_int, c_int, POINTER(c_int), POINTER(c_int),
-                                  POINTER(c_int), POINTER(c_int)]
+                                  POINTER(c_int), POINTER(c_int), POINTER(c_int)]
     lib.pr_fine_tuned.restype = c_int
     lib.pr_gram.argtypes = [c_void_p, POINTER(pr_grid_problem), c_void_p, c_int, c_void_p,
                             c_void_p]

@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpr.so")
-SOURCES = ["stencil.hip", "forced.hip", "gemm.hip", "small.hip", "grid.hip", "capi.cpp",
+SOURCES = ["stencil.hip", "stencil22.hip", "forced.hip", "gemm.hip", "small.hip", "grid.hip", "capi.cpp",
            "parareal.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -406,7 +406,7 @@ static int forced_cfg_forced() {
 // more workgroups. The tuner tries both policies.
 static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min_wgs,
                       bool forced, long long slots) {
-  int xc = forced ? kForcedChunk : kMaxChunk;
+  int xc = forced ? kForcedChunk : (kFusedCfgs[cfg].blocked ? kBlockedChunk : kMaxChunk);
   int nmax = 1;
   auto total = [&](int x) {
     long long t = 0;
@@ -436,13 +436,14 @@ static int fine_chunk(const std::vector<FineWork>& items, int cfg, long long min
 }
 
 // Workgroups of tiling cfg the device holds at once (cached per context).
-static long long resident_slots(const pr_ctx* c, int cfg, bool f32, bool forced) {
-  const int key = cfg * 4 + (f32 ? 1 : 0) + (forced ? 2 : 0);
+static long long resident_slots(const pr_ctx* c, int cfg, bool f32, bool forced, bool xonly) {
+  const int key = cfg * 8 + (f32 ? 1 : 0) + (forced ? 2 : 0) + (xonly ? 4 : 0);
   auto it = c->fused_slots.find(key);
   if (it != c->fused_slots.end()) return it->second;
   if (c->n_cu <= 0)
     PR_HIP(hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int per_cu = forced ? forced_blocks_per_cu(cfg, f32) : fused_blocks_per_cu(cfg, f32);
+  const int per_cu =
+      forced ? forced_blocks_per_cu(cfg, f32) : fused_blocks_per_cu(cfg, f32, xonly);
   const long long v = std::max<long long>(1, (long long)per_cu * std::max(1, c->n_cu));
   c->fused_slots[key] = v;
   return v;
@@ -453,12 +454,20 @@ static long long resident_slots(const pr_ctx* c, int cfg, bool f32, bool forced)
 // A launch shape: tiling kFusedCfgs[code % kNumFusedCfgs], chunk policy
 // code / kNumFusedCfgs.
 template <typename T>
+static bool all_xonly(const std::vector<FineDesc<T>>& d) {
+  for (auto& x : d)
+    if (!x.g.xonly) return false;
+  return true;
+}
+
+template <typename T>
 static long long shape_descs(pr_ctx* c, const std::vector<FineWork>& items,
                              std::vector<FineDesc<T>>& d, int code, bool forced) {
   const int cfg = code % kNumFusedCfgs;
   const long long min_wgs = kChunkMinWgs[code / kNumFusedCfgs];
   const long long slots =
-      min_wgs < 0 ? resident_slots(c, cfg, std::is_same<T, float>::value, forced) : 0;
+      min_wgs < 0 ? resident_slots(c, cfg, std::is_same<T, float>::value, forced, all_xonly(d))
+                  : 0;
   const int xc = fine_chunk(items, cfg, min_wgs, forced, slots);
   long long tiles = 0;
   for (size_t i = 0; i < items.size(); ++i) {
@@ -475,7 +484,7 @@ static long long shape_descs(pr_ctx* c, const std::vector<FineWork>& items,
 
 template <typename T>
 static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step, int cfg,
-                        bool forced, hipStream_t s) {
+                        bool forced, bool xonly, hipStream_t s) {
   if (forced) {
     if (std::is_same<T, float>::value)
       launch_forced_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, s);
@@ -484,28 +493,43 @@ static void launch_step(const FineDesc<T>* d, int nd, long long tiles, int step,
     return;
   }
   if (std::is_same<T, float>::value)
-    launch_fine_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, s);
+    launch_fine_step_f32((const FineDesc<float>*)d, nd, tiles, step, cfg, xonly, s);
   else
-    launch_fine_step_f64((const FineDesc<double>*)d, nd, tiles, step, cfg, s);
+    launch_fine_step_f64((const FineDesc<double>*)d, nd, tiles, step, cfg, xonly, s);
 }
 
 constexpr int kTuneReps = 3;
 
 // Tuning key: value size, largest grid, batch size class floor(log2(batch)),
 // and F for the forced-flow stencil.
-static std::string tune_key(int value_bytes, int nmax, int batch, bool forced) {
+static std::string tune_key(int value_bytes, int nmax, int batch, bool forced, bool blocked) {
   int cls = 0;
   while ((1LL << (cls + 1)) <= batch) ++cls;
   char key[64];
-  snprintf(key, sizeof key, "%d|%d|%d%s", value_bytes, nmax, cls, forced ? "|F" : "");
+  snprintf(key, sizeof key, "%d|%d|%d%s%s", value_bytes, nmax, cls, forced ? "|F" : "",
+           blocked ? "|B" : "");
   return key;
+}
+
+// Whether the blocked tilings (2 x 2 columns per thread, pair loads and
+// stores) apply to a batch: every grid even and every field and snapshot
+// column aligned to two values.
+template <typename T>
+static bool blocked_ok(const std::vector<FineWork>& items, const std::vector<FineDesc<T>>& d) {
+  auto al = [](const void* p) { return ((uintptr_t)p % (2 * sizeof(T))) == 0; };
+  for (size_t i = 0; i < items.size(); ++i) {
+    if (items[i].prob->n % 2 != 0) return false;
+    if (!al(d[i].first_src) || !al(d[i].buf[0]) || !al(d[i].buf[1])) return false;
+    if (d[i].snaps && (!al(d[i].snaps) || d[i].snap_ld % 2 != 0)) return false;
+  }
+  return true;
 }
 
 // Launch shapes the tuner tries: every tiling (the forced stencil: those of
 // kForcedCfgs; in FP64 not a 1024-thread one with two columns per thread,
 // whose four waves per SIMD leave too few registers) under every chunk
 // policy, the modelled one first.
-static std::vector<int> shape_codes(bool forced, int value_bytes) {
+static std::vector<int> shape_codes(bool forced, int value_bytes, bool blocked) {
   std::vector<int> v;
   for (int pol = kChunkPolicies - 1; pol >= 0; --pol) {
     if (forced) {
@@ -514,7 +538,8 @@ static std::vector<int> shape_codes(bool forced, int value_bytes) {
               fused_slots(kForcedCfgs[i]) > 1))
           v.push_back(kForcedCfgs[i] + kNumFusedCfgs * pol);
     } else {
-      for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg) v.push_back(cfg + kNumFusedCfgs * pol);
+      for (int cfg = 0; cfg < kNumFusedCfgs; ++cfg)
+        if (blocked || !kFusedCfgs[cfg].blocked) v.push_back(cfg + kNumFusedCfgs * pol);
     }
   }
   return v;
@@ -532,22 +557,23 @@ constexpr int kTuneFinal = 4;
 constexpr int kTuneRounds = 6;
 template <typename T>
 static int tune_fine(pr_ctx* c, const std::vector<FineWork>& items, std::vector<FineDesc<T>>& d,
-                     bool forced, hipStream_t s) {
+                     bool forced, bool blocked, hipStream_t s) {
   int nmax = 0;
   for (auto& w : items) nmax = std::max(nmax, w.prob->n);
-  const std::string key = tune_key((int)sizeof(T), nmax, (int)items.size(), forced);
+  const std::string key = tune_key((int)sizeof(T), nmax, (int)items.size(), forced, blocked);
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) return it->second;
   hipEvent_t e0 = event_get(c), e1 = event_get(c);
-  const std::vector<int> codes = shape_codes(forced, (int)sizeof(T));
+  const std::vector<int> codes = shape_codes(forced, (int)sizeof(T), blocked);
   auto time_code = [&](int code, int reps) {
     const int cfg = code % kNumFusedCfgs;
     const long long tiles = shape_descs<T>(c, items, d, code, forced);
     FineDesc<T>* dd = stage_push(c, d);
     stage_flush(c, s);
-    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
+    const bool xo = all_xonly(d);
+    launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, xo, s);
     PR_HIP(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, s);
+    for (int r = 0; r < reps; ++r) launch_step<T>(dd, (int)d.size(), tiles, 0, cfg, forced, xo, s);
     PR_HIP(hipEventRecord(e1, s));
     PR_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -642,19 +668,29 @@ static void fine_typed(pr_ctx* c, const std::vector<FineWork>& items, bool force
     descs.push_back(d);
   }
   if (max_steps > 0) {
+    const bool blocked = !forced && blocked_ok<T>(items, descs);
     int code = forced ? forced_cfg_forced() : forced_cfg();
-    if (code < 0) code = tune_fine<T>(c, items, descs, forced, s);
+    if (code >= 0 && kFusedCfgs[code % kNumFusedCfgs].blocked && !blocked) code = -1;
+    if (code < 0) code = tune_fine<T>(c, items, descs, forced, blocked, s);
     const int cfg = code % kNumFusedCfgs;
     const long long tiles = shape_descs<T>(c, items, descs, code, forced);
     FineDesc<T>* dd = stage_push(c, descs);
     stage_flush(c, s);
+    const bool xo = all_xonly(descs);
+    {
+      int nmax = 0;
+      for (auto& w : items) nmax = std::max(nmax, w.prob->n);
+      c->fine_planes[tune_key((int)sizeof(T), nmax, (int)items.size(), forced, blocked)] =
+          descs[0].xc;
+    }
     if (forced) {
       for (int step = 0; step < max_steps; ++step)
-        launch_step<T>(dd, (int)descs.size(), tiles, step, cfg, true, s);
+        launch_step<T>(dd, (int)descs.size(), tiles, step, cfg, true, false, s);
     } else if (f32) {
-      launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+      launch_fine_f32((const FineDesc<float>*)dd, (int)descs.size(), tiles, max_steps, cfg, xo, s);
     } else {
-      launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, s);
+      launch_fine_f64((const FineDesc<double>*)dd, (int)descs.size(), tiles, max_steps, cfg, xo,
+                      s);
     }
   }
   if (f32)
@@ -1350,11 +1386,15 @@ void pr_ctx_destroy(pr_ctx* c) {
 }
 
 pr_status pr_fine_tuned(const pr_ctx* c, int precision, int forced, int n, int batch,
-                        int* tile_y, int* tile_z, int* threads, int* planes) {
+                        int* tile_y, int* tile_z, int* threads, int* planes, int* blocked) {
   if (!c || batch < 1 || (precision != PR_F64 && precision != PR_MIXED)) return PR_EINVAL;
   int code = forced ? forced_cfg_forced() : forced_cfg();
+  const int vb = precision == PR_MIXED ? 4 : 8;
+  std::string key = tune_key(vb, n, batch, forced != 0, forced == 0);
+  if (!c->tuned.count(key) && !c->fine_planes.count(key))
+    key = tune_key(vb, n, batch, forced != 0, false);
   if (code < 0) {
-    auto it = c->tuned.find(tune_key(precision == PR_MIXED ? 4 : 8, n, batch, forced != 0));
+    auto it = c->tuned.find(key);
     if (it == c->tuned.end()) return PR_EINVAL;
     code = it->second;
   }
@@ -1362,15 +1402,23 @@ pr_status pr_fine_tuned(const pr_ctx* c, int precision, int forced, int n, int b
   if (tile_y) *tile_y = kFusedCfgs[cfg].ty;
   if (tile_z) *tile_z = kFusedCfgs[cfg].tz;
   if (threads) *threads = kFusedCfgs[cfg].nt;
+  if (blocked) *blocked = kFusedCfgs[cfg].blocked;
   if (planes) {
-    // chunk length for `batch` fields of n^3 under the key's policy
-    pr_grid_problem p{};
-    p.n = n;
-    const std::vector<FineWork> items(batch, FineWork{&p, 0.0, 0, nullptr, nullptr, 0, nullptr});
-    const long long min_wgs = kChunkMinWgs[code / kNumFusedCfgs];
-    const long long slots =
-        min_wgs < 0 ? resident_slots(c, cfg, precision == PR_MIXED, forced != 0) : 0;
-    *planes = std::min(n, fine_chunk(items, cfg, min_wgs, forced != 0, slots));
+    // chunk length of the key's last launch, else the policy's for `batch`
+    // fields of n^3 (general flows)
+    auto pit = c->fine_planes.find(key);
+    if (pit != c->fine_planes.end()) {
+      *planes = pit->second;
+    } else {
+      pr_grid_problem p{};
+      p.n = n;
+      const std::vector<FineWork> items(batch,
+                                        FineWork{&p, 0.0, 0, nullptr, nullptr, 0, nullptr});
+      const long long min_wgs = kChunkMinWgs[code / kNumFusedCfgs];
+      const long long slots =
+          min_wgs < 0 ? resident_slots(c, cfg, precision == PR_MIXED, forced != 0, false) : 0;
+      *planes = std::min(n, fine_chunk(items, cfg, min_wgs, forced != 0, slots));
+    }
   }
   return PR_OK;
 }

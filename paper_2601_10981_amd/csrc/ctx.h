@@ -26,6 +26,7 @@ struct pr_ctx {
   std::multimap<size_t, void*> pool;
   std::map<std::string, void*> tables;   // velocity tables by problem key
   std::map<std::string, int> tuned;      // fused-stencil configuration by batch key
+  std::map<std::string, int> fine_planes;  // x chunk of the last launch of each batch key
   // resident stencil workgroups by tiling and the device's compute units
   // (caches filled on first use, also through const queries)
   mutable std::map<int, long long> fused_slots;

@@ -142,13 +142,19 @@ constexpr int kForcedChunk = 128;  // the same for the forced-flow stencil
 // (y, z) plane per workgroup of NT threads. Every configuration computes
 // bitwise the same values (each point's arithmetic does not depend on the
 // tiling), so the choice is a pure performance knob.
+// blocked = 1: the 2 x 2 register-blocked kernel (k_rk4_b22, stencil22.hip),
+// one block of four columns per thread; it needs an even n and 2-value
+// aligned fields.
 struct FusedCfg {
-  int ty, tz, nt;
+  int ty, tz, nt, blocked;
 };
-constexpr int kNumFusedCfgs = 8;
+constexpr int kNumFusedCfgs = 11;
+constexpr int kNumColumnCfgs = 8;   // the one-column-per-thread tilings come first
 constexpr FusedCfg kFusedCfgs[kNumFusedCfgs] = {
-    {32, 32, 512}, {16, 32, 256}, {16, 32, 512}, {32, 32, 1024},
-    {8, 32, 256},  {16, 64, 512}, {8, 64, 512},  {16, 32, 1024}};
+    {32, 32, 512, 0}, {16, 32, 256, 0}, {16, 32, 512, 0}, {32, 32, 1024, 0},
+    {8, 32, 256, 0},  {16, 64, 512, 0}, {8, 64, 512, 0},  {16, 32, 1024, 0},
+    {32, 32, 448, 1}, {16, 64, 512, 1}, {16, 32, 256, 1}};
+constexpr int kBlockedChunk = 128;   // x planes per workgroup of the blocked tilings (at most)
 inline int fused_ty(int cfg) { return kFusedCfgs[cfg].ty; }
 inline int fused_tz(int cfg) { return kFusedCfgs[cfg].tz; }
 // Tilings of the forced-flow stencil (at most three columns per thread: it
@@ -159,6 +165,7 @@ constexpr int kForcedCfgs[kNumForcedCfgs] = {2, 3, 4, 6, 7};
 // thread count).
 inline int fused_slots(int cfg) {
   const FusedCfg& f = kFusedCfgs[cfg];
+  if (f.blocked) return 4;
   return ((f.ty + 8) * (f.tz + 8) + f.nt - 1) / f.nt;
 }
 
@@ -231,24 +238,32 @@ struct CorrectDesc {
 // ---- launchers -------------------------------------------------------------
 // Fused RK4 steps; cfg selects the tile shape (0: 32 x 32 tile, 512 threads;
 // 1: 16 x 32 tile, 256 threads). Every field of a launch uses one cfg.
+// xonly: every field of the launch has a velocity along x only (the blocked
+// tilings then use a kernel without the per-plane velocity table).
 void launch_fine_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
-                     int max_steps, int cfg, hipStream_t s);
+                     int max_steps, int cfg, bool xonly, hipStream_t s);
 void launch_fine_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
-                     int max_steps, int cfg, hipStream_t s);
+                     int max_steps, int cfg, bool xonly, hipStream_t s);
 // One RK4 step (step index `step`) of every field with step < n_steps.
 void launch_fine_step_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
-                          int step, int cfg, hipStream_t s);
+                          int step, int cfg, bool xonly, hipStream_t s);
 void launch_fine_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
-                          int step, int cfg, hipStream_t s);
+                          int step, int cfg, bool xonly, hipStream_t s);
 // The same for the forced flows (classical RK4 with stage times and forcing);
 // cfg must be one of kForcedCfgs.
 void launch_forced_step_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
                             int step, int cfg, hipStream_t s);
 void launch_forced_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
                             int step, int cfg, hipStream_t s);
+// The blocked tilings (kFusedCfgs[cfg].blocked).
+void launch_b22_step_f64(const FineDesc<double>* d_descs, int nfields, long long total_tiles,
+                         int step, int cfg, bool xonly, hipStream_t s);
+void launch_b22_step_f32(const FineDesc<float>* d_descs, int nfields, long long total_tiles,
+                         int step, int cfg, bool xonly, hipStream_t s);
+int b22_blocks_per_cu(int cfg, bool f32, bool xonly);
 // Workgroups of a tiling resident per CU at once (registers, LDS, threads),
 // from the runtime's occupancy calculator.
-int fused_blocks_per_cu(int cfg, bool f32);
+int fused_blocks_per_cu(int cfg, bool f32, bool xonly);
 int forced_blocks_per_cu(int cfg, bool f32);
 // f_j of piece j of a forced flow written as an N_g field (double or float).
 void launch_forcing_field(const Geom& g, int piece, void* out, int out_f32, hipStream_t s);

@@ -337,7 +337,7 @@ template <typename T>
 static void launch_step_impl(const FineDesc<T>* d, int nd, long long total, int step, int cfg,
                              hipStream_t s) {
   if (total <= 0) return;
-  static_assert(kNumFusedCfgs == 8, "one case per configuration");
+  static_assert(kNumColumnCfgs == 8, "one case per configuration");
   switch (cfg) {
     case 0: launch_cfg<T, 32, 32, 512>(d, nd, total, step, s); break;
     case 1: launch_cfg<T, 16, 32, 256>(d, nd, total, step, s); break;
@@ -375,30 +375,33 @@ static int occ_impl(int cfg) {
   return 0;
 }
 
-int fused_blocks_per_cu(int cfg, bool f32) {
+int fused_blocks_per_cu(int cfg, bool f32, bool xonly) {
+  if (kFusedCfgs[cfg].blocked) return b22_blocks_per_cu(cfg, f32, xonly);
   return f32 ? occ_impl<float>(cfg) : occ_impl<double>(cfg);
 }
 
 void launch_fine_step_f64(const FineDesc<double>* d, int nd, long long total, int step, int cfg,
-                          hipStream_t s) {
+                          bool xonly, hipStream_t s) {
+  if (kFusedCfgs[cfg].blocked) return launch_b22_step_f64(d, nd, total, step, cfg, xonly, s);
   launch_step_impl<double>(d, nd, total, step, cfg, s);
   PR_HIP(hipGetLastError());
 }
 void launch_fine_step_f32(const FineDesc<float>* d, int nd, long long total, int step, int cfg,
-                          hipStream_t s) {
+                          bool xonly, hipStream_t s) {
+  if (kFusedCfgs[cfg].blocked) return launch_b22_step_f32(d, nd, total, step, cfg, xonly, s);
   launch_step_impl<float>(d, nd, total, step, cfg, s);
   PR_HIP(hipGetLastError());
 }
 
 void launch_fine_f64(const FineDesc<double>* d, int nd, long long total, int max_steps, int cfg,
-                     hipStream_t s) {
-  for (int step = 0; step < max_steps; ++step) launch_step_impl<double>(d, nd, total, step, cfg, s);
-  PR_HIP(hipGetLastError());
+                     bool xonly, hipStream_t s) {
+  for (int step = 0; step < max_steps; ++step)
+    launch_fine_step_f64(d, nd, total, step, cfg, xonly, s);
 }
 void launch_fine_f32(const FineDesc<float>* d, int nd, long long total, int max_steps, int cfg,
-                     hipStream_t s) {
-  for (int step = 0; step < max_steps; ++step) launch_step_impl<float>(d, nd, total, step, cfg, s);
-  PR_HIP(hipGetLastError());
+                     bool xonly, hipStream_t s) {
+  for (int step = 0; step < max_steps; ++step)
+    launch_fine_step_f32(d, nd, total, step, cfg, xonly, s);
 }
 
 // out = L(in) for each valid column; invalid columns are written as zero.

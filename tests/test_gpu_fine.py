@@ -98,7 +98,7 @@ def test_fine_every_tile_configuration_is_bitwise_identical(ctx, prec, monkeypat
     ref_outs, ref_snaps = _run(ctx, cases, prec)          # autotuned
     for pol in range(3):
         monkeypatch.setenv("PR_FUSED_CHUNK", str(pol))
-        for cfg in range(8):
+        for cfg in range(11):   # the blocked tilings 8..10 fall back (n = 33 is odd)
             monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
             outs, snaps = _run(ctx, cases, prec)
             for i in range(len(cases)):
@@ -106,6 +106,41 @@ def test_fine_every_tile_configuration_is_bitwise_identical(ctx, prec, monkeypat
                 assert np.array_equal(to_np(snaps[i]), to_np(ref_snaps[i])), (pol, cfg, i)
     monkeypatch.delenv("PR_FUSED_CFG")
     monkeypatch.delenv("PR_FUSED_CHUNK")
+
+
+EVEN_CASES = [c for c in CASES if c[0] % 2 == 0] + [
+    (40, W.FLOW_ABC, (1.0, 1.0, 1.0), 0.05, 0.005, 3, 1, 6),
+    (36, W.FLOW_KOLMOGOROV, (0.8, 3.0, 0.0), 0.02, 0.01, 7, 3, 7)]
+
+
+@pytest.mark.parametrize("prec", [W.PREC_F64, W.PREC_MIXED], ids=["f64", "mixed"])
+def test_fine_blocked_tilings_are_bitwise_the_column_ones(ctx, prec, monkeypatch):
+    """The 2 x 2 register-blocked tilings (each thread four columns, LDS in
+    even/odd-z sub-planes) compute every point with the same operations as
+    the one-column tilings: bitwise the same fields and snapshots under every
+    chunk policy, on even grids with ragged tiles (n = 20, 36, 40 against
+    32 x 32 and 16 x 64 tiles), and the oracle's values (FP64 1e-12)."""
+    import paper_2601_10981_amd as pr
+    say(f"fine blocked tilings prec={prec}")
+    monkeypatch.setenv("PR_FUSED_CFG", "0")
+    ref_outs, ref_snaps = _run(ctx, EVEN_CASES, prec)
+    for pol in range(3):
+        monkeypatch.setenv("PR_FUSED_CHUNK", str(pol))
+        for cfg in (8, 9, 10):
+            monkeypatch.setenv("PR_FUSED_CFG", str(cfg))
+            outs, snaps = _run(ctx, EVEN_CASES, prec)
+            t = pr.pr_fine_tuned(ctx, prec, 40, len(EVEN_CASES), blocked=True)
+            assert t[3] == 1, t
+            for i in range(len(EVEN_CASES)):
+                assert np.array_equal(to_np(outs[i]), to_np(ref_outs[i])), (pol, cfg, i)
+                assert np.array_equal(to_np(snaps[i]), to_np(ref_snaps[i])), (pol, cfg, i)
+    monkeypatch.delenv("PR_FUSED_CFG")
+    monkeypatch.delenv("PR_FUSED_CHUNK")
+    if prec == W.PREC_F64:
+        for i, case in enumerate(EVEN_CASES):
+            n, flow, fp, kappa, dt, steps, se, seed = case
+            ref, _ = _oracle(n, flow, fp, kappa, dt, steps, se, W.random_field(n, seed))
+            assert rel_l2(to_np(ref_outs[i]), ref) <= 1e-12, case
 
 
 def test_fine_run_to_run_bitwise(ctx):

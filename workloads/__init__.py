@@ -209,6 +209,7 @@ ABC_256_MIXED = Workload(
     seed=3, init="fourier")
 
 STANDARD = [ABC_32_F64, KOL_128_F64, ABC_256_MIXED]
+BY_NAME = {w.name: w for w in STANDARD}
 
 
 def ensemble(count: int = 48, seed_base: int = 4000,
