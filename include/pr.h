@@ -360,6 +360,10 @@ typedef struct {
                          -1 where no such step ran                          */
   double* gap_ref;    /* the same layout: reference-vs-coarse gap (needs
                          U_ref); -1 where not recorded                      */
+  double* basis_orth; /* the same layout (opts.diag): max_ij |(Psi^T M Psi
+                         - I)_ij| over the valid columns of the basis Psi of
+                         that coarse step (the stage-2 basis; the k = 0
+                         basis in PR_MODE_FIXED_POD); -1 where not recorded */
 } pr_report;
 
 pr_status pr_parareal_solve(pr_ctx* ctx, const pr_grid_problem* prob,

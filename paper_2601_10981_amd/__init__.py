@@ -338,6 +338,8 @@ class Report:
     # coarse-gap diagnostics (opts.diag): k -> values for n = k..N-2
     gap_fine: dict = dataclasses.field(default_factory=dict)
     gap_ref: dict = dataclasses.field(default_factory=dict)
+    # max_ij |(Psi^T M Psi - I)_ij| of each recorded coarse step's basis
+    basis_orth: dict = dataclasses.field(default_factory=dict)
 
 
 class _ReportBuffers:
@@ -356,6 +358,7 @@ class _ReportBuffers:
         self.ranks = (ctypes.c_int * (cap * self.n_sub))()
         self.gap_fine = (ctypes.c_double * (cap * self.n_sub))()
         self.gap_ref = (ctypes.c_double * (cap * self.n_sub))()
+        self.basis_orth = (ctypes.c_double * (cap * self.n_sub))()
         self.rep = L.pr_report()
         self.rep.jump = self.jump
         self.rep.err = self.err
@@ -363,6 +366,7 @@ class _ReportBuffers:
         self.rep.ranks = self.ranks
         self.rep.gap_fine = self.gap_fine
         self.rep.gap_ref = self.gap_ref
+        self.rep.basis_orth = self.basis_orth
 
     def report(self, st: int, has_ref: bool) -> "Report":
         rep, k, n_sub, N = self.rep, self.rep.iters, self.n_sub, self.N
@@ -375,13 +379,14 @@ class _ReportBuffers:
                              for kk in range(1, k + 1)],
                       t_phase=dict(zip("FCUAG", list(rep.t_phase))),
                       fine_updates=rep.fine_updates, seconds=rep.seconds,
-                      gap_fine=self._gaps(self.gap_fine, k), gap_ref=self._gaps(self.gap_ref, k))
+                      gap_fine=self._gaps(self.gap_fine, k), gap_ref=self._gaps(self.gap_ref, k),
+                      basis_orth=self._gaps(self.basis_orth, k, keep_nan=True))
 
-    def _gaps(self, arr, k):
+    def _gaps(self, arr, k, keep_nan=False):
         out = {}
         for kk in range(1, k + 1):
             row = [arr[kk * self.n_sub + n] for n in range(kk, self.Np)]
-            if row and all(v >= 0 for v in row):
+            if row and all(v >= 0 or (keep_nan and v != v) for v in row):
                 out[kk] = row
         return out
 

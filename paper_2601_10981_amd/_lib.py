@@ -58,7 +58,8 @@ class pr_report(Structure):
                 ("jump", POINTER(c_double)), ("err", POINTER(c_double)),
                 ("t_iter", POINTER(c_double)), ("ranks", POINTER(c_int)),
                 ("t_phase", c_double * 5), ("fine_updates", c_double), ("seconds", c_double),
-                ("gap_fine", POINTER(c_double)), ("gap_ref", POINTER(c_double))]
+                ("gap_fine", POINTER(c_double)), ("gap_ref", POINTER(c_double)),
+                ("basis_orth", POINTER(c_double))]
 
 
 class pr_plan_info(Structure):

@@ -1284,6 +1284,8 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   rd.n_c_out = w.n_c_out;
   launch_reduced_one(rd, s);
   std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
+  if (w.diag_norms)   // the basis block of the Galerkin Gram: R^T M R
+    launch_orth_defect(Sbig, 16 * nb, w.m, cap, w.diag_norms + 8, s);
   if (w.diag_norms && w.n_in == 2 && w.fine) {
     // coarse-gap diagnostics: F(U_old) - G(U_old) and U_ref - G(U_new) with
     // their norms (Sec. 4, dT = delta t runs)

@@ -197,7 +197,8 @@ struct CoarseWork {
   double* norms4;         // 4 doubles (|U-prev|^2, |U|^2, |U-ref|^2, |ref|^2)
   // coarse-gap diagnostics (nullable): diag_norms[0..3] = the norms4 of
   // fine - Psi beta_1 against fine, [4..7] those of diag_ref - Psi beta_0
-  // against diag_ref (diag_ref nullable)
+  // against diag_ref (diag_ref nullable), [8] = max |R^T M R - I| of the
+  // basis R (its valid columns)
   double* diag_norms;
   const double* diag_ref;
 };

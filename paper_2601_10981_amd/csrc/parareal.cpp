@@ -32,6 +32,10 @@
 
 namespace pr {
 
+// per recorded sweep step: 8 coarse-gap norm partials and the basis's loss
+// of M-orthonormality
+constexpr int kDiagSlots = 9;
+
 struct Plan {
   pr_grid_problem prob;
   pr_parareal_opts o;
@@ -144,7 +148,7 @@ static Plan make_plan(const pr_grid_problem* p, const pr_parareal_opts* o) {
                                      : 2 * Np1 * o->cap0 * cs + warm_snaps)) +
                   (P.forced && !P.grid ? (size_t)P.np * cs : 0) + (size_t)P.nw * f8 +
                   ((size_t)4 << 20) +
-                  (P.diag ? (size_t)(P.max_iter + 1) * Np1 * 8 * 8 : 0);
+                  (P.diag ? (size_t)(P.max_iter + 1) * Np1 * kDiagSlots * 8 : 0);
   P.perF = plain ? 0 : (size_t)P.n_s * cs;        // snapshots of one subinterval
   // stage-2 basis and the pieces of L applied to it
   P.perS = plain ? 0 : (1 + (size_t)P.np) * o->cap * cs;
@@ -237,7 +241,8 @@ struct pr_solve {
   char* Psi = nullptr;
   char* LPsi = nullptr;     // per wave slot: np blocks of cap columns (L_j Psi)
   char* forcing = nullptr;  // forced flows: f_j fields of the np pieces
-  double* gaps = nullptr;   // diag: (max_iter + 1) x N' x 8 norms of the coarse gaps
+  double* gaps = nullptr;   // diag: (max_iter + 1) x N' x kDiagSlots (coarse-gap norms,
+                            // basis orthogonality)
   double *norms = nullptr, *betas0 = nullptr, *S0 = nullptr, *dscal = nullptr;
   int *m0slot = nullptr, *mS = nullptr, *misc = nullptr, *ranks = nullptr;
   double* host = nullptr;  // pinned: e_k, err_k
@@ -357,7 +362,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
       S->LPsi = (char*)owned_alloc(c, S, (size_t)P.waveS * P.np * P.o.cap * cs);
       if (P.forced) S->forcing = (char*)owned_alloc(c, S, (size_t)P.np * cs);
     }
-    if (P.diag) S->gaps = (double*)owned_alloc(c, S, (size_t)(P.max_iter + 1) * Np1 * 8 * 8);
+    if (P.diag) S->gaps = (double*)owned_alloc(c, S, (size_t)(P.max_iter + 1) * Np1 * kDiagSlots * 8);
     const int maxk = P.max_iter;
     const size_t n_norms = (size_t)(Np + 2) * 4, n_betas = Np1 * 32, n_S0 = 32 * 144, n_dscal = 8;
     const size_t n_dbl = n_norms + n_betas + n_S0 + n_dscal;
@@ -708,7 +713,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
     PR_HIP(hipMemcpyAsync(Ucur + (size_t)(k - 1) * ng, Uprev + (size_t)(k - 1) * ng, f8,
                           hipMemcpyDeviceToDevice, s));
     enqueue_correct(c, ng, {}, nullptr, S->Fn + (size_t)(k - 1) * ng, 0, Ucur + (size_t)k * ng,
-                    Uprev + (size_t)k * ng, Uref ? Uref + (size_t)(k + 1) * ng : nullptr,
+                    Uprev + (size_t)k * ng, Uref ? Uref + (size_t)(k + P.nw) * ng : nullptr,
                     S->norms + 4 * k, h3, s, "sol");
     // (iv) for the coarse-grid mode: G(U^k_n) - G(U^{k-1}_n) = G(U^k_n -
     // U^{k-1}_n) by linearity, plus F_n
@@ -742,7 +747,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
         w.t0 = t_hat(P, n);
         w.forcing = S->forcing;
         if (P.diag) {
-          w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
+          w.diag_norms = S->gaps + ((size_t)k * Np + n) * kDiagSlots;
           w.diag_ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
         }
         w.corr_out = Ucur + (size_t)(n + 1) * ng;
@@ -860,7 +865,7 @@ static void iterate_batch_impl(pr_ctx* c, const std::vector<pr_solve*>& live, hi
           w.t0 = t_hat(P, n);
           w.forcing = S->forcing;
           if (P.diag) {
-            w.diag_norms = S->gaps + ((size_t)k * Np + n) * 8;
+            w.diag_norms = S->gaps + ((size_t)k * Np + n) * kDiagSlots;
             w.diag_ref = Uref ? Uref + (size_t)(n + 1 + P.nw) * ng : nullptr;
           }
           w.corr_out = Ucur + (size_t)(n + 1) * ng;
@@ -951,25 +956,28 @@ static pr_status finish_solve(pr_ctx* c, pr_solve* S, double* U_out, pr_report* 
                             hipMemcpyDeviceToHost, s));
     for (int i = 0; i < 5; ++i) rep->t_phase[i] = S->t_phase[i];
     rep->fine_updates = S->fine_updates;
-    if (rep->gap_fine || rep->gap_ref) {
+    if (rep->gap_fine || rep->gap_ref || rep->basis_orth) {
       // coarse-gap diagnostics: sqrt(|F - G|^2 / |F|^2) and sqrt(|U_ref - G|^2 /
-      // |U_ref|^2) per recorded sweep step, -1 elsewhere
+      // |U_ref|^2) per recorded sweep step, and the loss of M-orthonormality
+      // of that step's basis; -1 elsewhere
       std::vector<double> g;
       if (P.diag && S->k > 0 && Np > 0) {
-        g.resize((size_t)(S->k + 1) * Np * 8);
+        g.resize((size_t)(S->k + 1) * Np * kDiagSlots);
         PR_HIP(hipMemcpyAsync(g.data(), S->gaps, g.size() * 8, hipMemcpyDeviceToHost, s));
         PR_HIP(hipStreamSynchronize(s));
       }
       for (int kk = 0; kk <= P.max_iter; ++kk)
         for (int n = 0; n < Np; ++n) {
-          double gf = -1.0, gr = -1.0;
+          double gf = -1.0, gr = -1.0, bo = -1.0;
           if (!g.empty() && kk >= 1 && kk <= S->k && n >= kk) {
-            const double* a = &g[((size_t)kk * Np + n) * 8];
+            const double* a = &g[((size_t)kk * Np + n) * kDiagSlots];
             if (a[3] > 0) gf = std::sqrt(a[1] / a[3]);
             if (S->U_ref && a[7] > 0) gr = std::sqrt(a[5] / a[7]);
+            bo = a[8];
           }
           if (rep->gap_fine) rep->gap_fine[(size_t)kk * Np + n] = gf;
           if (rep->gap_ref) rep->gap_ref[(size_t)kk * Np + n] = gr;
+          if (rep->basis_orth) rep->basis_orth[(size_t)kk * Np + n] = bo;
         }
     }
   }

@@ -453,6 +453,10 @@ void launch_reduced0(const Reduced0Desc* d, hipStream_t s);
 // out[i] = -in[i], i < n (one small vector, n <= 256).
 void launch_negate(const double* in, double* out, int n, hipStream_t s);
 
+// out[0] = max_{i, j < min(*m, cap)} |G[i ld + j] - delta_ij| (device m).
+void launch_orth_defect(const double* G, int ld, const int* m, int cap, double* out,
+                        hipStream_t s);
+
 // Partial-sum reduction of jump norms: per item sums partial (nwg x 4) in
 // fixed order into out (4 doubles, times h^3).
 // ---- grid transfers of the coarse-grid coarse propagator ---------------------

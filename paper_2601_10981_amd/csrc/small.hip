@@ -765,4 +765,32 @@ void launch_negate(const double* in, double* out, int n, hipStream_t s) {
   PR_HIP(hipGetLastError());
 }
 
+// out = max over i, j < min(*m, cap) of |G[i ld + j] - delta_ij| (NaN if any
+// entry is NaN): the loss of M-orthonormality of a basis from its Gram.
+__global__ void k_orth_defect(const double* __restrict__ G, int ld, const int* __restrict__ m,
+                              int cap, double* out) {
+  __shared__ double red[256];
+  const int q = min(*m, cap);
+  double v = 0.0;
+  for (int e = threadIdx.x; e < q * q; e += 256) {
+    const int i = e / q, j = e % q;
+    const double d = fabs(G[(size_t)i * ld + j] - (i == j ? 1.0 : 0.0));
+    if (!(d <= v)) v = d;   // keeps a NaN
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int t = 0; t < 256; ++t)
+      if (!(red[t] <= r)) r = red[t];
+    out[0] = r;
+  }
+}
+
+void launch_orth_defect(const double* G, int ld, const int* m, int cap, double* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_orth_defect, dim3(1), dim3(256), 0, s, G, ld, m, cap, out);
+  PR_HIP(hipGetLastError());
+}
+
 }  // namespace pr

@@ -486,6 +486,49 @@ def test_warm_up_window_of_two_subintervals(ctx, mode):
         assert worst <= 10.0 * env[k] + 1e-12
         if mode == W.MODE_ADAPTIVE:
             assert rep.ranks[k - 1] == ores.ranks[k]
+        # the reported error of iterate k: U_n against the reference at its
+        # own time (n + 2) DeltaT
+        host = max(rel_l2(Un[j], to_np(ref[j])) for j in range(2, opts.N + 1))
+        say(f"  reported error {rep.err[k]:.6e}, from the states {host:.6e}")
+        assert abs(rep.err[k] - host) <= 1e-10 * host + 1e-15
     U, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0), U_ref=ref)
     assert rep.iters == opts.N - 2 and rep.converged
     assert np.array_equal(to_np(U), to_np(ref))
+    assert rep.err[-1] == 0.0
+
+
+@pytest.mark.parametrize("prec,small_cholqr,bound", [
+    (W.PREC_F64, "1", 1e-2), (W.PREC_F64, "0", 1e-12), (W.PREC_MIXED, "1", 1e-6)],
+    ids=["f64", "f64_mode_gram", "mixed"])
+def test_stage2_basis_m_orthonormal(ctx, monkeypatch, prec, small_cholqr, bound):
+    """Loss of M-orthonormality, max_ij |(Psi^T M Psi - I)_ij|, of every
+    stage-2 basis the sweep uses, read from the sweep's own Galerkin Gram
+    (opts.diag). The case keeps every mode above the rank threshold tau_r
+    (gamma = 1, caps above the ranks), so lambda_1 / lambda_m is as large as
+    the rank rule allows. Bounds from the arithmetic:
+    * FP64, CholQR factor from the coefficient Gram C^T G C (default): the
+      rounding of the snapshot Gram G stays in the modes, about
+      eps lambda_1 / lambda_m <= eps / tau_r = 2.2e-3 (1e-2 with margin);
+    * FP64 with a Gram pass over the formed modes (PR_SMALL_CHOLQR=0): a few
+      eps;
+    * PR_MIXED (always the pass over the modes, in FP64, of modes stored in
+      FP32): the FP32 rounding of the stored modes, a few units of 2^-24."""
+    import paper_2601_10981_amd as pr
+    monkeypatch.setenv("PR_SMALL_CHOLQR", small_cholqr)
+    prob = W.Problem(n=12, kappa=0.05, flow=W.FLOW_ABC, fp=(1.0, 1.0, 1.0), precision=prec)
+    opts = W.PararealOpts(T=0.6, N=6, dt=0.01, cap0=12, cap=31, tol=0.0, max_iter=3,
+                          gamma1=1.0, gamma2=1.0, gamma3=1.0, diag=1)
+    u0 = W.fourier_field(prob.n, 21, n_modes=8, kmax=3.0)
+    p = pr.problem_of(prob)
+    _, rep = pr.pr_parareal_solve(ctx, p, opts, to_dev(u0))
+    assert rep.iters == 3
+    worst = 0.0
+    for k in range(1, 4):
+        row = rep.basis_orth[k]
+        say(f"basis orthogonality k={k} {prec} small_cholqr={small_cholqr}: {row} "
+            f"ranks {rep.ranks[k - 1]}")
+        assert len(row) == opts.N - 1 - k
+        for v in row:
+            assert v == v and 0.0 <= v <= bound, (k, v)
+            worst = max(worst, v)
+    say(f"worst {worst:.3e} (bound {bound:.0e})")
