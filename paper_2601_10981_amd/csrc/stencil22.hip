@@ -134,7 +134,7 @@ struct B22 {
   static_assert(SZ >= BZ + 2, "guard columns");
 };
 
-template <typename T, int TY, int TZ, int NT, bool XONLY, int RING>
+template <typename T, int TY, int TZ, int NT, bool XONLY, int RING, bool SPLIT>
 __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long long lt, T* lds,
                                            T (*vxt)[kB22Chunk + 10]) {
 #pragma clang fp contract(off)
@@ -201,6 +201,14 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
       vxt[1][i] = tab[4 * n + x];
     }
 
+  // A wave whose 64 blocks are all interior output blocks runs every stage on
+  // every lane: its copy of the march has no per-lane stage gating (SPLIT:
+  // the tilings whose register budget holds both copies without spilling).
+  constexpr bool kSplit = SPLIT && XONLY;
+  const bool full = kSplit && __ballot(!(inner && outp)) == 0ull;
+  auto body = [&](auto fullc) {
+  constexpr bool FULL = decltype(fullc)::value;
+  const bool live_ = FULL || live, mid_ = FULL || mid, outp_ = FULL || outp;
   // rings as in rk4_tile, per point of the block
   T Y[4][RING], W1[4][3], W2[4][3], W3[4][3];
 #pragma unroll
@@ -251,10 +259,10 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
       p[SUB + li] = a1;
       p[SUB + li + SZ] = a3;
     };
-    if (live) put(pl, Y[0][k3], Y[1][k3], Y[2][k3], Y[3][k3]);
-    if (live) put(pl + PLANE, W1[0][j1], W1[1][j1], W1[2][j1], W1[3][j1]);
-    if (mid) put(pl + 2 * PLANE, W2[0][j1], W2[1][j1], W2[2][j1], W2[3][j1]);
-    if (mid) put(pl + 3 * PLANE, W3[0][j1], W3[1][j1], W3[2][j1], W3[3][j1]);
+    if (live_) put(pl, Y[0][k3], Y[1][k3], Y[2][k3], Y[3][k3]);
+    if (live_) put(pl + PLANE, W1[0][j1], W1[1][j1], W1[2][j1], W1[3][j1]);
+    if (mid_) put(pl + 2 * PLANE, W2[0][j1], W2[1][j1], W2[2][j1], W2[3][j1]);
+    if (mid_) put(pl + 3 * PLANE, W3[0][j1], W3[1][j1], W3[2][j1], W3[3][j1]);
     __syncthreads();
     const int iv = tt - (x0 - 6);
     T vy_p[4], vz_p[4];   // per-plane velocity parts of stages 1..4
@@ -332,7 +340,7 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
       // stage 1 at plane tt + 3 (every block)
       in1();
       T w1[4] = {(T)0, (T)0, (T)0, (T)0};
-      if (live) {
+      if (live_) {
         comp(a, b, e, rd(pl), vy_p[0], vz_p[0], L);
 #pragma unroll
         for (int k = 0; k < 4; ++k) w1[k] = fma(c1, L[k], Y[k][k3]);
@@ -341,7 +349,7 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
       for (int k = 0; k < 4; ++k) W1[k][j2] = w1[k];
       // stage 2 at plane tt + 2
       T w2[4] = {(T)0, (T)0, (T)0, (T)0};
-      if (s2 && mid) {
+      if (s2 && mid_) {
         inW(W1);
         comp(a, b, e, rd(pl + PLANE), vy_p[1], vz_p[1], L);
 #pragma unroll
@@ -351,7 +359,7 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
       for (int k = 0; k < 4; ++k) W2[k][j2] = w2[k];
       // stage 3 at plane tt + 1
       T w3[4] = {(T)0, (T)0, (T)0, (T)0};
-      if (s3 && mid) {
+      if (s3 && mid_) {
         inW(W2);
         comp(a, b, e, rd(pl + 2 * PLANE), vy_p[2], vz_p[2], L);
 #pragma unroll
@@ -360,7 +368,7 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
 #pragma unroll
       for (int k = 0; k < 4; ++k) W3[k][j2] = w3[k];
       // output stage at plane tt
-      if (s4 && outp) {
+      if (s4 && outp_) {
         inW(W3);
         comp(a, b, e, rd(pl + 3 * PLANE), vy_p[3], vz_p[3], L);
         store();
@@ -382,6 +390,13 @@ __device__ __forceinline__ void rk4_tile22(const FineDesc<T>& d, int step, long 
   left -= min(left, RING - 6);
   for (; left >= RING; left -= RING) run_all<0, RING>(march);
   run_upto<0, RING>(march, left);
+  };
+  if constexpr (kSplit) {
+    if (full) body(std::true_type{});
+    else body(std::false_type{});
+  } else {
+    body(std::false_type{});
+  }
 #undef PR_B22_LOAD
 }
 
@@ -397,8 +412,9 @@ constexpr int b22_waves_per_simd() {
 
 // XO = 1: every field of the launch has a velocity along x only, and the
 // per-plane velocity table is not needed (more workgroups fit a CU);
-// XO = 0: each field takes its own operator form.
-template <typename T, int TY, int TZ, int NT, int RING, bool XO>
+// XO = 0: each field takes its own operator form. SPLIT (with XO = 1): fully
+// interior waves take a march without per-lane stage gating.
+template <typename T, int TY, int TZ, int NT, int RING, bool XO, bool SPLIT>
 __global__ __launch_bounds__(NT, (b22_waves_per_simd<T, TY, TZ, NT, XO>())) void k_rk4_b22(
     const FineDesc<T>* __restrict__ descs, int nd, int step, long long total, long long per_xcd) {
   using G = B22<T, TY, TZ>;
@@ -413,11 +429,11 @@ __global__ __launch_bounds__(NT, (b22_waves_per_simd<T, TY, TZ, NT, XO>())) void
   const FineDesc<T>& d = descs[f];
   if (step >= d.n_steps) return;
   if (XO || d.g.xonly)
-    rk4_tile22<T, TY, TZ, NT, true, RING>(d, step, t - d.tile_begin, lds,
-                                          (T (*)[kB22Chunk + 10])vxt);
+    rk4_tile22<T, TY, TZ, NT, true, RING, XO && SPLIT>(d, step, t - d.tile_begin, lds,
+                                                       (T (*)[kB22Chunk + 10])vxt);
   else
-    rk4_tile22<T, TY, TZ, NT, false, RING>(d, step, t - d.tile_begin, lds,
-                                           (T (*)[kB22Chunk + 10])vxt);
+    rk4_tile22<T, TY, TZ, NT, false, RING, false>(d, step, t - d.tile_begin, lds,
+                                                  (T (*)[kB22Chunk + 10])vxt);
 }
 
 // The y ring: nine planes, loads four steps ahead of their first use (on
@@ -425,11 +441,20 @@ __global__ __launch_bounds__(NT, (b22_waves_per_simd<T, TY, TZ, NT, XO>())) void
 // twelve nears the register limit).
 constexpr int kB22Ring = 9;
 
+// Tilings whose fully interior waves take the ungated march: FP64 with 32
+// columns along z (both copies of the march fit 256 VGPRs without spilling;
+// at 64 columns they do not, and FP32 runs at more waves per SIMD).
+template <typename T, int TY, int TZ>
+constexpr bool b22_split() {
+  return sizeof(T) == 8 && TZ == 32;
+}
+
 template <typename T, int TY, int TZ, int NT, bool XO>
 static void launch_b22_xo(const FineDesc<T>* d, int nd, long long total, int step,
                           hipStream_t s) {
   const long long g8 = (total + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_rk4_b22<T, TY, TZ, NT, kB22Ring, XO>), dim3((unsigned)g8), dim3(NT), 0, s,
+  hipLaunchKernelGGL((k_rk4_b22<T, TY, TZ, NT, kB22Ring, XO, b22_split<T, TY, TZ>()>),
+                     dim3((unsigned)g8), dim3(NT), 0, s,
                      d, nd, step, total, g8 / 8);
 }
 
@@ -443,8 +468,8 @@ static void launch_b22(const FineDesc<T>* d, int nd, long long total, int step, 
 template <typename T, int TY, int TZ, int NT, bool XO>
 static int occ_b22_xo() {
   int v = 0;
-  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_rk4_b22<T, TY, TZ, NT, kB22Ring, XO>,
-                                                      NT, 0));
+  PR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &v, k_rk4_b22<T, TY, TZ, NT, kB22Ring, XO, b22_split<T, TY, TZ>()>, NT, 0));
   return v;
 }
 
