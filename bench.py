@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--stencil-only", action="store_true",
                     help="time only the batched fine propagator (profiling runs)")
+    ap.add_argument("--stencil-f32", action="store_true",
+                    help="with --stencil-only: the same fields with the FP32 stencil (PR_MIXED)")
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the serial fine reference (no error history; profiling runs)")
     ap.add_argument("--sweep", action="store_true",
@@ -177,23 +179,25 @@ def cpu_baseline(w, budget_s):
                       f"{el:.1f} s)"}
 
 
-def copy_bandwidth(stream, nbytes=1 << 30, reps=10):
-    """Achieved HBM bandwidth of a plain device copy (torch's copy kernel):
-    nbytes read and nbytes written per copy, timed with HIP events on the
-    current stream; the best of reps."""
+def copy_bandwidth(stream, nbytes=1 << 30, trials=3, back_to_back=10):
+    """Achieved HBM bandwidth of a plain device copy (the runtime's copy
+    kernel): nbytes read and nbytes written per copy, back_to_back copies
+    between two HIP events on the current stream (so the events' own cost
+    is spread over them); the best of trials."""
     import torch
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
     b.copy_(a)
     best = None
-    for _ in range(reps):
+    for _ in range(trials):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        b.copy_(a)
+        for _ in range(back_to_back):
+            b.copy_(a)
         e1.record(stream)
         torch.cuda.synchronize()
-        s = e0.elapsed_time(e1) * 1e-3
+        s = e0.elapsed_time(e1) * 1e-3 / back_to_back
         best = s if best is None else min(best, s)
     del a, b
     return round(2 * nbytes / best / 1e9, 1)
@@ -429,13 +433,25 @@ def mixed256_run(args):
     # pr_parareal_solve), so that every iteration reports progress
     h = pr.pr_solve_begin(ctx, p32, opts, U_ref[0], U_ref=U_ref)
     k = 0
+    t_diag = 0.0      # progress checks, excluded from the solve time
+    state = torch.empty(ng, dtype=torch.float64, device="cuda")
     while not pr.pr_solve_done(h):
         pr.pr_solve_step_batch(ctx, [h])
         k += 1
-        log(f"  iteration {k} done at {time.perf_counter() - t0:.1f} s")
+        msg = f"  iteration {k} done at {time.perf_counter() - t0 - t_diag:.1f} s"
+        if k <= 4 or k % 16 == 0:
+            td = time.perf_counter()
+            e = 0.0
+            for j in range(1, N + 1):
+                pr.pr_solve_state(ctx, h, j, out=state)
+                e = max(e, (torch.linalg.vector_norm(state - U_ref[j]) /
+                            torch.linalg.vector_norm(U_ref[j])).item())
+            msg += f", max rel error {e:.3e}"
+            t_diag += time.perf_counter() - td
+        log(msg)
     _, rep = pr.pr_solve_end(ctx, h, U_out=U_out)
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el = time.perf_counter() - t0 - t_diag
     # the converged prefix U_j, j <= k + 1, is the FP32-stencil serial fine
     # solution: its distance to the FP64 one is the mixed-precision error of F
     prefix = [float("%.3e" % (torch.linalg.vector_norm(U_out[j] - U_ref[j]) /
@@ -486,20 +502,22 @@ def ensemble_run(args):
     # each instance's state at T against its own serial fine solution with
     # the FP64 stencil (after the timed loop)
     log("ensemble: FP64 serial references")
-    errs = []
+    errs, errs0 = [], []
     for r, w in zip(reqs, ws):
         import dataclasses
         p64 = pr.problem_of(dataclasses.replace(w.problem, precision=W.PREC_F64))
         plan = pr.pr_plan(p64, w.opts)
         u = W.fourier_field_device(w.problem.n, w.seed, "cuda").reshape(-1).clone()
+        n0 = torch.linalg.vector_norm(u).item()
         v = torch.empty_like(u)
         for j in range(w.opts.N):
             pr.pr_fine_propagate(ctx, [dict(prob=p64, dt=plan["dt"], n_steps=plan["n_f"],
                                             u_in=u, u_out=v, t0=j * w.opts.T / w.opts.N)])
             u, v = v, u
         torch.cuda.synchronize()
-        errs.append(float((torch.linalg.vector_norm(r.result - u) /
-                           torch.linalg.vector_norm(u)).item()))
+        d = torch.linalg.vector_norm(r.result - u).item()
+        errs.append(d / torch.linalg.vector_norm(u).item())
+        errs0.append(d / n0)
     out = {"mode": "ensemble", "instances": len(done), "wall_s": round(st.wall, 2),
            "solves_per_s": round(len(done) / st.wall, 4), "steps": st.steps,
            "fine_gpts": round(sum(c.fine_updates for c in done) / st.wall / 1e9, 1),
@@ -508,6 +526,12 @@ def ensemble_run(args):
            "iters": [c.iters for c in done], "status": [c.status for c in done],
            "err_at_T_vs_fp64_serial": [float("%.2e" % e) for e in errs],
            "max_err_at_T": float("%.3e" % max(errs)),
+           # the same difference relative to the initial field: the FP32
+           # stencil's rounding floor does not decay with the solution
+           "err_at_T_rel_initial": [float("%.2e" % e) for e in errs0],
+           "max_err_at_T_rel_initial": float("%.3e" % max(errs0)),
+           "decay_at_T": [float("%.2e" % (a / b)) if b > 0 else None
+                          for a, b in zip(errs0, errs)],
            "seeds": f"4000..{4000 + len(done) - 1}"}
     ctx.close()
     print(json.dumps(out))
@@ -540,7 +564,9 @@ def study_run(args):
             pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=plan["dt"], n_steps=plan["n_f"],
                                             u_in=ref[j], u_out=ref[j + 1])])
         for ml, p, mode in ((0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (0, 0, 1), (0, 0, 2)):
-            opts = W.PararealOpts(**{**base.__dict__, "ml": ml, "p": p, "mode": mode})
+            # Parareal-I builds its fixed POD basis over T_0 = 2 DeltaT (Sec. 4)
+            opts = W.PararealOpts(**{**base.__dict__, "ml": ml, "p": p, "mode": mode,
+                                     "n_warm": 2 if mode == W.MODE_FIXED_POD else 1})
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, rep = pr.pr_parareal_solve(ctx, prob, opts, u0, U_ref=ref)
@@ -658,6 +684,10 @@ def paper_flow_run(args):
                                                                    W.MODE_FIXED_POD),
                             ("parareal_II_coarse_grid", W.MODE_COARSE_GRID)):
             opts = dataclasses.replace(base, mode=mode)
+            if mode == W.MODE_FIXED_POD:
+                # Parareal-I: the fixed basis from T_0 = 2 DeltaT = 10 (Sec. 4);
+                # delta_M = 20 keeps its 1000 warm-up steps within 64 snapshots
+                opts = dataclasses.replace(opts, n_warm=2, dM=20)
             log(f"  {mname}")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -767,8 +797,12 @@ def main():
     import paper_2601_10981_amd as pr
     import workloads as W
 
+    import dataclasses
     w = W.KOL_128_F64
-    prob = pr.problem_of(w.problem)
+    f32 = args.stencil_only and args.stencil_f32
+    prec = pr.PR_MIXED if f32 else pr.PR_F64
+    prob = pr.problem_of(dataclasses.replace(w.problem, precision=W.PREC_MIXED) if f32
+                         else w.problem)
     opts = w.opts
     n = w.problem.n
     ng = n ** 3
@@ -823,11 +857,12 @@ def main():
     launches = n_f
     avg_launch_s = fine_ms * 1e-3 / launches
     # algorithmic bytes of one fused RK4 step: read y and write y_new once
-    # per point (8 + 8 B in FP64); halo re-reads and LDS traffic are not counted
-    bytes_per_launch = 16 * ng * B
+    # per point (8 + 8 B in FP64, 4 + 4 B in FP32); halo re-reads and LDS
+    # traffic are not counted
+    bytes_per_launch = (8 if f32 else 16) * ng * B
     achieved = bytes_per_launch / avg_launch_s / 1e9
     stencil_gpts = B * ng * n_f / (fine_ms * 1e-3) / 1e9
-    kname = pr.fine_kernel_name(ctx, pr.PR_F64, n, B) or "k_rk4_fused<double>"
+    kname = pr.fine_kernel_name(ctx, prec, n, B) or "k_rk4_fused<double>"
     copy_gbs = copy_bandwidth(stream)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -849,7 +884,7 @@ def main():
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
-                t = pr.pr_fine_tuned(ctx, pr.PR_F64, n, B, blocked=True)
+                t = pr.pr_fine_tuned(ctx, prec, n, B, blocked=True)
                 key = "%dx%dx%d%s/chunks%d" % (t[:3] + ("b22" if t[3] else "", pol))
                 sweep[key] = round(B * ng * n_f / (ms * 1e-3) / 1e9, 2)
                 log(f"  tiling {key}: {sweep[key]} GPts/s")
