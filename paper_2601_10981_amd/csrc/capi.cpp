@@ -738,6 +738,10 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
   size_t part_total = 0;
   for (auto& it : items) {
     PR_CHECK(it.cols.size() == ncol, "Gram column list size mismatch");
+    // the FP32-MFMA kernel reads every column as float
+    if (f32)
+      for (const ColDesc& cd : it.cols)
+        PR_CHECK(cd.ptr == nullptr || cd.f32, "FP32 Gram over a column that is not FP32");
     GemmDesc d{};
     d.nrows = it.nrows;
     d.chunk_rows = gram_chunk_rows(it.nrows);

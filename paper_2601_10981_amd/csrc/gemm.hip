@@ -237,12 +237,13 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
         // vector loads pay in the symmetric (POD) Grams; the sweep's one-item
         // Galerkin products measured slower with them
         if (UL == 4 && NB == 0 && act && cv[t] && c16[t] && rb + 3 < r_end) {
-          load_col4<In>(cp[t], cf[t], rb, v[t]);
+          load_col4<In>(cp[t], F32 ? 1 : cf[t], rb, v[t]);
         } else {
 #pragma unroll
           for (int u = 0; u < UL; ++u) {
             const long long row = rb + u;
-            v[t][u] = (act && cv[t] && row < r_end) ? load_col<In>(cp[t], cf[t], row) : (In)0;
+            v[t][u] = (act && cv[t] && row < r_end) ? load_col<In>(cp[t], F32 ? 1 : cf[t], row)
+                                                    : (In)0;
           }
         }
       }
@@ -257,7 +258,10 @@ __global__ __launch_bounds__(256) void k_gemm_tn(const GemmDesc* __restrict__ de
             if (NB == 0 && jb < ia) continue;
             const int p = (NB == 0) ? ia * NA - ia * (ia - 1) / 2 + (jb - ia) : ia * NB + jb;
             const int ib = (NB == 0) ? jb : NA + jb;
-            if (ia >= tA || jb >= tB) continue;
+            // FP32 multiplies every tile pair (padding tiles hold zeros):
+            // a per-pair branch there splits the FP32 accumulators' live
+            // ranges and the compiler copies them around every MFMA
+            if (!F32 && (ia >= tA || jb >= tB)) continue;
             const In va = (kCanAinB && a_in_b) ? v[kCanAinB ? NA + ia : ia][u] : v[ia][u];
             if constexpr (F32)
               acc32[p] = M::op(va, v[ib][u], acc32[p]);
