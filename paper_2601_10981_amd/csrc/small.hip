@@ -14,6 +14,12 @@ namespace pr {
 constexpr int kMaxN = 64;
 constexpr int kMaxSweeps = 40;
 constexpr double kJacobiRel = 1e-15;
+// A rotation is also skipped when |a_pq| is at the rounding level of the whole
+// matrix (unit roundoff times its trace, the sum of the eigenvalues of the
+// PSD Gram). With the relative test alone, pairs of eigenvalues near the
+// bottom of a fast-decaying spectrum keep rotating on rounding noise until
+// the sweep limit; their eigenvectors are no better resolved by it.
+constexpr double kJacobiAbs = 0x1p-53;
 
 __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ descs) {
   const EigDesc d = descs[blockIdx.x];
@@ -32,6 +38,7 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
   // original, kpos: original -> compact or -1)
   __shared__ int kid[kMaxN], kpos[kMaxN];
   __shared__ int nk_sh;
+  __shared__ double trace_sh;
   const int tid = threadIdx.x;
   const int nc = d.nc;
   if (tid < 64) {
@@ -51,6 +58,13 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
     V[i][j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < nk; ++i) tr += A[i][i];
+    trace_sh = tr;
+  }
+  __syncthreads();
+  const double floor_abs = kJacobiAbs * trace_sh;
   const int half = N / 2;
   for (int sweep = 0; sweep < kMaxSweeps && N >= 2; ++sweep) {
     if (tid == 0) rotated = 0;
@@ -63,7 +77,8 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
         const int p = min(a, b), q = max(a, b);
         const double apq = A[p][q], app = A[p][p], aqq = A[q][q];
         double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-300 && fabs(apq) > kJacobiRel * sqrt(fabs(app * aqq))) {
+        if (fabs(apq) > 1e-300 && fabs(apq) > kJacobiRel * sqrt(fabs(app * aqq)) &&
+            fabs(apq) > floor_abs) {
           const double tau = (aqq - app) / (2.0 * apq);
           double t;
           if (fabs(tau) > 1e150) t = 0.5 / tau;
