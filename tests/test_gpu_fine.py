@@ -253,3 +253,42 @@ def test_fine_full_size_kolmogorov128(ctx):
     pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=n_f, u_in=uin[3], u_out=one)])
     torch.cuda.synchronize()
     assert torch.equal(one, uout[3])
+
+
+@pytest.mark.parametrize("forced_cfg", [None, "8"], ids=["tuned", "b22_32x32"])
+def test_fine_full_size_bench_launch_63_fields(ctx, monkeypatch, forced_cfg):
+    """The stencil launch the benchmark times: 63 subinterval fields of the
+    128^3 Kolmogorov workload in one batched launch (the autotuner's pick,
+    and the 2 x 2 blocked 32 x 32 tiling over whole 128-plane chunks that
+    the committed profile covers). Sampled oracle parity on the first, a
+    middle and the last field after three steps (<= 1e-12), and bitwise
+    agreement of every field with the same field propagated alone."""
+    import torch
+    import paper_2601_10981_amd as pr
+    if forced_cfg is not None:
+        monkeypatch.setenv("PR_FUSED_CFG", forced_cfg)
+        monkeypatch.setenv("PR_FUSED_CHUNK", "1")
+    w = W.KOL_128_F64
+    prob = pr.problem_of(w.problem)
+    u0 = to_dev(W.initial_field(w))
+    n_f, dt = fd.steps_per_subinterval(w.opts.T / w.opts.N, w.opts.dt)
+    B = w.opts.N - 1
+    uin = torch.stack([u0 * (1.0 + 0.01 * i) for i in range(B)])
+    uout = torch.empty_like(uin)
+    say(f"fine 128^3 x{B}, 3 steps, cfg {forced_cfg}")
+    pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=3, u_in=uin[i], u_out=uout[i])
+                               for i in range(B)])
+    torch.cuda.synchronize()
+    if forced_cfg is not None:
+        t = pr.pr_fine_tuned(ctx, pr.PR_F64, w.problem.n, B, planes=True, blocked=True)
+        assert t == (32, 32, 448, 128, 1), t
+    op = fd.Operator.of(w.problem)
+    for i in (0, B // 2, B - 1):
+        n = w.problem.n
+        ref, _ = fd.fine_propagate(op, to_np(uin[i]).reshape(n, n, n), dt, 3)
+        assert rel_l2(to_np(uout[i]), ref) <= 1e-12, i
+    one = torch.empty_like(uin[0])
+    for i in (0, B - 1):
+        pr.pr_fine_propagate(ctx, [dict(prob=prob, dt=dt, n_steps=3, u_in=uin[i], u_out=one)])
+        torch.cuda.synchronize()
+        assert torch.equal(one, uout[i]), i
