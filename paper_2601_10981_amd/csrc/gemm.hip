@@ -659,30 +659,24 @@ void launch_correct(const CorrectDesc* d, int nd, long long total_wg, hipStream_
   PR_HIP(hipGetLastError());
 }
 
-// Per item: out[0..4) = scale * fixed-order sums of partial[nwg][4].
-__global__ __launch_bounds__(256) void k_norm_reduce(const NormReduceDesc* __restrict__ descs) {
-  __shared__ double red[4][4];
+// Per item (one wave each): out[0..4) = scale * fixed-order sums of
+// partial[nwg][4] (strided per lane, then the wave's butterfly).
+__global__ __launch_bounds__(64) void k_norm_reduce(const NormReduceDesc* __restrict__ descs) {
   const NormReduceDesc& d = descs[blockIdx.x];
   double s[4] = {0, 0, 0, 0};
-  for (int w = threadIdx.x; w < d.nwg; w += 256)
+  for (int w = threadIdx.x; w < d.nwg; w += 64)
 #pragma unroll
     for (int i = 0; i < 4; ++i) s[i] += d.partial[(long long)w * 4 + i];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < 4; ++i) s[i] = wave_sum(s[i]);
-  if (lane == 0)
+  if (threadIdx.x == 0)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) red[wave][i] = s[i];
-  __syncthreads();
-  if (threadIdx.x < 4) {
-    const int i = threadIdx.x;
-    d.out[i] = d.scale * ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
-  }
+    for (int i = 0; i < 4; ++i) d.out[i] = d.scale * s[i];
 }
 
 void launch_norm_reduce(const NormReduceDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(256), 0, s, d);
+  hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(64), 0, s, d);
   PR_HIP(hipGetLastError());
 }
 
@@ -755,24 +749,17 @@ __global__ __launch_bounds__(256) void k_cgs(const CgsArgs a) {
   }
 }
 
-// Per output j <= n (one workgroup each): scale * the chunk partials summed
-// in a fixed order (strided per thread, then a fixed tree).
-__global__ __launch_bounds__(256) void k_cgs_reduce(const CgsArgs a) {
-  __shared__ double red[256];
+// Per output j <= n (one wave each): scale * the chunk partials summed in a
+// fixed order (strided per lane, then the wave's butterfly).
+__global__ __launch_bounds__(64) void k_cgs_reduce(const CgsArgs a) {
   const int j = blockIdx.x == 0 ? a.n : (int)blockIdx.x - 1;
   const PR_GLOBAL double* part = gptr(a.partial);
   double s = 0.0;
-  for (int q = threadIdx.x; q < a.nchunks; q += 256) s += part[(long long)q * (a.n + 1) + j];
-  red[threadIdx.x] = s;
-  __syncthreads();
-#pragma unroll
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
+  for (int q = threadIdx.x; q < a.nchunks; q += 64) s += part[(long long)q * (a.n + 1) + j];
+  s = wave_sum(s);
   if (threadIdx.x == 0) {
     if (j == a.n) {
-      const double nd2 = a.scale * red[0];
+      const double nd2 = a.scale * s;
       *gptr(a.norm) = nd2;
       if (a.flag) {
         // the degenerate-augmentation test (||d~|| <= tau ||u||), squared
@@ -782,7 +769,7 @@ __global__ __launch_bounds__(256) void k_cgs_reduce(const CgsArgs a) {
         *gptr(a.dscale) = flag ? 1.0 / sqrt(nd2) : 0.0;
       }
     } else {
-      gptr(a.dots)[j] = a.scale * red[0];
+      gptr(a.dots)[j] = a.scale * s;
     }
   }
 }
@@ -830,7 +817,7 @@ void launch_cgs(const CgsArgs& a, hipStream_t s) {
   else if (dots) cgs_width<true, false>(a, s);
   else cgs_width<false, true>(a, s);
   PR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cgs_reduce, dim3(dots ? a.n + 1 : 1), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_cgs_reduce, dim3(dots ? a.n + 1 : 1), dim3(64), 0, s, a);
   PR_HIP(hipGetLastError());
 }
 
