@@ -66,6 +66,16 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
   __syncthreads();
   const double floor_abs = kJacobiAbs * trace_sh;
   const int half = N / 2;
+  // this thread's (pair, column) slots of a round's updates: the same in every
+  // round, so their index arithmetic stays out of the rotation loop
+  constexpr int kSlots = (kMaxN / 2 * kMaxN + 255) / 256;
+  int slot_i[kSlots], slot_k[kSlots];
+#pragma unroll
+  for (int r = 0; r < kSlots; ++r) {
+    const int e = tid + 256 * r;
+    slot_i[r] = e < half * N ? e / N : -1;
+    slot_k[r] = e < half * N ? e % N : 0;
+  }
   for (int sweep = 0; sweep < kMaxSweeps && N >= 2; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -93,8 +103,10 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
         qq[tid] = q;
       }
       __syncthreads();
-      for (int e = tid; e < half * N; e += 256) {
-        const int i = e / N, k = e % N;
+#pragma unroll
+      for (int r2 = 0; r2 < kSlots; ++r2) {
+        const int i = slot_i[r2], k = slot_k[r2];
+        if (i < 0) break;
         const double s = sn[i];
         if (s == 0.0) continue;
         const double c = cs[i];
@@ -104,8 +116,10 @@ __global__ __launch_bounds__(256) void k_eig_select(const EigDesc* __restrict__ 
         A[q][k] = s * apk + c * aqk;
       }
       __syncthreads();
-      for (int e = tid; e < half * N; e += 256) {
-        const int i = e / N, k = e % N;
+#pragma unroll
+      for (int r2 = 0; r2 < kSlots; ++r2) {
+        const int i = slot_i[r2], k = slot_k[r2];
+        if (i < 0) break;
         const double s = sn[i];
         if (s == 0.0) continue;
         const double c = cs[i];
