@@ -1110,7 +1110,10 @@ void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi
                      const double* coef, const void* fine, int fine_f32, double* out,
                      const double* prev, const double* ref, double* norms4, double h3,
                      hipStream_t s, const std::string& tag) {
-  const int nwg = (int)std::min<long long>(4096, std::max<long long>(1, (nrows + 2047) / 2048));
+  // about one row per thread (at most 4096 workgroups): the correction reads
+  // its columns one after another, so a small grid needs many workgroups in
+  // flight to hide the load latency
+  const int nwg = (int)std::min<long long>(4096, std::max<long long>(1, (nrows + 255) / 256));
   double* part = (double*)scratch(c, tag + "_cpart", (size_t)nwg * 4 * 8);
   CorrectDesc d{};
   d.nrows = nrows;

@@ -480,10 +480,28 @@ struct RedShared {
   int q, n_c, bad;
 };
 
+// This thread's entries (row, column) of a q x q reduced system, e = tid +
+// 256 r for r < 4 (q <= 32): fixed for a kernel, so the loops over the
+// system's entries do no index division.
+struct QSlots {
+  int i[4], j[4];
+};
+__device__ __forceinline__ QSlots q_slots(int q) {
+  QSlots sl;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = tid + 256 * r;
+    sl.i[r] = e < q * q ? e / q : -1;
+    sl.j[r] = e < q * q ? e % q : 0;
+  }
+  return sl;
+}
+
 // Cholesky in place of sh.M (q x q, lower); sets bad on a non-positive (or
 // NaN) pivot, which is then clamped only so the factorisation completes: the
 // callers turn bad into NaN coefficients.
-__device__ void red_cholesky(RedShared& sh, int q) {
+__device__ void red_cholesky(RedShared& sh, int q, const QSlots& sl) {
   const int tid = threadIdx.x;
   for (int j = 0; j < q; ++j) {
     if (tid == 0) {
@@ -495,10 +513,11 @@ __device__ void red_cholesky(RedShared& sh, int q) {
     const double ljj = sh.M[j][j];
     for (int i = j + 1 + tid; i < q; i += 256) sh.M[i][j] /= ljj;
     __syncthreads();
-    const int t = q - j - 1;
-    for (int e = tid; e < t * t; e += 256) {
-      const int i = j + 1 + e / t, k = j + 1 + e % t;
-      if (k <= i) sh.M[i][k] -= sh.M[i][j] * sh.M[k][j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = sl.i[r], k = sl.j[r];
+      if (i < 0) break;
+      if (k > j && k <= i) sh.M[i][k] -= sh.M[i][j] * sh.M[k][j];
     }
     __syncthreads();
   }
@@ -520,13 +539,15 @@ __device__ void red_solve(const RedShared& sh, int q, double* x, int stride) {
 
 // Given sh.M (Cholesky factor) and sh.K holding L_r, turn sh.K into
 // M_r^{-1} L_r, apply the guard and form sh.B = P4(h K) by Horner.
-__device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0) {
+__device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0, const QSlots& sl) {
   const int tid = threadIdx.x;
   if (tid < q) red_solve(sh, q, &sh.K[0][tid], kMaxQ + 2);
   __syncthreads();
   double s = 0.0;
-  for (int e = tid; e < q * q; e += 256) {
-    const double v = sh.K[e / q][e % q];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (sl.i[r] < 0) break;
+    const double v = sh.K[sl.i[r]][sl.j[r]];
     s += v * v;
   }
   sh.red[tid] = s;
@@ -542,21 +563,29 @@ __device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0) {
   __syncthreads();
   const double h = dT / sh.n_c;
   // B = I + (h/4) K
-  for (int e = tid; e < q * q; e += 256) {
-    const int i = e / q, j = e % q;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = sl.i[r], j = sl.j[r];
+    if (i < 0) break;
     sh.B[i][j] = (i == j ? 1.0 : 0.0) + 0.25 * h * sh.K[i][j];
   }
   __syncthreads();
   const double cf[3] = {h / 3.0, h / 2.0, h};
   for (int st = 0; st < 3; ++st) {
-    for (int e = tid; e < q * q; e += 256) {
-      const int i = e / q, j = e % q;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = sl.i[r], j = sl.j[r];
+      if (i < 0) break;
       double acc = 0.0;
       for (int k = 0; k < q; ++k) acc += sh.K[i][k] * sh.B[k][j];
       sh.T[i][j] = (i == j ? 1.0 : 0.0) + cf[st] * acc;
     }
     __syncthreads();
-    for (int e = tid; e < q * q; e += 256) sh.B[e / q][e % q] = sh.T[e / q][e % q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (sl.i[r] < 0) break;
+      sh.B[sl.i[r]][sl.j[r]] = sh.T[sl.i[r]][sl.j[r]];
+    }
     __syncthreads();
   }
 }
@@ -566,7 +595,8 @@ __device__ void red_propagator(RedShared& sh, int q, double dT, int n_c0) {
 // and the unsolved L_r,j / f_r,j in the same places. Solves in place and sets
 // sh.n_c by the guard on sum_j ||K_j||_F (|theta_j| <= 1 bounds
 // ||K(t)||_F by it at every t).
-__device__ void red_forced_setup(RedShared& sh, int q, int np, double dT, int n_c0) {
+__device__ void red_forced_setup(RedShared& sh, int q, int np, double dT, int n_c0,
+                                 const QSlots& sl) {
   const int tid = threadIdx.x;
   double (*P[kMaxPieces])[kMaxQ + 2] = {sh.K, sh.B, sh.T};
   for (int e = tid; e < np * q; e += 256) red_solve(sh, q, &P[e / q][0][e % q], kMaxQ + 2);
@@ -575,8 +605,10 @@ __device__ void red_forced_setup(RedShared& sh, int q, int np, double dT, int n_
   double nrm = 0.0;
   for (int j = 0; j < np; ++j) {
     double s = 0.0;
-    for (int e = tid; e < q * q; e += 256) {
-      const double v = P[j][e / q][e % q];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (sl.i[r] < 0) break;
+      const double v = P[j][sl.i[r]][sl.j[r]];
       s += v * v;
     }
     sh.red[tid] = s;
@@ -637,15 +669,16 @@ __device__ void red_advance_forced(RedShared& sh, int q, int nv, int np, int kin
 // beta[v] <- B^{n_c} beta[v] for v < nv.
 __device__ void red_advance(RedShared& sh, int q, int nv) {
   const int tid = threadIdx.x;
+  const bool act = tid < nv * q;
+  const int v = act ? tid / q : 0, i = act ? tid % q : 0;
   for (int it = 0; it < sh.n_c; ++it) {
-    if (tid < nv * q) {
-      const int v = tid / q, i = tid % q;
+    if (act) {
       double acc = 0.0;
       for (int k = 0; k < q; ++k) acc += sh.B[i][k] * sh.beta[v][k];
       sh.tmp[v][i] = acc;
     }
     __syncthreads();
-    if (tid < nv * q) sh.beta[tid / q][tid % q] = sh.tmp[tid / q][tid % q];
+    if (act) sh.beta[v][i] = sh.tmp[v][i];
     __syncthreads();
   }
 }
@@ -683,7 +716,8 @@ __device__ void reduced_run(const ReducedDesc& d) {
     sh.g[j][a] = d.S[(long long)sh.idx[a] * d.ld + d.off_F + j];
   }
   __syncthreads();
-  red_cholesky(sh, q);
+  const QSlots sl = q_slots(q);
+  red_cholesky(sh, q, sl);
   if (tid < d.n_in) red_solve(sh, q, sh.beta[tid], 1);
   __syncthreads();
   // M_r not positive definite (a NaN or a breakdown): the coefficients become
@@ -691,10 +725,10 @@ __device__ void reduced_run(const ReducedDesc& d) {
   if (sh.bad && tid < d.n_in * q) sh.beta[tid / q][tid % q] = NAN;
   __syncthreads();
   if (d.forced) {
-    red_forced_setup(sh, q, np, d.dT, d.n_c);
+    red_forced_setup(sh, q, np, d.dT, d.n_c, sl);
     red_advance_forced(sh, q, d.n_in, np, d.forced, d.w, d.t0, d.dT);
   } else {
-    red_propagator(sh, q, d.dT, d.n_c);
+    red_propagator(sh, q, d.dT, d.n_c, sl);
     red_advance(sh, q, d.n_in);
   }
   const int w = d.cap + 1;
@@ -759,13 +793,14 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   if (tid < q) sh.beta[0][tid] = d.S[(long long)tid * d.ld + d.off_U];
   if (d.forced && tid < np * q) sh.g[tid / q][tid % q] = d.S[(long long)(tid % q) * d.ld + d.off_F + tid / q];
   __syncthreads();
-  red_cholesky(sh, q);
+  const QSlots sl = q_slots(q);
+  red_cholesky(sh, q, sl);
   if (tid == 0) red_solve(sh, q, sh.beta[0], 1);
   __syncthreads();
   if (sh.bad && tid < q) sh.beta[0][tid] = NAN;   // as in reduced_run
   __syncthreads();
-  if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c);
-  else red_propagator(sh, q, d.dT, d.n_c);
+  if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c, sl);
+  else red_propagator(sh, q, d.dT, d.n_c, sl);
   for (int n = 0; n < d.count; ++n) {
     // subinterval n runs over [(n + n_warm) dT, (n + n_warm + 1) dT]
     if (d.forced)
