@@ -163,18 +163,38 @@ hipEvent_t event_get(pr_ctx* c) {
 }
 void event_put(pr_ctx* c, hipEvent_t e) { c->ev_pool.push_back(e); }
 
+hipEvent_t timing_event_get(pr_ctx* c) {
+  if (!c->ev_pool_timing.empty()) {
+    hipEvent_t e = c->ev_pool_timing.back();
+    c->ev_pool_timing.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PR_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+  return e;
+}
+void timing_event_put(pr_ctx* c, hipEvent_t e) { c->ev_pool_timing.push_back(e); }
+
+PhaseEvents::~PhaseEvents() {
+  if (c)
+    for (hipEvent_t e : marks) timing_event_put(c, e);
+}
+hipEvent_t PhaseEvents::mark() {
+  hipEvent_t e = timing_event_get(c);
+  marks.push_back(e);
+  PR_HIP(hipEventRecord(e, s));
+  return e;
+}
 void PhaseEvents::begin(int phase) {
-  if (!c) return;
-  end();
+  if (!c || phase == cur) return;
+  hipEvent_t e = mark();
+  if (cur >= 0) open.push_back({cur, {cur_start, e}});
   cur = phase;
-  cur_start = event_get(c);
-  PR_HIP(hipEventRecord(cur_start, s));
+  cur_start = e;
 }
 void PhaseEvents::end() {
   if (!c || cur < 0) return;
-  hipEvent_t e = event_get(c);
-  PR_HIP(hipEventRecord(e, s));
-  open.push_back({cur, {cur_start, e}});
+  open.push_back({cur, {cur_start, mark()}});
   cur = -1;
   cur_start = nullptr;
 }
@@ -184,10 +204,15 @@ void PhaseEvents::collect() {
     float ms = 0.f;
     PR_HIP(hipEventElapsedTime(&ms, o.second.first, o.second.second));
     t[o.first] += ms * 1e-3;
-    event_put(c, o.second.first);
-    event_put(c, o.second.second);
   }
   open.clear();
+  // events of the running phase stay out of the pool until it ends
+  size_t keep = 0;
+  for (hipEvent_t e : marks) {
+    if (e == cur_start) marks[keep++] = e;
+    else timing_event_put(c, e);
+  }
+  marks.resize(keep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1390,6 +1415,7 @@ void pr_ctx_destroy(pr_ctx* c) {
   }
   if (c->host_scalars) (void)hipHostFree(c->host_scalars);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto e : c->ev_pool_timing) (void)hipEventDestroy(e);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   delete c;
 }

@@ -47,6 +47,9 @@ struct pr_ctx {
   double* host_scalars = nullptr;
 
   std::vector<hipEvent_t> ev_pool;
+  // Events used only to time phases: recorded without the system-scope
+  // fence, whose cache writeback otherwise stalls the stream at every mark.
+  std::vector<hipEvent_t> ev_pool_timing;
 };
 
 namespace pr {
@@ -211,20 +214,31 @@ void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi
                      const double* prev, const double* ref, double* norms4, double h3,
                      hipStream_t s, const std::string& tag);
 
-// Phase timing with events (F, C, U, A, G).
+// Phase timing with events (F, C, U, A, G). One event marks each phase
+// change: it ends the interval of the phase before and starts the next one.
 struct PhaseEvents {
   pr_ctx* c = nullptr;
   hipStream_t s = nullptr;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
+  std::vector<hipEvent_t> marks;   // every event recorded, released by collect()
   double t[5] = {0, 0, 0, 0, 0};
   int cur = -1;
   hipEvent_t cur_start = nullptr;
+  PhaseEvents() = default;
+  PhaseEvents(const PhaseEvents&) = delete;
+  PhaseEvents& operator=(const PhaseEvents&) = delete;
+  ~PhaseEvents();
   void begin(int phase);
   void end();
   void collect();   // after a synchronisation point
+ private:
+  hipEvent_t mark();
 };
 
 hipEvent_t event_get(pr_ctx* c);
 void event_put(pr_ctx* c, hipEvent_t e);
+// Timing-only events (no system-scope fence at record; not for host waits).
+hipEvent_t timing_event_get(pr_ctx* c);
+void timing_event_put(pr_ctx* c, hipEvent_t e);
 
 }  // namespace pr

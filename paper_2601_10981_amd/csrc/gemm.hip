@@ -659,24 +659,38 @@ void launch_correct(const CorrectDesc* d, int nd, long long total_wg, hipStream_
   PR_HIP(hipGetLastError());
 }
 
-// Per item (one wave each): out[0..4) = scale * fixed-order sums of
-// partial[nwg][4] (strided per lane, then the wave's butterfly).
-__global__ __launch_bounds__(64) void k_norm_reduce(const NormReduceDesc* __restrict__ descs) {
+// Per item (one workgroup each): out[0..4) = scale * fixed-order sums of
+// partial[nwg][4] (strided per thread, each wave's butterfly, then the four
+// waves in order). The partials are 32-byte aligned rows of four.
+__global__ __launch_bounds__(256) void k_norm_reduce(const NormReduceDesc* __restrict__ descs) {
+  __shared__ double red[4][4];
   const NormReduceDesc& d = descs[blockIdx.x];
+  const PR_GLOBAL v2d_t* part = (const PR_GLOBAL v2d_t*)gptr(d.partial);
   double s[4] = {0, 0, 0, 0};
-  for (int w = threadIdx.x; w < d.nwg; w += 64)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) s[i] += d.partial[(long long)w * 4 + i];
+#pragma unroll 4
+  for (int w = threadIdx.x; w < d.nwg; w += 256) {
+    const v2d_t a = part[2 * w], b = part[2 * w + 1];
+    s[0] += a.x;
+    s[1] += a.y;
+    s[2] += b.x;
+    s[3] += b.y;
+  }
 #pragma unroll
   for (int i = 0; i < 4; ++i) s[i] = wave_sum(s[i]);
-  if (threadIdx.x == 0)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d.out[i] = d.scale * s[i];
+    for (int i = 0; i < 4; ++i) red[wave][i] = s[i];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    const int i = threadIdx.x;
+    d.out[i] = d.scale * ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
+  }
 }
 
 void launch_norm_reduce(const NormReduceDesc* d, int nd, hipStream_t s) {
   if (nd <= 0) return;
-  hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(64), 0, s, d);
+  hipLaunchKernelGGL(k_norm_reduce, dim3(nd), dim3(256), 0, s, d);
   PR_HIP(hipGetLastError());
 }
 
