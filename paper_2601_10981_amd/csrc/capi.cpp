@@ -388,6 +388,22 @@ int gram_chunk_rows(long long nrows) {
   return (int)std::min(ch, std::max<long long>(cap, 64));
 }
 
+// One item alone: about three workgroups per CU (its kernel holds three
+// waves per SIMD), so that enough row loads are in flight.
+constexpr long long kGalerkinChunks = 768;
+int galerkin_chunk_rows(long long nrows) {
+  long long ch = (nrows + kGalerkinChunks - 1) / kGalerkinChunks;
+  ch = std::max<long long>(ch, 1024);
+  ch = (ch + 63) / 64 * 64;
+  const long long cap = (nrows + 63) / 64 * 64;
+  return (int)std::min(ch, std::max<long long>(cap, 64));
+}
+
+long long gram_chunks_max(long long nrows) {
+  const long long a = gram_chunk_rows(nrows), b = galerkin_chunk_rows(nrows);
+  return std::max((nrows + a - 1) / a, (nrows + b - 1) / b);
+}
+
 // ---------------------------------------------------------------------------
 // fine propagator
 // Chunk-length policies of the fused stencil (fine_chunk). Policies 0 and 1
@@ -769,7 +785,8 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
         PR_CHECK(cd.ptr == nullptr || cd.f32, "FP32 Gram over a column that is not FP32");
     GemmDesc d{};
     d.nrows = it.nrows;
-    d.chunk_rows = gram_chunk_rows(it.nrows);
+    d.chunk_rows = it.chunk_rows > 0 ? it.chunk_rows : gram_chunk_rows(it.nrows);
+    PR_CHECK(d.chunk_rows % 64 == 0, "Gram chunks must hold whole 64-row steps");
     d.nchunks = (int)((it.nrows + d.chunk_rows - 1) / d.chunk_rows);
     d.wg_begin = wg;
     wg += d.nchunks;
@@ -1288,6 +1305,7 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   gb.ld = 16 * nb;
   gb.scale = h3;
   gb.a_in_b = 1;                                   // A = B's leading Psi block
+  gb.chunk_rows = galerkin_chunk_rows(ng);
   PR_CHECK(32 * gb.ld * 8 <= 57344 - 20480, "Galerkin block exceeds its scratch");
   enqueue_gram(c, {gb}, na, nb, false, s, "co_g");
 

@@ -100,6 +100,10 @@ inline int tiles_x(int n) { return (n + kChunkX - 1) / kChunkX; }
 // Chunking of the MFMA Gram: rows per chunk (multiple of 64) for an item of
 // `nrows` rows; independent of the batch.
 int gram_chunk_rows(long long nrows);
+// Rows per workgroup of the sweep's one-item Galerkin product, and the most
+// chunks either chunking gives for nrows (partial buffers are sized by it).
+int galerkin_chunk_rows(long long nrows);
+long long gram_chunks_max(long long nrows);
 
 // Enqueue helpers shared by the entry points and the solver.
 struct FineWork {
@@ -147,6 +151,7 @@ struct GramWork {
   double scale;
   int a_in_b = 0;              // 1: the A columns are a prefix of the B columns
                                // (then null slots); A is taken from B's loads
+  int chunk_rows = 0;          // rows per workgroup (0: gram_chunk_rows)
 };
 void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
                   hipStream_t s, const std::string& tag);

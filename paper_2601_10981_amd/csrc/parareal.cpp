@@ -186,8 +186,7 @@ static bool helpers_fit(const pr_ctx* c, size_t fine_b, size_t pod_b) {
 // augmentation fields, L R, Gram partials of the sweep) for one solve.
 static size_t shared_scratch_bytes(const Plan& P) {
   const size_t f8 = (size_t)P.ng * 8, fs = (size_t)P.ng * P.sf;
-  const long long ch = gram_chunk_rows(P.ng);
-  const size_t nch = (size_t)((P.ng + ch - 1) / ch);
+  const size_t nch = (size_t)gram_chunks_max(P.ng);
   // coarse-grid mode: two coarse fields, the coarse fine-step work fields
   const size_t grid = P.grid ? (size_t)P.pc.n * P.pc.n * P.pc.n * (16 + (P.f32 ? 12 : 8)) : 0;
   // coarse step: augmentation fields d, L_j d (co_fields) and Gram partials
@@ -378,7 +377,7 @@ static pr_solve* begin_solve(pr_ctx* c, const pr_grid_problem* prob, const pr_pa
     S->ranks = S->misc + 64;
     PR_HIP(hipHostMalloc((void**)&S->host, 64));
     // shared helper scratch, pre-sized so nothing regrows mid-iteration
-    const long long nch = (ng + gram_chunk_rows(ng) - 1) / gram_chunk_rows(ng);
+    const long long nch = gram_chunks_max(ng);
     scratch(c, "co_g_part", (size_t)nch * 10 * 256 * 8);
     scratch(c, "co_fields", fs * 2 + f8);
     scratch(c, "co_LR", (size_t)P.o.cap * fs);
