@@ -763,15 +763,21 @@ __global__ __launch_bounds__(256) void k_cgs(const CgsArgs a) {
   }
 }
 
-// Per output j <= n (one wave each): scale * the chunk partials summed in a
-// fixed order (strided per lane, then the wave's butterfly).
-__global__ __launch_bounds__(64) void k_cgs_reduce(const CgsArgs a) {
+// Per output j <= n (one workgroup each): scale * the chunk partials summed
+// in a fixed order (strided per thread, each wave's butterfly, then the four
+// waves in order).
+__global__ __launch_bounds__(256) void k_cgs_reduce(const CgsArgs a) {
+  __shared__ double red[4];
   const int j = blockIdx.x == 0 ? a.n : (int)blockIdx.x - 1;
   const PR_GLOBAL double* part = gptr(a.partial);
   double s = 0.0;
-  for (int q = threadIdx.x; q < a.nchunks; q += 64) s += part[(long long)q * (a.n + 1) + j];
+#pragma unroll 4
+  for (int q = threadIdx.x; q < a.nchunks; q += 256) s += part[(long long)q * (a.n + 1) + j];
   s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    s = (red[0] + red[1]) + (red[2] + red[3]);
     if (j == a.n) {
       const double nd2 = a.scale * s;
       *gptr(a.norm) = nd2;
@@ -831,7 +837,7 @@ void launch_cgs(const CgsArgs& a, hipStream_t s) {
   else if (dots) cgs_width<true, false>(a, s);
   else cgs_width<false, true>(a, s);
   PR_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cgs_reduce, dim3(dots ? a.n + 1 : 1), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_cgs_reduce, dim3(dots ? a.n + 1 : 1), dim3(256), 0, s, a);
   PR_HIP(hipGetLastError());
 }
 
