@@ -25,7 +25,9 @@
 namespace pr {
 
 // Evaluate (L in) along x for one (j, k) column over planes [x0, x1),
-// calling emit(x, p, Lv) for each plane. Periodic wrap on every axis.
+// calling emit(x, p, Lv) for each plane. Periodic wrap on every axis. The
+// loads of four planes are issued before any of them is used, so a thread
+// waits for memory once per four planes rather than once per plane.
 template <typename T, typename Emit>
 __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __restrict__ in, int j,
                                         int k, int x0, int x1, Emit emit) {
@@ -39,25 +41,44 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
   const T vy_z = tab[3 * n + k];
   const T vz_y = tab[5 * n + j];
   const int q = j * n + k;
+  const int oym = jm * n + k, oyp = jp * n + k, ozm = j * n + km, ozp = j * n + kp;
   const int xm0 = (x0 == 0) ? n - 1 : x0 - 1;
   T cm = in[(long long)xm0 * plane + q];
   T c0 = in[(long long)x0 * plane + q];
-#pragma unroll 4
-  for (int x = x0; x < x1; ++x) {
-    const int xp = (x == n - 1) ? 0 : x + 1;
-    const long long base = (long long)x * plane;
-    const T cp = in[(long long)xp * plane + q];
-    const T ym = in[base + jm * n + k];
-    const T yp = in[base + jp * n + k];
-    const T zm = in[base + j * n + km];
-    const T zp = in[base + j * n + kp];
-    const T vy = tab[2 * n + x] + vy_z;
-    const T vz = tab[4 * n + x] + vz_y;
+  auto point = [&](int x, T cp, T ym, T yp, T zm, T zp, T ty, T tz) {
+    const T vy = ty + vy_z;
+    const T vz = tz + vz_y;
     const T lap = ((cp + cm) + (yp + ym) + (zp + zm)) - (T)6 * c0;
     const T adv = vx * (cp - cm) + vy * (yp - ym) + vz * (zp - zm);
-    emit(x, base + q, clap * lap - adv);
+    emit(x, (long long)x * plane + q, clap * lap - adv);
     cm = c0;
     c0 = cp;
+  };
+  constexpr int U = 4;
+  int x = x0;
+  for (; x + U <= x1; x += U) {
+    T cp[U], ym[U], yp[U], zm[U], zp[U], ty[U], tz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int xx = x + u;
+      const int xp = (xx == n - 1) ? 0 : xx + 1;
+      const long long base = (long long)xx * plane;
+      cp[u] = in[(long long)xp * plane + q];
+      ym[u] = in[base + oym];
+      yp[u] = in[base + oyp];
+      zm[u] = in[base + ozm];
+      zp[u] = in[base + ozp];
+      ty[u] = tab[2 * n + xx];
+      tz[u] = tab[4 * n + xx];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) point(x + u, cp[u], ym[u], yp[u], zm[u], zp[u], ty[u], tz[u]);
+  }
+  for (; x < x1; ++x) {
+    const int xp = (x == n - 1) ? 0 : x + 1;
+    const long long base = (long long)x * plane;
+    point(x, in[(long long)xp * plane + q], in[base + oym], in[base + oyp], in[base + ozm],
+          in[base + ozp], tab[2 * n + x], tab[4 * n + x]);
   }
 }
 
