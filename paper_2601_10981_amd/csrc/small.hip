@@ -486,6 +486,7 @@ struct RedShared {
 struct QSlots {
   int i[4], j[4];
 };
+static_assert(kMaxQ * kMaxQ <= 4 * 256, "four entries per thread cover the largest system");
 __device__ __forceinline__ QSlots q_slots(int q) {
   QSlots sl;
   const int tid = threadIdx.x;
