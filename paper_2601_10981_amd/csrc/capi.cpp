@@ -768,9 +768,10 @@ void enqueue_fine(pr_ctx* c, const std::vector<FineWork>& items, hipStream_t s,
 
 // ---------------------------------------------------------------------------
 // Gram products
-void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
-                  hipStream_t s, const std::string& tag) {
-  if (items.empty()) return;
+StagedGram stage_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
+                      const std::string& tag) {
+  StagedGram g;
+  if (items.empty()) return g;
   const int P = (nb == 0) ? na * (na + 1) / 2 : na * nb;
   const size_t ncol = (size_t)(na + nb) * 16;
   std::vector<GemmDesc> descs;
@@ -817,17 +818,35 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
     descs[i].partial = part + part_off[i];
     descs[i].cols = stage_push(c, items[i].cols);
   }
-  GemmDesc* dd = stage_push(c, descs);
+  g.dd = stage_push(c, descs);
+  g.nd = (int)descs.size();
+  g.wg = wg;
+  g.na = na;
+  g.nb = nb;
+  g.f32 = f32;
+  return g;
+}
+
+void launch_gram_staged(const StagedGram& g, hipStream_t s) {
+  if (g.nd <= 0) return;
+  launch_gemm_tn(g.dd, g.nd, g.wg, g.na, g.nb, g.f32, s);
+  launch_gemm_reduce(g.dd, g.nd, g.na, g.nb, s);
+}
+
+void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
+                  hipStream_t s, const std::string& tag) {
+  const StagedGram g = stage_gram(c, items, na, nb, f32, tag);
   stage_flush(c, s);
-  launch_gemm_tn(dd, (int)descs.size(), wg, na, nb, f32, s);
-  launch_gemm_reduce(dd, (int)descs.size(), na, nb, s);
+  launch_gram_staged(g, s);
 }
 
 // ---------------------------------------------------------------------------
 // L applied to columns
-void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s) {
-  if (items.empty()) return;
+StagedApplyL stage_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items) {
+  StagedApplyL st;
+  if (items.empty()) return st;
   const bool f32 = items[0].prob->precision == PR_MIXED;
+  st.f32 = f32;
   long long tiles = 0;
   // x planes per workgroup: kChunkX, or 4 when that leaves a launch (one
   // column of L d in the sweep) under 2048 workgroups
@@ -852,9 +871,8 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
       d.push_back(a);
     }
-    auto* dd = stage_push(c, d);
-    stage_flush(c, s);
-    launch_applyL_f32(dd, (int)d.size(), tiles, s);
+    st.dd = stage_push(c, d);
+    st.nd = (int)d.size();
   } else {
     std::vector<ApplyLDesc<double>> d;
     for (auto& w : items) {
@@ -873,10 +891,23 @@ void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipSt
       tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
       d.push_back(a);
     }
-    auto* dd = stage_push(c, d);
-    stage_flush(c, s);
-    launch_applyL_f64(dd, (int)d.size(), tiles, s);
+    st.dd = stage_push(c, d);
+    st.nd = (int)d.size();
   }
+  st.tiles = tiles;
+  return st;
+}
+
+void launch_applyL_staged(const StagedApplyL& st, hipStream_t s) {
+  if (st.nd <= 0) return;
+  if (st.f32) launch_applyL_f32((const ApplyLDesc<float>*)st.dd, st.nd, st.tiles, s);
+  else launch_applyL_f64((const ApplyLDesc<double>*)st.dd, st.nd, st.tiles, s);
+}
+
+void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s) {
+  const StagedApplyL st = stage_applyL_batch(c, items);
+  stage_flush(c, s);
+  launch_applyL_staged(st, s);
 }
 
 void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out, int ncols,
@@ -887,14 +918,20 @@ void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* o
 // L_j applied to ncols columns (ld elements apart; 0: N_g) for every piece j
 // of the problem's flow: piece j's columns at out + j * ncols columns (one
 // piece, L itself, for a steady flow).
-void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
-                           int ncols, const int* mptr, hipStream_t s, long long ld) {
+static std::vector<ApplyLWork> applyL_piece_work(const pr_grid_problem& p, const void* in,
+                                                 void* out, int ncols, const int* mptr,
+                                                 long long ld) {
   if (ld <= 0) ld = ngrid(p);
   const size_t col = (size_t)ld * (p.precision == PR_MIXED ? 4 : 8);
   std::vector<ApplyLWork> v;
   for (int j = 0; j < flow_pieces(p); ++j)
     v.push_back(ApplyLWork{&p, in, (char*)out + (size_t)j * ncols * col, ncols, mptr, j, ld});
-  enqueue_applyL_batch(c, v, s);
+  return v;
+}
+
+void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
+                           int ncols, const int* mptr, hipStream_t s, long long ld) {
+  enqueue_applyL_batch(c, applyL_piece_work(p, in, out, ncols, mptr, ld), s);
 }
 
 // The forcing fields f_j of a forced flow's pieces (field precision), one
@@ -1148,10 +1185,10 @@ void enqueue_pod(pr_ctx* c, const std::vector<PodWork>& items, hipStream_t s,
 
 // ---------------------------------------------------------------------------
 // correction / lift
-void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi,
-                     const double* coef, const void* fine, int fine_f32, double* out,
-                     const double* prev, const double* ref, double* norms4, double h3,
-                     hipStream_t s, const std::string& tag) {
+StagedCorrect stage_correct(pr_ctx* c, long long nrows, const ColDesc* psi_dev, int npsi,
+                            const double* coef, const void* fine, int fine_f32, double* out,
+                            const double* prev, const double* ref, double* norms4, double h3,
+                            const std::string& tag) {
   // about one row per thread (at most 4096 workgroups): the correction reads
   // its columns one after another, so a small grid needs many workgroups in
   // flight to hide the load latency
@@ -1159,8 +1196,8 @@ void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi
   double* part = (double*)scratch(c, tag + "_cpart", (size_t)nwg * 4 * 8);
   CorrectDesc d{};
   d.nrows = nrows;
-  d.psi = psi.empty() ? nullptr : stage_push(c, psi);
-  d.npsi = (int)psi.size();
+  d.psi = npsi > 0 ? psi_dev : nullptr;
+  d.npsi = npsi;
   d.coef = coef;
   d.fine = fine;
   d.fine_f32 = fine_f32;
@@ -1170,12 +1207,29 @@ void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi
   d.partial = part;
   d.wg_begin = 0;
   d.nwg = nwg;
-  CorrectDesc* dd = stage_push1(c, d);
+  StagedCorrect k;
+  k.dd = stage_push1(c, d);
   NormReduceDesc nr{part, nwg, h3, norms4};
-  NormReduceDesc* nrd = stage_push1(c, nr);
+  k.nrd = stage_push1(c, nr);
+  k.nwg = nwg;
+  return k;
+}
+
+void launch_correct_staged(const StagedCorrect& k, hipStream_t s) {
+  if (!k.dd) return;
+  launch_correct(k.dd, 1, k.nwg, s);
+  launch_norm_reduce(k.nrd, 1, s);
+}
+
+void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi,
+                     const double* coef, const void* fine, int fine_f32, double* out,
+                     const double* prev, const double* ref, double* norms4, double h3,
+                     hipStream_t s, const std::string& tag) {
+  const ColDesc* pd = psi.empty() ? nullptr : stage_push(c, psi);
+  const StagedCorrect k = stage_correct(c, nrows, pd, (int)psi.size(), coef, fine, fine_f32, out,
+                                        prev, ref, norms4, h3, tag);
   stage_flush(c, s);
-  launch_correct(dd, 1, nwg, s);
-  launch_norm_reduce(nrd, 1, s);
+  launch_correct_staged(k, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1231,7 +1285,75 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     return col_of((const char*)LR + (size_t)jp * cap * cld * sf, j, cld, f32, w.m);
   };
   auto f64col = [&](const double* x) { return ColDesc{x, nullptr, 0, 0}; };
-  const int* aug = nullptr;
+  const int* aug = w.u_aug ? flag : nullptr;
+
+  // Every descriptor of the launches after the Gram-Schmidt passes is staged
+  // first and uploaded by one flush, so the step's launches are not
+  // interleaved with descriptor uploads.
+  StagedApplyL st_Ld;
+  if (w.u_aug) st_Ld = stage_applyL_batch(c, applyL_piece_work(p, dcol, Ld, 1, flag, 0));
+  // Galerkin products of Psi = [R, d] against [Psi, L_j Psi per piece,
+  // u_in, f_j per piece], the B columns packed (cap + 1 per block) so the
+  // launch shape follows the columns that can be valid
+  GramWork gb;
+  gb.nrows = ng;
+  const int npsi = cap + 1;
+  std::vector<ColDesc> psi;
+  for (int j = 0; j < npsi; ++j)
+    psi.push_back(j < cap ? Rcol(j)
+                          : (aug ? ColDesc{dcol, aug, 0, f32 ? 1 : 0} : col_null()));
+  const int na = (npsi + 15) / 16;
+  gb.cols = psi;                                   // A tiles
+  gb.cols.resize((size_t)na * 16, col_null());
+  std::vector<ColDesc> bc(psi);                    // B: Psi
+  for (int jp = 0; jp < np; ++jp)                  // B: L_j Psi per piece
+    for (int j = 0; j < npsi; ++j)
+      bc.push_back(j < cap ? LRcol(jp, j)
+                           : (aug ? ColDesc{(const char*)Ld + (size_t)jp * ng * sf, aug, 0,
+                                            f32 ? 1 : 0}
+                                  : col_null()));
+  const int off_U = (int)bc.size();
+  for (int i = 0; i < w.n_in; ++i) bc.push_back(f64col(w.u_in[i]));   // B: states
+  const int off_F = (int)bc.size();
+  for (int jp = 0; forced && jp < np; ++jp)                            // B: forcing
+    bc.push_back(col_of(forcing, jp, cld, f32, nullptr));
+  const int nb = ((int)bc.size() + 15) / 16;
+  bc.resize((size_t)nb * 16, col_null());
+  gb.cols.insert(gb.cols.end(), bc.begin(), bc.end());
+  gb.out = Sbig;
+  gb.ld = 16 * nb;
+  gb.scale = h3;
+  gb.a_in_b = 1;                                   // A = B's leading Psi block
+  gb.chunk_rows = galerkin_chunk_rows(ng);
+  PR_CHECK(32 * gb.ld * 8 <= 57344 - 20480, "Galerkin block exceeds its scratch");
+  const StagedGram st_g = stage_gram(c, {gb}, na, nb, false, "co_g");
+
+  double* beta = w.beta_out ? w.beta_out : betas;
+  const std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
+  const ColDesc* psi_dev = stage_push(c, psi_cols);
+  // coarse-gap diagnostics: F(U_old) - G(U_old) and U_ref - G(U_new) with
+  // their norms (Sec. 4, dT = delta t runs)
+  const bool gaps = w.diag_norms && w.n_in == 2 && w.fine;
+  double* nbeta = (double*)(sm + 57344);   // 2 x (cap + 1)
+  StagedCorrect st_gap_f, st_gap_r, st_corr;
+  std::vector<StagedCorrect> st_lift;
+  if (gaps) {
+    double* dout = (double*)scratch(c, "co_diag", (size_t)ng * 8);
+    st_gap_f = stage_correct(c, ng, psi_dev, npsi, nbeta + (cap + 1), w.fine, 0, dout, nullptr,
+                             w.fine, w.diag_norms, h3, "co");
+    if (w.diag_ref)
+      st_gap_r = stage_correct(c, ng, psi_dev, npsi, nbeta, w.diag_ref, 0, dout, nullptr,
+                               w.diag_ref, w.diag_norms + 4, h3, "co");
+  }
+  if (w.corr_out)
+    st_corr = stage_correct(c, ng, psi_dev, npsi, coef, w.fine, 0, w.corr_out, w.prev, w.ref,
+                            w.norms4 ? w.norms4 : nrm, h3, "co");
+  for (int i = 0; i < w.n_in; ++i)
+    if (w.lift[i])
+      st_lift.push_back(stage_correct(c, ng, psi_dev, npsi, beta + (size_t)i * (cap + 1), nullptr,
+                                      0, w.lift[i], nullptr, nullptr, nrm, h3, "co"));
+  stage_flush(c, s);
+
   if (w.u_aug) {
     P.begin(3);
     // CGS2 of eqaug, one fused pass each: (1) c1 = R^T M u and |u|_M^2;
@@ -1268,49 +1390,13 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
     a3.dscale = dscale;
     launch_cgs(a3, s);
     launch_scale_into(dtil, dcol, f32, ng, dscale, s);
-    aug = flag;
     P.begin(2);
-    enqueue_applyL_pieces(c, p, dcol, Ld, 1, flag, s);
+    launch_applyL_staged(st_Ld, s);
   }
   P.begin(2);
-  // Galerkin products of Psi = [R, d] against [Psi, L_j Psi per piece,
-  // u_in, f_j per piece], the B columns packed (cap + 1 per block) so the
-  // launch shape follows the columns that can be valid
-  GramWork gb;
-  gb.nrows = ng;
-  const int npsi = cap + 1;
-  std::vector<ColDesc> psi;
-  for (int j = 0; j < npsi; ++j)
-    psi.push_back(j < cap ? Rcol(j)
-                          : (aug ? ColDesc{dcol, aug, 0, f32 ? 1 : 0} : col_null()));
-  const int na = (npsi + 15) / 16;
-  gb.cols = psi;                                   // A tiles
-  gb.cols.resize((size_t)na * 16, col_null());
-  std::vector<ColDesc> bc(psi);                    // B: Psi
-  for (int jp = 0; jp < np; ++jp)                  // B: L_j Psi per piece
-    for (int j = 0; j < npsi; ++j)
-      bc.push_back(j < cap ? LRcol(jp, j)
-                           : (aug ? ColDesc{(const char*)Ld + (size_t)jp * ng * sf, aug, 0,
-                                            f32 ? 1 : 0}
-                                  : col_null()));
-  const int off_U = (int)bc.size();
-  for (int i = 0; i < w.n_in; ++i) bc.push_back(f64col(w.u_in[i]));   // B: states
-  const int off_F = (int)bc.size();
-  for (int jp = 0; forced && jp < np; ++jp)                            // B: forcing
-    bc.push_back(col_of(forcing, jp, cld, f32, nullptr));
-  const int nb = ((int)bc.size() + 15) / 16;
-  bc.resize((size_t)nb * 16, col_null());
-  gb.cols.insert(gb.cols.end(), bc.begin(), bc.end());
-  gb.out = Sbig;
-  gb.ld = 16 * nb;
-  gb.scale = h3;
-  gb.a_in_b = 1;                                   // A = B's leading Psi block
-  gb.chunk_rows = galerkin_chunk_rows(ng);
-  PR_CHECK(32 * gb.ld * 8 <= 57344 - 20480, "Galerkin block exceeds its scratch");
-  enqueue_gram(c, {gb}, na, nb, false, s, "co_g");
+  launch_gram_staged(st_g, s);
 
   P.begin(4);
-  double* beta = w.beta_out ? w.beta_out : betas;
   ReducedDesc rd{};
   rd.S = Sbig;
   rd.ld = 16 * nb;
@@ -1333,28 +1419,15 @@ void enqueue_coarse(pr_ctx* c, const CoarseWork& w, hipStream_t s, PhaseEvents* 
   rd.coef = coef;
   rd.n_c_out = w.n_c_out;
   launch_reduced_one(rd, s);
-  std::vector<ColDesc> psi_cols(psi.begin(), psi.begin() + cap + 1);
   if (w.diag_norms)   // the basis block of the Galerkin Gram: R^T M R
     launch_orth_defect(Sbig, 16 * nb, w.m, cap, w.diag_norms + 8, s);
-  if (w.diag_norms && w.n_in == 2 && w.fine) {
-    // coarse-gap diagnostics: F(U_old) - G(U_old) and U_ref - G(U_new) with
-    // their norms (Sec. 4, dT = delta t runs)
-    double* nbeta = (double*)(sm + 57344);   // 2 x (cap + 1)
+  if (gaps) {
     launch_negate(beta, nbeta, 2 * (cap + 1), s);
-    double* dout = (double*)scratch(c, "co_diag", (size_t)ng * 8);
-    enqueue_correct(c, ng, psi_cols, nbeta + (cap + 1), w.fine, 0, dout, nullptr, w.fine,
-                    w.diag_norms, h3, s, "co");
-    if (w.diag_ref)
-      enqueue_correct(c, ng, psi_cols, nbeta, w.diag_ref, 0, dout, nullptr, w.diag_ref,
-                      w.diag_norms + 4, h3, s, "co");
+    launch_correct_staged(st_gap_f, s);
+    launch_correct_staged(st_gap_r, s);
   }
-  if (w.corr_out)
-    enqueue_correct(c, ng, psi_cols, coef, w.fine, 0, w.corr_out, w.prev, w.ref,
-                    w.norms4 ? w.norms4 : nrm, h3, s, "co");
-  for (int i = 0; i < w.n_in; ++i)
-    if (w.lift[i])
-      enqueue_correct(c, ng, psi_cols, beta + (size_t)i * (cap + 1), nullptr, 0, w.lift[i],
-                      nullptr, nullptr, nrm, h3, s, "co");
+  launch_correct_staged(st_corr, s);
+  for (const StagedCorrect& k : st_lift) launch_correct_staged(k, s);
   P.end();
 }
 

@@ -155,6 +155,19 @@ struct GramWork {
 };
 void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
                   hipStream_t s, const std::string& tag);
+// The enqueue helpers in two halves: stage_* pushes the descriptors (no
+// flush, no launch), launch_*_staged launches once a flush has uploaded them.
+// A caller staging several launches flushes once for all of them.
+struct StagedGram {
+  GemmDesc* dd = nullptr;
+  int nd = 0;
+  long long wg = 0;
+  int na = 0, nb = 0;
+  bool f32 = false;
+};
+StagedGram stage_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb, bool f32,
+                      const std::string& tag);
+void launch_gram_staged(const StagedGram& g, hipStream_t s);
 
 void enqueue_applyL(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out, int ncols,
                     const int* mptr, hipStream_t s);
@@ -169,6 +182,14 @@ struct ApplyLWork {
   int skip_tail = 0;      // 1: columns >= *mptr left unwritten (else zeroed)
 };
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
+struct StagedApplyL {
+  bool f32 = false;
+  const void* dd = nullptr;   // ApplyLDesc<float> or <double>
+  int nd = 0;
+  long long tiles = 0;
+};
+StagedApplyL stage_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items);
+void launch_applyL_staged(const StagedApplyL& st, hipStream_t s);
 void enqueue_applyL_pieces(pr_ctx* c, const pr_grid_problem& p, const void* in, void* out,
                            int ncols, const int* mptr, hipStream_t s, long long ld = 0);
 void enqueue_forcing_fields(pr_ctx* c, const pr_grid_problem& p, void* out, hipStream_t s,
@@ -218,6 +239,17 @@ void enqueue_correct(pr_ctx* c, long long nrows, const std::vector<ColDesc>& psi
                      const double* coef, const void* fine, int fine_f32, double* out,
                      const double* prev, const double* ref, double* norms4, double h3,
                      hipStream_t s, const std::string& tag);
+struct StagedCorrect {
+  CorrectDesc* dd = nullptr;
+  NormReduceDesc* nrd = nullptr;
+  int nwg = 0;
+};
+// psi_dev: npsi column descriptors already staged (shared by several calls).
+StagedCorrect stage_correct(pr_ctx* c, long long nrows, const ColDesc* psi_dev, int npsi,
+                            const double* coef, const void* fine, int fine_f32, double* out,
+                            const double* prev, const double* ref, double* norms4, double h3,
+                            const std::string& tag);
+void launch_correct_staged(const StagedCorrect& k, hipStream_t s);
 
 // Phase timing with events (F, C, U, A, G). One event marks each phase
 // change: it ends the interval of the phase before and starts the next one.
