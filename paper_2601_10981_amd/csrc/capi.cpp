@@ -842,66 +842,75 @@ void enqueue_gram(pr_ctx* c, const std::vector<GramWork>& items, int na, int nb,
 
 // ---------------------------------------------------------------------------
 // L applied to columns
+// Descriptors of one L launch of element type T: tiles of tq points of the
+// (y, z) plane (tq_of(n) tiles per plane) by cx planes.
+template <typename T, typename TQ>
+static long long applyL_descs(pr_ctx* c, const std::vector<ApplyLWork>& items, int cx, TQ tq_of,
+                              std::vector<ApplyLDesc<T>>& d) {
+  long long tiles = 0;
+  for (auto& w : items) {
+    ApplyLDesc<T> a{};
+    a.g = geom_piece(geom_of(c, *w.prob), w.piece);
+    a.in = (const T*)w.in;
+    a.out = (T*)w.out;
+    a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
+    a.ncols = w.ncols;
+    a.mptr = w.mptr;
+    a.skip_tail = w.skip_tail;
+    a.tiles_q = tq_of(w.prob->n);
+    a.chunk_x = cx;
+    a.tiles_x = (w.prob->n + cx - 1) / cx;
+    a.tile_begin = tiles;
+    tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
+    d.push_back(a);
+  }
+  return tiles;
+}
+
 StagedApplyL stage_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items) {
   StagedApplyL st;
   if (items.empty()) return st;
   const bool f32 = items[0].prob->precision == PR_MIXED;
   st.f32 = f32;
-  long long tiles = 0;
-  // x planes per workgroup: kChunkX, or 4 when that leaves a launch (one
-  // column of L d in the sweep) under 2048 workgroups
-  long long wide = 0;
-  for (auto& w : items) wide += (long long)tiles_q(w.prob->n) * tiles_x(w.prob->n) * w.ncols;
-  const int cx = wide < 2048 ? 4 : kChunkX;
+  // The LDS-window kernel (kWinQ points per workgroup) for launches of many
+  // columns whose grids all allow it; otherwise kTileQ points per workgroup
+  // with x chunks of kChunkX planes, or of 4 when that leaves a launch (one
+  // column of L d in the sweep) under 2048 workgroups.
+  auto win_tq = [](int n) { return (n * n + kWinQ - 1) / kWinQ; };
+  bool win = true;
+  long long wide = 0, wide_win = 0;
+  for (auto& w : items) {
+    const int n = w.prob->n;
+    win = win && n >= kWinMinN && n <= kWinMaxN;
+    wide += (long long)tiles_q(n) * tiles_x(n) * w.ncols;
+    wide_win += (long long)win_tq(n) * tiles_x(n) * w.ncols;
+  }
+  // PR_APPLYL_WIN=0 never takes the window kernel, =1 whenever the grids
+  // allow it (tests compare the two)
+  const char* ew = getenv("PR_APPLYL_WIN");
+  if (ew && *ew == '0') win = false;
+  else if (!(ew && *ew == '1')) win = win && wide_win >= 2048;
+  const int cx = (win || wide >= 2048) ? kChunkX : 4;
+  auto tq = [&](int n) { return win ? win_tq(n) : tiles_q(n); };
   if (f32) {
     std::vector<ApplyLDesc<float>> d;
-    for (auto& w : items) {
-      ApplyLDesc<float> a{};
-      a.g = geom_piece(geom_of(c, *w.prob), w.piece);
-      a.in = (const float*)w.in;
-      a.out = (float*)w.out;
-      a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
-      a.ncols = w.ncols;
-      a.mptr = w.mptr;
-      a.skip_tail = w.skip_tail;
-      a.tiles_q = tiles_q(w.prob->n);
-      a.chunk_x = cx;
-      a.tiles_x = (w.prob->n + cx - 1) / cx;
-      a.tile_begin = tiles;
-      tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
-      d.push_back(a);
-    }
+    st.tiles = applyL_descs<float>(c, items, cx, tq, d);
     st.dd = stage_push(c, d);
     st.nd = (int)d.size();
   } else {
     std::vector<ApplyLDesc<double>> d;
-    for (auto& w : items) {
-      ApplyLDesc<double> a{};
-      a.g = geom_piece(geom_of(c, *w.prob), w.piece);
-      a.in = (const double*)w.in;
-      a.out = (double*)w.out;
-      a.ld = w.ld > 0 ? w.ld : ngrid(*w.prob);
-      a.ncols = w.ncols;
-      a.mptr = w.mptr;
-      a.skip_tail = w.skip_tail;
-      a.tiles_q = tiles_q(w.prob->n);
-      a.chunk_x = cx;
-      a.tiles_x = (w.prob->n + cx - 1) / cx;
-      a.tile_begin = tiles;
-      tiles += (long long)a.tiles_q * a.tiles_x * w.ncols;
-      d.push_back(a);
-    }
+    st.tiles = applyL_descs<double>(c, items, cx, tq, d);
     st.dd = stage_push(c, d);
     st.nd = (int)d.size();
   }
-  st.tiles = tiles;
+  st.win = win;
   return st;
 }
 
 void launch_applyL_staged(const StagedApplyL& st, hipStream_t s) {
   if (st.nd <= 0) return;
-  if (st.f32) launch_applyL_f32((const ApplyLDesc<float>*)st.dd, st.nd, st.tiles, s);
-  else launch_applyL_f64((const ApplyLDesc<double>*)st.dd, st.nd, st.tiles, s);
+  if (st.f32) launch_applyL_f32((const ApplyLDesc<float>*)st.dd, st.nd, st.tiles, st.win, s);
+  else launch_applyL_f64((const ApplyLDesc<double>*)st.dd, st.nd, st.tiles, st.win, s);
 }
 
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s) {

@@ -184,6 +184,7 @@ struct ApplyLWork {
 void enqueue_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items, hipStream_t s);
 struct StagedApplyL {
   bool f32 = false;
+  bool win = false;           // the LDS-window kernel
   const void* dd = nullptr;   // ApplyLDesc<float> or <double>
   int nd = 0;
   long long tiles = 0;

@@ -278,8 +278,15 @@ struct UploadBlob {
 };
 void launch_upload(const UploadBlob& b, unsigned int* dst, int nw, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, long long n, hipStream_t s);
-void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, hipStream_t s);
-void launch_applyL_f32(const ApplyLDesc<float>* d, int nitems, long long total_tiles, hipStream_t s);
+// win: the LDS-window kernel (every item's n in [kWinMinN, kWinMaxN]; tiles of kWinQ
+// points of the (y, z) plane); else tiles of kTileQ points.
+void launch_applyL_f64(const ApplyLDesc<double>* d, int nitems, long long total_tiles, bool win,
+                       hipStream_t s);
+void launch_applyL_f32(const ApplyLDesc<float>* d, int nitems, long long total_tiles, bool win,
+                       hipStream_t s);
+constexpr int kWinQ = 1024;     // points of the (y, z) plane per workgroup of the window kernel
+constexpr int kWinMaxN = 256;   // largest n of the window kernel (window kWinQ + 2 n values)
+constexpr int kWinMinN = 64;    // smallest (n^2 > kWinQ + n, so a window wraps at most once)
 
 // Gram / A^T B: shape = number of A tiles (na) and B tiles (nb, 0 = symmetric
 // Gram of the A tiles). f32 selects the FP32 MFMA (products of float data).

@@ -24,6 +24,16 @@
 
 namespace pr {
 
+// (L u) at one point from its centre c0, x neighbours cm / cp, y neighbours
+// ym / yp and z neighbours zm / zp, velocity (vx, vy, vz).
+template <typename T>
+__device__ __forceinline__ T l_point(T cm, T c0, T cp, T ym, T yp, T zm, T zp, T vx, T vy, T vz,
+                                     T clap) {
+  const T lap = ((cp + cm) + (yp + ym) + (zp + zm)) - (T)6 * c0;
+  const T adv = vx * (cp - cm) + vy * (yp - ym) + vz * (zp - zm);
+  return clap * lap - adv;
+}
+
 // Evaluate (L in) along x for one (j, k) column over planes [x0, x1),
 // calling emit(x, p, Lv) for each plane. Periodic wrap on every axis. The
 // loads of four planes are issued before any of them is used, so a thread
@@ -46,11 +56,8 @@ __device__ __forceinline__ void march_L(const Geom& g, const PR_GLOBAL T* __rest
   T cm = in[(long long)xm0 * plane + q];
   T c0 = in[(long long)x0 * plane + q];
   auto point = [&](int x, T cp, T ym, T yp, T zm, T zp, T ty, T tz) {
-    const T vy = ty + vy_z;
-    const T vz = tz + vz_y;
-    const T lap = ((cp + cm) + (yp + ym) + (zp + zm)) - (T)6 * c0;
-    const T adv = vx * (cp - cm) + vy * (yp - ym) + vz * (zp - zm);
-    emit(x, (long long)x * plane + q, clap * lap - adv);
+    emit(x, (long long)x * plane + q,
+         l_point<T>(cm, c0, cp, ym, yp, zm, zp, vx, ty + vy_z, tz + vz_y, clap));
     cm = c0;
     c0 = cp;
   };
@@ -454,14 +461,131 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   march_L<T>(d.g, in, j, k, x0, x1, [&](int, long long p, T Lv) { out[p] = Lv; });
 }
 
-void launch_applyL_f64(const ApplyLDesc<double>* d, int nd, long long tt, hipStream_t s) {
+// out = L(in) through an LDS window of each plane (kWinMinN <= n <= kWinMaxN: a
+// window index then wraps at most once either way): a
+// workgroup owns kWinQ consecutive points q = j n + k of the (y, z) plane and
+// marches along x. Plane x's window holds the points q0 - n .. q0 + kWinQ + n
+// (periodic in q), which covers every y and z neighbour of the owned points,
+// so a point costs (kWinQ + 2 n) / kWinQ loads instead of five. Two window
+// buffers hold planes x and x + 1; plane x + 2 is loaded into registers while
+// plane x is computed. Same arithmetic per point as k_apply_L.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_L_win(const ApplyLDesc<T>* __restrict__ descs,
+                                                     int nd) {
+  constexpr int U = kWinQ / 256;                      // points per thread
+  constexpr int NW = (kWinQ + 2 * kWinMaxN + 255) / 256;   // window loads per thread (at most)
+  __shared__ T win[2][kWinQ + 2 * kWinMaxN];
+  const long long t = blockIdx.x;
+  const int f = find_desc(descs, nd, t);
+  const ApplyLDesc<T> d = descs[f];
+  const long long lt = t - d.tile_begin;
+  const int per_col = d.tiles_q * d.tiles_x;
+  const int col = (int)(lt / per_col);
+  const int r = (int)(lt - (long long)col * per_col);
+  const int tq = r % d.tiles_q, tx = r / d.tiles_q;
+  const int n = d.g.n;
+  const int plane = n * n;
+  const int tid = threadIdx.x;
+  const int q0 = tq * kWinQ;
+  const int x0 = tx * d.chunk_x, x1 = min(n, x0 + d.chunk_x);
+  const PR_GLOBAL T* in = gptr(d.in) + (long long)col * d.ld;
+  PR_GLOBAL T* out = gptr(d.out) + (long long)col * d.ld;
+  const bool valid = (d.mptr == nullptr) || (col < *d.mptr);
+  if (!valid) {
+    if (d.skip_tail) return;
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + tid + 256 * u;
+      if (q < plane)
+        for (int x = x0; x < x1; ++x) out[(long long)x * plane + q] = (T)0;
+    }
+    return;
+  }
+  const PR_GLOBAL T* tab = gptr(tab_of<T>(d.g));
+  const T clap = (T)d.g.c_lap;
+  const int W = kWinQ + 2 * n;
+  // this thread's points: window index of the centre and of the z neighbours
+  bool ok[U];
+  int q[U], wc[U], wzm[U], wzp[U];
+  T vx[U], vyz[U], vzy[U], cm[U];
+  const int xm0 = (x0 == 0) ? n - 1 : x0 - 1;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int l = tid + 256 * u;
+    q[u] = q0 + l;
+    ok[u] = q[u] < plane;
+    const int qq = ok[u] ? q[u] : 0;
+    const int j = qq / n, k = qq - j * n;
+    wc[u] = n + l;
+    wzm[u] = (k > 0) ? wc[u] - 1 : wc[u] + n - 1;
+    wzp[u] = (k < n - 1) ? wc[u] + 1 : wc[u] - (n - 1);
+    vx[u] = tab[0 * n + j] + tab[1 * n + k];
+    vyz[u] = tab[3 * n + k];
+    vzy[u] = tab[5 * n + j];
+    cm[u] = ok[u] ? in[(long long)xm0 * plane + qq] : (T)0;
+  }
+  T reg[NW];
+  auto load = [&](int x) {
+    const PR_GLOBAL T* p = in + (long long)x * plane;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int w = tid + 256 * i;
+      int qq = q0 - n + w;
+      qq = qq < 0 ? qq + plane : (qq >= plane ? qq - plane : qq);
+      reg[i] = w < W ? p[qq] : (T)0;
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int w = tid + 256 * i;
+      if (w < W) win[b][w] = reg[i];
+    }
+  };
+  load(x0);
+  store(0);
+  load(x0 == n - 1 ? 0 : x0 + 1);
+  store(1);
+  __syncthreads();
+  for (int x = x0; x < x1; ++x) {
+    const int cur = (x - x0) & 1, nxt = cur ^ 1;
+    const bool more = x + 1 < x1;   // plane x + 1 is computed, so plane x + 2 is needed
+    if (more) load(x + 2 >= n ? x + 2 - n : x + 2);
+    const T ty = tab[2 * n + x], tz = tab[4 * n + x];
+    const T* wcur = win[cur];
+    const T* wnxt = win[nxt];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const T c0 = wcur[wc[u]];
+      const T Lv = l_point<T>(cm[u], c0, wnxt[wc[u]], wcur[wc[u] - n], wcur[wc[u] + n],
+                              wcur[wzm[u]], wcur[wzp[u]], vx[u], ty + vyz[u], tz + vzy[u], clap);
+      out[(long long)x * plane + q[u]] = Lv;
+      cm[u] = c0;
+    }
+    if (more) {
+      __syncthreads();   // every read of plane x's window is done
+      store(cur);
+      __syncthreads();
+    }
+  }
+}
+
+void launch_applyL_f64(const ApplyLDesc<double>* d, int nd, long long tt, bool win,
+                       hipStream_t s) {
   if (tt <= 0) return;
-  hipLaunchKernelGGL(k_apply_L<double>, dim3((unsigned)tt), dim3(kTileQ), 0, s, d, nd);
+  if (win)
+    hipLaunchKernelGGL(k_apply_L_win<double>, dim3((unsigned)tt), dim3(256), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL(k_apply_L<double>, dim3((unsigned)tt), dim3(kTileQ), 0, s, d, nd);
   PR_HIP(hipGetLastError());
 }
-void launch_applyL_f32(const ApplyLDesc<float>* d, int nd, long long tt, hipStream_t s) {
+void launch_applyL_f32(const ApplyLDesc<float>* d, int nd, long long tt, bool win,
+                       hipStream_t s) {
   if (tt <= 0) return;
-  hipLaunchKernelGGL(k_apply_L<float>, dim3((unsigned)tt), dim3(kTileQ), 0, s, d, nd);
+  if (win)
+    hipLaunchKernelGGL(k_apply_L_win<float>, dim3((unsigned)tt), dim3(256), 0, s, d, nd);
+  else
+    hipLaunchKernelGGL(k_apply_L<float>, dim3((unsigned)tt), dim3(kTileQ), 0, s, d, nd);
   PR_HIP(hipGetLastError());
 }
 

@@ -153,3 +153,34 @@ def test_coarse_rank_zero_basis_augments_by_u(ctx, prec):
     for i in range(2):
         assert abs(beta[i, cap] - betas[i][0]) <= tol * abs(betas[i][0])
         assert np.all(beta[i, :cap] == 0.0)
+
+
+@pytest.mark.parametrize("n,flow,fp,prec", [
+    (64, W.FLOW_ABC, (1.0, 1.0, 1.0), W.PREC_F64),
+    (72, W.FLOW_ABC, (0.8, 1.1, 0.6), W.PREC_F64),
+    (72, W.FLOW_KOLMOGOROV, (0.8, 3.0, 0.0), W.PREC_F64),
+    (72, W.FLOW_ABC, (1.0, 1.0, 1.0), W.PREC_MIXED)],
+    ids=["abc64", "abc72", "kol72", "abc72_mixed"])
+def test_coarse_L_window_kernel(ctx, monkeypatch, n, flow, fp, prec):
+    """L applied through the LDS window of each plane (the kernel the solver
+    uses for the bases of many subintervals at 64^3 and up): bitwise the
+    per-column kernel's L Psi, hence the same coarse outputs, on grids whose
+    plane is not a whole number of windows (72^2 = 5.06 x 1024), and the
+    oracle's values in FP64 (1e-12)."""
+    say(f"coarse L window kernel n={n} flow={flow} prec={prec}")
+    cap = 8
+    op, h3, R, m, U1, U2 = _setup(n=n, cap=cap, flow=flow, fp=fp)
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("PR_APPLYL_WIN", mode)
+        res[mode] = _gpu(ctx, n, R, m, cap, [U1, U2], 0.2, 3, u_aug=U1, prec=prec,
+                         flow=flow, fp=fp)
+    monkeypatch.delenv("PR_APPLYL_WIN")
+    for a, b in zip(res["0"][0], res["1"][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res["0"][1], res["1"][1])
+    if prec == W.PREC_F64:
+        Psi, aug = coarse.augment(R, U1, h3)
+        lifted, _, _ = coarse.coarse_propagate(op, Psi, [U1, U2], 0.2, 3, h3)
+        for o, l in zip(res["1"][0], lifted):
+            assert rel_l2(o, l) <= 1e-12
