@@ -872,25 +872,34 @@ StagedApplyL stage_applyL_batch(pr_ctx* c, const std::vector<ApplyLWork>& items)
   if (items.empty()) return st;
   const bool f32 = items[0].prob->precision == PR_MIXED;
   st.f32 = f32;
-  // The LDS-window kernel (kWinQ points per workgroup) for launches of many
-  // columns whose grids all allow it; otherwise kTileQ points per workgroup
-  // with x chunks of kChunkX planes, or of 4 when that leaves a launch (one
-  // column of L d in the sweep) under 2048 workgroups.
+  // The LDS-window kernel (kWinQ points per workgroup) for launches whose
+  // grids all allow it and that give 2048 workgroups at an x chunk of 4 to 32
+  // planes (the bases of a wave); otherwise kTileQ points per workgroup with
+  // x chunks of kChunkX planes, or of 4 when that leaves a launch (one column
+  // of L d in the sweep) under 2048 workgroups.
   auto win_tq = [](int n) { return (n * n + kWinQ - 1) / kWinQ; };
   bool win = true;
-  long long wide = 0, wide_win = 0;
+  long long wide = 0;
   for (auto& w : items) {
     const int n = w.prob->n;
     win = win && n >= kWinMinN && n <= kWinMaxN;
     wide += (long long)tiles_q(n) * tiles_x(n) * w.ncols;
-    wide_win += (long long)win_tq(n) * tiles_x(n) * w.ncols;
   }
   // PR_APPLYL_WIN=0 never takes the window kernel, =1 whenever the grids
   // allow it (tests compare the two)
   const char* ew = getenv("PR_APPLYL_WIN");
+  // the window kernel's x chunk: the longest of 32, 16, 8, 4 planes that
+  // gives 2048 workgroups (each chunk also loads two planes ahead)
+  auto win_wgs = [&](int x) {
+    long long t = 0;
+    for (auto& w : items) t += (long long)win_tq(w.prob->n) * ((w.prob->n + x - 1) / x) * w.ncols;
+    return t;
+  };
+  int cxw = kChunkX;
+  while (cxw > 4 && win_wgs(cxw) < 2048) cxw /= 2;
   if (ew && *ew == '0') win = false;
-  else if (!(ew && *ew == '1')) win = win && wide_win >= 2048;
-  const int cx = (win || wide >= 2048) ? kChunkX : 4;
+  else if (!(ew && *ew == '1')) win = win && win_wgs(cxw) >= 2048;
+  const int cx = win ? cxw : (wide >= 2048 ? kChunkX : 4);
   auto tq = [&](int n) { return win ? win_tq(n) : tiles_q(n); };
   if (f32) {
     std::vector<ApplyLDesc<float>> d;
