@@ -239,7 +239,10 @@ pr_status pr_gram_noalloc(pr_ctx* ctx, const pr_grid_problem* prob, const void* 
  *   u_out[i]     NULL, or device N_g doubles: Psi beta_i(dT_total)
  *   beta_out     NULL, or device n_in x (cap + 1) doubles (row i = beta_i in
  *                the basis [R(:, 0..m), d]; unused entries zero)
- *   n_c_out      NULL, or device int: steps after the guard */
+ *   n_c_out      NULL, or device int: steps after the guard
+ * L R is applied per column, or for launches of many columns on grids with
+ * 64 <= n <= 256 through an LDS window of each plane (the same values bit for
+ * bit); PR_APPLYL_WIN=0 or 1 forces the per-column or the window kernel. */
 typedef struct {
   const pr_grid_problem* prob;
   const void* R;
