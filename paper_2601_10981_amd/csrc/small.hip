@@ -501,27 +501,36 @@ __device__ __forceinline__ QSlots q_slots(int q) {
 
 // Cholesky in place of sh.M (q x q, lower); sets bad on a non-positive (or
 // NaN) pivot, which is then clamped only so the factorisation completes: the
-// callers turn bad into NaN coefficients.
+// callers turn bad into NaN coefficients. Right-looking elimination on the
+// unscaled pivot column (one barrier per column: after step j - 1, column j
+// and its pivot are final), then one pass scales the columns by the square
+// roots of their pivots.
 __device__ void red_cholesky(RedShared& sh, int q, const QSlots& sl) {
   const int tid = threadIdx.x;
   for (int j = 0; j < q; ++j) {
-    if (tid == 0) {
-      const double dj = sh.M[j][j];
-      if (!(dj > 0.0)) sh.bad = 1;
-      sh.M[j][j] = sqrt(fmax(dj, 1e-300));
-    }
-    __syncthreads();
-    const double ljj = sh.M[j][j];
-    for (int i = j + 1 + tid; i < q; i += 256) sh.M[i][j] /= ljj;
-    __syncthreads();
+    const double inv = 1.0 / fmax(sh.M[j][j], 1e-300);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = sl.i[r], k = sl.j[r];
       if (i < 0) break;
-      if (k > j && k <= i) sh.M[i][k] -= sh.M[i][j] * sh.M[k][j];
+      if (k > j && k <= i) sh.M[i][k] -= (sh.M[i][j] * inv) * sh.M[k][j];
     }
     __syncthreads();
   }
+  if (tid < q) {
+    const double dj = sh.M[tid][tid];
+    if (!(dj > 0.0)) sh.bad = 1;
+    sh.tmp[0][tid] = sqrt(fmax(dj, 1e-300));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = sl.i[r], k = sl.j[r];
+    if (i < 0) break;
+    if (k < i) sh.M[i][k] /= sh.tmp[0][k];
+    else if (k == i) sh.M[i][i] = sh.tmp[0][i];
+  }
+  __syncthreads();
 }
 
 // Solve (L L^T) x = b in place for a vector held by one thread.
@@ -684,6 +693,78 @@ __device__ void red_advance(RedShared& sh, int q, int nv) {
   }
 }
 
+// sh.B <- B^{n_c} by binary powering of the one-step propagator (sh.K and
+// sh.T serve as work matrices; K is not needed after the propagator is
+// formed). One barrier per product.
+__device__ void red_power(RedShared& sh, int q, const QSlots& sl) {
+  if (sh.n_c == 1) return;
+  double (*A[3])[kMaxQ + 2] = {sh.B, sh.K, sh.T};
+  int ib = 0, ir = 1, it = 2;   // base, result, spare (the same in every thread)
+  bool have = false;
+  auto mul = [&](int x, int y, int z) {   // A[z] = A[x] A[y]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = sl.i[r], j = sl.j[r];
+      if (i < 0) break;
+      double acc = 0.0;
+      for (int k = 0; k < q; ++k) acc += A[x][i][k] * A[y][k][j];
+      A[z][i][j] = acc;
+    }
+    __syncthreads();
+  };
+  for (int e = sh.n_c; e > 0; e >>= 1) {
+    if (e & 1) {
+      if (!have) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (sl.i[r] < 0) break;
+          A[ir][sl.i[r]][sl.j[r]] = A[ib][sl.i[r]][sl.j[r]];
+        }
+        __syncthreads();
+        have = true;
+      } else {
+        mul(ir, ib, it);
+        const int t = ir;
+        ir = it;
+        it = t;
+      }
+    }
+    if (e > 1) {
+      mul(ib, ib, it);
+      const int t = ib;
+      ib = it;
+      it = t;
+    }
+  }
+  if (ir != 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (sl.i[r] < 0) break;
+      sh.B[sl.i[r]][sl.j[r]] = A[ir][sl.i[r]][sl.j[r]];
+    }
+    __syncthreads();
+  }
+}
+
+// beta[v] <- P beta[v] for v < nv, P = sh.B (after red_power: B^{n_c}).
+__device__ void red_apply(RedShared& sh, int q, int nv) {
+  const int tid = threadIdx.x;
+  const bool act = tid < nv * q;
+  const int v = act ? tid / q : 0, i = act ? tid % q : 0;
+  if (act) {
+    double acc = 0.0;
+    for (int k = 0; k < q; ++k) acc += sh.B[i][k] * sh.beta[v][k];
+    sh.tmp[v][i] = acc;
+  }
+  __syncthreads();
+  if (act) sh.beta[v][i] = sh.tmp[v][i];
+  __syncthreads();
+}
+
+// Products of a binary power cost about three matrix-vector steps each: the
+// power pays from this many steps on.
+constexpr int kPowerMinSteps = 64;
+
 __device__ void reduced_run(const ReducedDesc& d) {
   __shared__ RedShared sh;
   const int tid = threadIdx.x;
@@ -730,7 +811,12 @@ __device__ void reduced_run(const ReducedDesc& d) {
     red_advance_forced(sh, q, d.n_in, np, d.forced, d.w, d.t0, d.dT);
   } else {
     red_propagator(sh, q, d.dT, d.n_c, sl);
-    red_advance(sh, q, d.n_in);
+    if (sh.n_c >= kPowerMinSteps) {
+      red_power(sh, q, sl);
+      red_apply(sh, q, d.n_in);
+    } else {
+      red_advance(sh, q, d.n_in);
+    }
   }
   const int w = d.cap + 1;
   for (int e = tid; e < d.n_in * w; e += 256) d.beta[e] = 0.0;
@@ -800,13 +886,19 @@ __global__ __launch_bounds__(256) void k_reduced0(const Reduced0Desc* __restrict
   __syncthreads();
   if (sh.bad && tid < q) sh.beta[0][tid] = NAN;   // as in reduced_run
   __syncthreads();
-  if (d.forced) red_forced_setup(sh, q, np, d.dT, d.n_c, sl);
-  else red_propagator(sh, q, d.dT, d.n_c, sl);
+  // the same propagator for every subinterval: its n_c-th power once, then
+  // one product per subinterval
+  if (d.forced) {
+    red_forced_setup(sh, q, np, d.dT, d.n_c, sl);
+  } else {
+    red_propagator(sh, q, d.dT, d.n_c, sl);
+    red_power(sh, q, sl);
+  }
   for (int n = 0; n < d.count; ++n) {
     // subinterval n runs over [(n + n_warm) dT, (n + n_warm + 1) dT]
     if (d.forced)
       red_advance_forced(sh, q, 1, np, d.forced, d.w, (double)(n + d.n_warm) * d.dT, d.dT);
-    else red_advance(sh, q, 1);
+    else red_apply(sh, q, 1);
     for (int e = tid; e < d.ld_out; e += 256)
       d.betas[(long long)n * d.ld_out + e] = (e < q) ? sh.beta[0][e] : 0.0;
   }
