@@ -184,3 +184,29 @@ def test_coarse_L_window_kernel(ctx, monkeypatch, n, flow, fp, prec):
         lifted, _, _ = coarse.coarse_propagate(op, Psi, [U1, U2], 0.2, 3, h3)
         for o, l in zip(res["1"][0], lifted):
             assert rel_l2(o, l) <= 1e-12
+
+
+@pytest.mark.parametrize("n,prec", [(256, W.PREC_F64), (250, W.PREC_MIXED)],
+                         ids=["n256_f64", "n250_mixed"])
+def test_coarse_L_window_kernel_largest_grids(ctx, monkeypatch, n, prec):
+    """The window kernel at the top of its range (n = 256: a 1536-value window
+    per plane) and on a plane of 62,500 points (61.04 windows): the coarse
+    outputs are bitwise those of the per-column kernel. A random
+    M-orthonormal basis stands in for a POD basis (no oracle at this size)."""
+    say(f"coarse L window kernel n={n} prec={prec}")
+    rng = np.random.default_rng(11)
+    cap, m = 8, 6
+    h3 = (2 * math.pi / n) ** 3
+    Q, _ = np.linalg.qr(rng.standard_normal((n ** 3, m)))
+    R = Q / math.sqrt(h3)
+    U1 = rng.standard_normal(n ** 3)
+    U2 = U1 + 0.1 * rng.standard_normal(n ** 3)
+    res = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("PR_APPLYL_WIN", mode)
+        res[mode] = _gpu(ctx, n, R, m, cap, [U1, U2], 0.05, 2, u_aug=U1, prec=prec)
+    monkeypatch.delenv("PR_APPLYL_WIN")
+    for a, b in zip(res["0"][0], res["1"][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res["0"][1], res["1"][1])
+    assert np.all(np.isfinite(res["1"][1]))
