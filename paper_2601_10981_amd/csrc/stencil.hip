@@ -461,10 +461,10 @@ __global__ __launch_bounds__(kTileQ) void k_apply_L(const ApplyLDesc<T>* __restr
   march_L<T>(d.g, in, j, k, x0, x1, [&](int, long long p, T Lv) { out[p] = Lv; });
 }
 
-// out = L(in) through an LDS window of each plane (kWinMinN <= n <= kWinMaxN: a
-// window index then wraps at most once either way): a
-// workgroup owns kWinQ consecutive points q = j n + k of the (y, z) plane and
-// marches along x. Plane x's window holds the points q0 - n .. q0 + kWinQ + n
+// out = L(in) through an LDS window of each plane, for kWinMinN <= n <=
+// kWinMaxN (a window index then wraps at most once either way). A workgroup
+// owns kWinQ consecutive points q = j n + k of the (y, z) plane and marches
+// along x. Plane x's window holds the points q0 - n .. q0 + kWinQ + n
 // (periodic in q), which covers every y and z neighbour of the owned points,
 // so a point costs (kWinQ + 2 n) / kWinQ loads instead of five. Two window
 // buffers hold planes x and x + 1; plane x + 2 is loaded into registers while
