@@ -613,23 +613,34 @@ __global__ __launch_bounds__(256) void k_correct(const CorrectDesc* __restrict__
   const PR_GLOBAL double* ref = d.ref ? gptr(d.ref) : nullptr;
   PR_GLOBAL double* out = gptr(d.out);
   double s_jump = 0, s_u = 0, s_err = 0, s_ref = 0;
+  auto col = [&](int c, long long row) {
+    return sf[c] ? (double)gptr((const float*)sp[c])[row] : gptr((const double*)sp[c])[row];
+  };
   for (long long row = r0 + threadIdx.x; row < r1; row += 256) {
+    // every load of the row is issued before the sums that use it (out,
+    // prev and ref are distinct buffers); the sums keep their order
     double v = 0.0;
     if (d.fine) v = d.fine_f32 ? (double)gptr((const float*)d.fine)[row] : gptr((const double*)d.fine)[row];
+    const double pv = prev ? prev[row] : 0.0;
+    const double r = ref ? ref[row] : 0.0;
     double g = 0.0;
-    for (int c = 0; c < np; ++c) {
-      const double x = sf[c] ? (double)gptr((const float*)sp[c])[row] : gptr((const double*)sp[c])[row];
-      g += sc[c] * x;
+    int c = 0;
+    for (; c + 4 <= np; c += 4) {
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = col(c + u, row);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g += sc[c + u] * x[u];
     }
+    for (; c < np; ++c) g += sc[c] * col(c, row);
     v += g;
     out[row] = v;
     s_u += v * v;
     if (prev) {
-      const double dj = v - prev[row];
+      const double dj = v - pv;
       s_jump += dj * dj;
     }
     if (ref) {
-      const double r = ref[row];
       const double de = v - r;
       s_err += de * de;
       s_ref += r * r;
