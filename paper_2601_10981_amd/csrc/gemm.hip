@@ -499,10 +499,10 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
   double a0[MAXOUT], a1[MAXOUT];
 #pragma unroll
   for (int j = 0; j < MAXOUT; ++j) a0[j] = a1[j] = 0.0;
-  // wide outputs (few waves resident): eight input columns per round for up
-  // to 16 outputs, four above that (registers), their loads issued together
-  // before the multiply-adds, so a wave waits for memory once per round;
-  // narrow ones already hide the latency with occupancy
+  // wide outputs (few waves resident): four input columns per round, their
+  // loads issued together before the multiply-adds, so a wave waits for
+  // memory once per round; narrow ones already hide the latency with
+  // occupancy
   auto ld = [&](int c, long long r) -> double {
     if (sf[c]) return (double)gptr((const float*)sp[c])[r];
     return gptr((const double*)sp[c])[r];
