@@ -507,17 +507,16 @@ __global__ __launch_bounds__(256) void k_tsmm(const TsmmDesc* __restrict__ descs
     if (sf[c]) return (double)gptr((const float*)sp[c])[r];
     return gptr((const double*)sp[c])[r];
   };
-  constexpr int RW = (MAXOUT == 16) ? 8 : 4;
   int c = 0;
-  for (; MAXOUT > 8 && c + RW <= nv; c += RW) {
-    double x0[RW], x1[RW];
+  for (; MAXOUT > 8 && c + 4 <= nv; c += 4) {
+    double x0[4], x1[4];
 #pragma unroll
-    for (int u = 0; u < RW; ++u) {
+    for (int u = 0; u < 4; ++u) {
       x0[u] = ld(c + u, r0);
       x1[u] = ld(c + u, q1);
     }
 #pragma unroll
-    for (int u = 0; u < RW; ++u) {
+    for (int u = 0; u < 4; ++u) {
       const double* Cr = sC + (c + u) * MAXOUT;
 #pragma unroll
       for (int j = 0; j < MAXOUT; ++j)
