@@ -733,10 +733,18 @@ __global__ __launch_bounds__(256) void k_cgs(const CgsArgs a) {
   for (long long r = r_begin + threadIdx.x; r < r_end; r += 256) {
     double x[MAXC];
     if (m > 0) {
+      if constexpr (!SUB) {
+        // the dots pass loads no column j >= m (m is uniform: whole-wave
+        // branches); 63 -> 56 us per call at 128^3. The update passes lost
+        // 1-2 us that way and load all MAXC columns in one block.
 #pragma unroll
-      for (int j = 0; j < MAXC; ++j) {
-        const double v = (double)p[j][r];
-        x[j] = j < m ? v : 0.0;
+        for (int j = 0; j < MAXC; ++j) x[j] = j < m ? (double)p[j][r] : 0.0;
+      } else {
+#pragma unroll
+        for (int j = 0; j < MAXC; ++j) {
+          const double v = (double)p[j][r];
+          x[j] = j < m ? v : 0.0;
+        }
       }
     } else {
 #pragma unroll
